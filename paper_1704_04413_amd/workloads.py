@@ -1,0 +1,61 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the smoke check.
+
+This module holds no arithmetic of the lattice Boltzmann method: it only
+builds the macroscopic initial fields of the paper's two test cases (the
+doubly periodic shear layer of Sec. III.B, Eqs. MB_InitialState_ux/uy, and the
+Sod tube of Sec. III.C) and seeded uniform noise.  Lattice constants (c_s^2)
+are always supplied by the caller, so each side of a comparison uses its own.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def cell_centres(n: int) -> np.ndarray:
+    """Dimensionless cell-centre coordinates (i + 1/2)/n, i = 0..n-1."""
+    return (np.arange(n, dtype=np.float64) + 0.5) / n
+
+
+def shear_layer_fields(nx: int, ny: int, u0: float, k: float = 80.0, delta: float = 0.05,
+                       phase: float = 0.0):
+    """Doubly periodic shear layer: rho = 1, two tanh shear layers at y = 1/4
+    and 3/4 of width 1/k, transverse perturbation of relative amplitude delta.
+    `phase` shifts the perturbation, sin(2 pi (x + 1/4 + phase)).
+    Returns rho, ux, uy as float64 arrays indexed [y, x]."""
+    x = cell_centres(nx)[None, :]
+    y = cell_centres(ny)[:, None]
+    ux = np.where(y <= 0.5, u0 * np.tanh(k * (y - 0.25)), u0 * np.tanh(k * (0.75 - y)))
+    ux = np.broadcast_to(ux, (ny, nx)).copy()
+    uy = np.broadcast_to(u0 * delta * np.sin(2.0 * np.pi * (x + 0.25 + phase)), (ny, nx)).copy()
+    rho = np.ones((ny, nx))
+    return rho, ux, uy
+
+
+def shear_layer_params(cs2: float, n: int, re: float, mach: float = 0.1):
+    """Characteristic speed u0 = Mach * c_s and the discrete relaxation time
+    giving Re = u0 n / nu with nu = c_s^2 (tau - 1/2) (isothermal)."""
+    u0 = mach * np.sqrt(cs2)
+    nu = u0 * n / re
+    return float(u0), float(0.5 + nu / cs2)
+
+
+def sod_fields(nx: int, ny: int, rho_l=8.0, p_l=10.0, rho_r=1.0, p_r=1.0, x_split=None,
+               theta_ref="left"):
+    """Sod tube along x, periodic in y.  Cells i < x_split hold the left state,
+    the rest the right state; u = 0.  Temperatures are normalised by the left
+    state's (theta_ref="left": theta_L = 1) or the right state's
+    (theta_ref="right": theta_R = 1).  Returns rho, ux, uy, theta [y, x]."""
+    x_split = nx // 2 if x_split is None else x_split
+    t_l, t_r = p_l / rho_l, p_r / rho_r
+    t0 = t_l if theta_ref == "left" else t_r
+    left = (np.arange(nx) < x_split)[None, :]
+    rho = np.broadcast_to(np.where(left, rho_l, rho_r), (ny, nx)).astype(np.float64).copy()
+    theta = np.broadcast_to(np.where(left, t_l / t0, t_r / t0), (ny, nx)).astype(np.float64).copy()
+    zeros = np.zeros((ny, nx))
+    return rho, zeros.copy(), zeros.copy(), theta
+
+
+def uniform_noise(seed: int, q: int, ny: int, nx: int) -> np.ndarray:
+    """U(-1, 1) samples of shape (q, ny, nx) from NumPy's PCG64 with `seed`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-1.0, 1.0, size=(q, ny, nx))
