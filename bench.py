@@ -1,0 +1,225 @@
+"""Throughput benchmark of the recursive-regularized LBM step on one MI355X.
+
+Default workload: D2V37, isothermal recursive regularization at the lattice's
+full order (N = 4), doubly periodic shear layer on 1024 x 1024 nodes, FP64
+populations (the plain form), Re = 1e5, Mach 0.1.  A step is one fused
+stream-and-collide launch over the whole grid.
+
+Prints ONE JSON line: MLUPS over the timed steps, the HBM roofline of the
+step kernel (algorithmic bytes 2 Q sizeof(f) per node over the kernel's
+average duration, from HIP events recorded around every launch on the
+library's stream), the CPU oracle timed on a bounded sample of the same
+workload, and a per-lattice / per-precision sweep.
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+METRIC = "MLUPS and % of HBM roofline per lattice; closure/low-precision vs plain at stated error"
+STORAGE_FLAGS = {"fp64": 0, "fp32": 0x2, "bf16": 0x4}
+STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1704_04413_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(os.path.basename(p).encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def read_traffic(name: str):
+    """HBM bytes per launch measured by rocprofv3 counters (profiles/<name>),
+    valid only if the kernel sources have not changed since."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0):
+    q, reach, n_eq, cs2 = b.lbm_lattice_info(lattice)
+    u0, tau = wl.shear_layer_params(cs2, n, re)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    flags = STORAGE_FLAGS[storage] | (b.LBM_THERMAL if thermal else 0)
+    theta = np.ones_like(rho) if thermal else None
+    noise = wl.uniform_noise(seed, q, n, n)
+    sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, theta=theta, noise=noise, noise_amp=1e-8,
+                       flags=flags)
+    return sim, dict(q=q, tau=tau, u0=u0, rho=rho, ux=ux, uy=uy, noise=noise)
+
+
+def time_steps(torch, sim, steps, warmup):
+    """Whole-region wall time plus per-launch HIP-event durations."""
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    stream = sim.stream
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, e in ev:
+        s.record(stream)
+        sim.step(1)
+        e.record(stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kms = np.array([s.elapsed_time(e) for s, e in ev])
+    return t1 - t0, kms
+
+
+def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
+
+
+def cpu_baseline(wl, lattice_name, n, steps, seed=0):
+    """The oracle as it stands, timed on the host cores on `steps` steps of
+    the full grid (MLUPS)."""
+    import oracle as orc
+
+    lat = orc.lattice(lattice_name)
+    u0, tau = wl.shear_layer_params(lat.cs2, n, 1e5)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    noise = wl.uniform_noise(seed, lat.Q, n, n)
+    f = orc.init_populations(lat, rho, ux, uy, None, noise, 1e-8)
+    t0 = time.perf_counter()
+    orc.step(lat, f, tau, steps)
+    dt = time.perf_counter() - t0
+    return dict(value=round(n * n * steps / dt / 1e6, 4), unit="MLUPS", cores=orc.threads(), kind="oracle",
+                sample=f"{steps} steps of the {lattice_name} {n}x{n} FP64 RR shear layer ({dt:.1f} s)")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--lattice", default="D2V37")
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--storage", default="fp64", choices=list(STORAGE_FLAGS))
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=25)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--copy-only", action="store_true", help="only run 1 GiB device copies (counter calibration)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1704_04413_amd import binding as b
+    from paper_1704_04413_amd import workloads as wl
+
+    if not os.path.exists(b.LIB_PATH):
+        from paper_1704_04413_amd import build as hipbuild
+
+        hipbuild.build()
+    b.lib()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    if args.copy_only:
+        print(json.dumps({"copy_GBs": round(copy_bandwidth(torch), 1)}), flush=True)
+        return
+
+    sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage)
+    wall, kms = time_steps(torch, sim, args.steps, args.warmup)
+    mom = sim.moments()
+    sim.close()
+    nodes = args.n * args.n
+    mlups = nodes * args.steps / wall / 1e6
+    bytes_per_launch = 2 * meta["q"] * STORAGE_BYTES[args.storage] * nodes
+    kavg = float(kms.mean()) * 1e-3
+    achieved = bytes_per_launch / kavg / 1e9
+    traffic = read_traffic(f"{args.lattice.lower()}_{args.storage}_{args.n}_traffic.txt")
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.storage == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"{args.lattice} isothermal recursive-regularized shear layer {args.n}x{args.n}, "
+                        f"{args.storage} populations, order {b.lbm_lattice_info(args.lattice)[2]}, "
+                        "Re 1e5, Mach 0.1",
+            "lattice": args.lattice, "nx": args.n, "ny": args.n, "storage": args.storage, "scheme": "pull",
+            "tau": meta["tau"],
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "bytes_per_launch": bytes_per_launch,
+            "kernel_ms_avg": round(float(kms.mean()), 5),
+            "kernel_ms_min": round(float(kms.min()), 5),
+        },
+        "nonfinite_nodes": int(mom["sums"][8]),
+    }
+    if not args.no_sweep:
+        sweep = []
+        cases = [("D2Q9", "fp64", False), ("D2V17", "fp64", False), ("D2V37", "fp64", False),
+                 ("D2V37", "fp64", True), ("D2Q9", "fp32", False), ("D2V17", "fp32", False),
+                 ("D2V37", "fp32", False), ("D2V37", "bf16", False)]
+        for lat, st, th in cases:
+            s2, m2 = make_sim(b, wl, lat, args.n, st, thermal=th)
+            w2, k2 = time_steps(torch, s2, 50, 5)
+            s2.close()
+            bpl = 2 * m2["q"] * STORAGE_BYTES[st] * nodes
+            gbs = bpl / (float(k2.mean()) * 1e-3) / 1e9
+            sweep.append({"lattice": lat, "storage": st, "thermal": th, "MLUPS": round(nodes * 50 / w2 / 1e6, 1),
+                          "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        out["per_lattice"] = sweep
+        out["copy_GBs"] = round(copy_bandwidth(torch), 1)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.lattice, args.n, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

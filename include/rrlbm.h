@@ -1,0 +1,145 @@
+/*
+ * rrlbm.h -- C-ABI of the MI355X (gfx950) recursive-regularized lattice
+ * Boltzmann library (librrlbm.so).
+ *
+ * Method: Coreixas, Wissocq, Puigt, Boussuge, Sagaut, "Recursive
+ * regularization step for high-order lattice Boltzmann methods".  One time
+ * step is the explicit stream-and-collide scheme of Sec. III.A, with the
+ * regularized collision of Eq. (RegularizedCollision) / Eq. (GenRegCollision)
+ * at a single relaxation time: the non-equilibrium populations are rebuilt
+ * from Hermite coefficients, a1^(2) by projection (Eq. a12Proj) and the higher
+ * orders by the recursive formula (Malaspinas' isothermal form,
+ * Eq. MalaspinasRecursiveRelation; the thermal extension,
+ * Eq. RecursiveRelation_ThermalCase, with a1^(3) rebuilt through
+ * Eq. TempGradLBM as App. C describes).  Lattices are those of Table I.
+ *
+ * Conventions shared by every entry point
+ *   - Grids are periodic, nx by ny nodes, lattice units (dx = dt = 1).
+ *   - Velocities are integers in canonical order: ascending c_y, then
+ *     ascending c_x (lbm_lattice_velocities lists them).
+ *   - Field arrays (rho, ux, uy, theta, vorticity) are FP64, row-major [y][x],
+ *     nx*ny elements.  Population arrays exchanged with the caller are FP64,
+ *     [i][y][x], Q*nx*ny elements.
+ *   - "device" pointers are HIP device allocations (e.g. torch tensors on
+ *     cuda:0); "host" pointers are ordinary memory.  The library never frees
+ *     caller memory.
+ *   - Every launch goes on the HIP stream given to lbm_init (a hipStream_t
+ *     passed as void*; NULL is the default stream).  Calls are asynchronous
+ *     unless stated otherwise.
+ *   - Return value: 0 on success or a negative LBM_E* code; the calling
+ *     thread's message is then available from lbm_last_error().
+ *
+ * Storage (population precision)
+ *   LBM_STORE_FP64 (default) keeps the plain populations f_i in double and does
+ *   all arithmetic in double.  LBM_STORE_FP32 / LBM_STORE_BF16 keep the
+ *   weight-shifted populations g_i = f_i - w_i in float / bfloat16 and do all
+ *   arithmetic in float.
+ */
+#ifndef RRLBM_H
+#define RRLBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Lattices (Table I). */
+#define LBM_D2Q9 0  /* E^9_{2,5},  c_s^2 = 1/3, basis 1,x,y,xx,xy,yy,xxy,xyy,xxyy */
+#define LBM_D2V17 1 /* E^17_{2,7}, all Hermite tensors of rank <= 3           */
+#define LBM_D2V37 2 /* E^37_{2,9}, all Hermite tensors of rank <= 4           */
+
+/* Flags for lbm_init (bitwise OR). */
+#define LBM_THERMAL 0x1u        /* thermal/compressible form; D2V37 only          */
+#define LBM_STORE_FP32 0x2u     /* store f - w in float, float arithmetic          */
+#define LBM_STORE_BF16 0x4u     /* store f - w in bfloat16, float arithmetic       */
+#define LBM_COLL_PR 0x10u       /* projection-based regularization (Sec. II.E)     */
+#define LBM_COLL_BGK 0x20u      /* BGK collision (Sec. III.A)                      */
+#define LBM_EQ_INIT_ORDER2 0x100u /* initial f^(0) truncated at Hermite order 2    */
+#define LBM_A13_PROJECTED 0x200u  /* thermal RR: keep the projected a1^(3)         */
+
+/* Error codes. */
+#define LBM_OK 0
+#define LBM_EINVAL (-1)   /* invalid argument (lattice, size, order, flags, NULL) */
+#define LBM_ETAU (-2)     /* tau <= 1/2 or not finite                             */
+#define LBM_EDEVICE (-3)  /* a HIP call failed                                    */
+#define LBM_ENOMEM (-4)   /* the context could not allocate its scratch           */
+
+/* Lattice constants (Table I).  Any output pointer may be NULL.
+ * q: number of velocities; reach: largest |c_x| or |c_y|; n_eq: highest
+ * Hermite rank of the basis (the order the equilibrium is expanded to);
+ * cs2: c_s^2 in lattice units.  Returns LBM_EINVAL for an unknown lattice. */
+int lbm_lattice_info(int lattice, int* q, int* reach, int* n_eq, double* cs2);
+
+/* Velocities and weights in canonical order; host arrays of q entries each
+ * (any may be NULL). */
+int lbm_lattice_velocities(int lattice, int* cx, int* cy, double* w);
+
+/* Elements (of the storage type) one population buffer must hold for an
+ * nx by ny grid: q planes of nx*ny values plus padding.  Negative on error. */
+int64_t lbm_buffer_elems(int lattice, int nx, int ny);
+
+/* Creates a context and writes the initial state.
+ *   lattice    LBM_D2Q9, LBM_D2V17 or LBM_D2V37.
+ *   nx, ny     grid size; each must be >= the lattice reach and nx*ny*q must
+ *              stay below 2^31.
+ *   tau        discrete relaxation time (tau-bar of Sec. III.A, > 1/2):
+ *              nu = c_s^2 theta (tau - 1/2).
+ *   reg_order  regularization order N, 2 <= N <= n_eq; the non-equilibrium
+ *              part keeps Hermite ranks 2..N of the basis while the
+ *              equilibrium always uses the full basis.  Ignored for BGK.
+ *   flags      LBM_* flags above.  LBM_THERMAL requires LBM_D2V37.
+ *   f_a, f_b   two device buffers of lbm_buffer_elems() elements of the
+ *              storage type (double, float or bfloat16), caller-owned; they
+ *              must stay valid until lbm_destroy.
+ *   rho,ux,uy  device FP64 fields of the initial state.
+ *   theta      device FP64 field of theta = T/T_0 (thermal), or NULL (= 1).
+ *   noise      device FP64 array [i][y][x] or NULL; the initial populations are
+ *              f^(0)(rho, u, theta) + noise_amp * w_i * noise.
+ *   stream     hipStream_t for every launch of this context.
+ * The buffer then holds the post-collision populations of step 0.  *out is
+ * set only on success. */
+int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_order, uint32_t flags,
+             void* f_a, void* f_b, const double* rho, const double* ux, const double* uy,
+             const double* theta, const double* noise, double noise_amp, void* stream);
+
+/* Advances nsteps (>= 0) time steps: each is one fused launch that gathers
+ * f_i(x - c_i) (periodic pull), regularizes, relaxes and stores.  Returns
+ * LBM_EDEVICE if a launch fails.  A blow-up is not an error (lbm_moments
+ * counts non-finite nodes). */
+int lbm_step(lbm_ctx* ctx, int nsteps);
+
+/* Number of steps taken since lbm_init. */
+int64_t lbm_step_count(const lbm_ctx* ctx);
+
+/* Macroscopic fields of the current step (rho, u and theta are collision
+ * invariants, so they are the fields before and after the collision).
+ * rho, ux, uy, theta, vort: device FP64 fields or NULL.  vort is
+ * d(uy)/dx - d(ux)/dy from the periodic fourth-order centred difference.
+ * sums: host array of LBM_NSUMS doubles or NULL; when given the call
+ * synchronizes the stream and fills, over all nodes,
+ *   [0] sum rho          [1] sum rho ux        [2] sum rho uy
+ *   [3] sum rho E = sum_i f_i |c_i|^2 / 2      [4] sum |u|^2   [5] sum |u|^4
+ *   [6] sum omega^2      [7] sum omega^4       [8] non-finite nodes
+ *   [9] sum theta */
+#define LBM_NSUMS 10
+int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* theta, double* vort,
+                double* sums);
+
+/* Copies the current post-collision populations into the device FP64 array
+ * f_out[i][y][x] (shifted storage is converted back to f = g + w). */
+int lbm_populations(lbm_ctx* ctx, double* f_out);
+
+/* Frees the context's own scratch (not the caller's buffers).  NULL is a no-op. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Message describing the last error on the calling thread ("" if none). */
+const char* lbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RRLBM_H */

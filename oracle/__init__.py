@@ -61,8 +61,14 @@ def lib():
         L.orc_collide.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double, i64, dp, dp]
         L.orc_step.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] + [ctypes.c_int] * 3 + [dp, dp]
         L.orc_moments.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, dp, dp]
+        L.orc_threads.argtypes = []
         _lib = L
     return _lib
+
+
+def threads() -> int:
+    """Host threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def _p(a):

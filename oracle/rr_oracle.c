@@ -30,6 +30,9 @@
  * the fixed point, RR2 == PR2, PR4 == BGK on D2Q9, shear-wave decay).
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -412,6 +415,16 @@ static void node_collide(const orc_lattice_t* L, const orc_cfg_t* c, const doubl
 }
 
 /* ---- Exported API ------------------------------------------------------ */
+
+/* Threads the parallel loops use. */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
 
 /* Fills Q, n_eq, c_s^2, velocities (canonical order) and weights.
  * cx, cy, w may be NULL.  Returns 0, or -1 for an unknown lattice. */

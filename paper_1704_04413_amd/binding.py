@@ -1,0 +1,205 @@
+"""ctypes binding of librrlbm.so (the C-ABI of include/rrlbm.h).
+
+Functions keep the C names and only marshal arguments: device arrays are
+torch tensors on the GPU (passed by data pointer), streams are torch streams.
+Every step of the method runs in the HIP library; there is no fallback, and
+loading fails loudly when the library has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librrlbm.so")
+
+LBM_D2Q9, LBM_D2V17, LBM_D2V37 = 0, 1, 2
+LATTICES = {"D2Q9": LBM_D2Q9, "D2V17": LBM_D2V17, "D2V37": LBM_D2V37}
+LBM_THERMAL = 0x1
+LBM_STORE_FP32 = 0x2
+LBM_STORE_BF16 = 0x4
+LBM_COLL_PR = 0x10
+LBM_COLL_BGK = 0x20
+LBM_EQ_INIT_ORDER2 = 0x100
+LBM_A13_PROJECTED = 0x200
+LBM_NSUMS = 10
+
+LBM_OK, LBM_EINVAL, LBM_ETAU, LBM_EDEVICE, LBM_ENOMEM = 0, -1, -2, -3, -4
+
+# every symbol declared in include/rrlbm.h
+EXPORTS = ["lbm_lattice_info", "lbm_lattice_velocities", "lbm_buffer_elems", "lbm_init", "lbm_step",
+           "lbm_step_count", "lbm_moments", "lbm_populations", "lbm_destroy", "lbm_last_error"]
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"librrlbm error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load librrlbm.so (raises if it is missing: there is no other path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
+        L.lbm_lattice_info.argtypes = [ctypes.c_int, ip, ip, ip, dp]
+        L.lbm_lattice_velocities.argtypes = [ctypes.c_int, ip, ip, dp]
+        L.lbm_buffer_elems.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.lbm_buffer_elems.restype = ctypes.c_int64
+        L.lbm_init.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                               ctypes.c_int, ctypes.c_uint32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp]
+        L.lbm_step.argtypes = [vp, ctypes.c_int]
+        L.lbm_step_count.argtypes = [vp]
+        L.lbm_step_count.restype = ctypes.c_int64
+        L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, dp]
+        L.lbm_populations.argtypes = [vp, vp]
+        L.lbm_destroy.argtypes = [vp]
+        L.lbm_destroy.restype = None
+        L.lbm_last_error.argtypes = []
+        L.lbm_last_error.restype = ctypes.c_char_p
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != LBM_OK:
+        raise LbmError(rc, lbm_last_error())
+    return rc
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def lattice_id(lattice) -> int:
+    return LATTICES[lattice] if isinstance(lattice, str) else int(lattice)
+
+
+def lbm_last_error() -> str:
+    return lib().lbm_last_error().decode()
+
+
+def lbm_lattice_info(lattice):
+    q, r, n, cs2 = ctypes.c_int(), ctypes.c_int(), ctypes.c_int(), ctypes.c_double()
+    _check(lib().lbm_lattice_info(lattice_id(lattice), ctypes.byref(q), ctypes.byref(r), ctypes.byref(n),
+                                  ctypes.byref(cs2)))
+    return q.value, r.value, n.value, cs2.value
+
+
+def lbm_lattice_velocities(lattice):
+    q = lbm_lattice_info(lattice)[0]
+    cx, cy, w = (ctypes.c_int * q)(), (ctypes.c_int * q)(), (ctypes.c_double * q)()
+    _check(lib().lbm_lattice_velocities(lattice_id(lattice), cx, cy, w))
+    return np.array(list(cx)), np.array(list(cy)), np.array(list(w))
+
+
+def lbm_buffer_elems(lattice, nx, ny) -> int:
+    n = lib().lbm_buffer_elems(lattice_id(lattice), nx, ny)
+    if n < 0:
+        raise LbmError(int(n), lbm_last_error())
+    return int(n)
+
+
+def lbm_init(lattice, nx, ny, tau, reg_order, flags, f_a, f_b, rho, ux, uy, theta=None, noise=None,
+             noise_amp=0.0, stream=None):
+    """Returns the context handle (an integer)."""
+    ctx = ctypes.c_void_p()
+    s = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+    _check(lib().lbm_init(ctypes.byref(ctx), lattice_id(lattice), nx, ny, tau, reg_order, flags, _ptr(f_a),
+                          _ptr(f_b), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), _ptr(noise), noise_amp, s))
+    return ctx.value
+
+
+def lbm_step(ctx, nsteps: int):
+    _check(lib().lbm_step(ctypes.c_void_p(ctx), nsteps))
+
+
+def lbm_step_count(ctx) -> int:
+    return int(lib().lbm_step_count(ctypes.c_void_p(ctx)))
+
+
+def lbm_moments(ctx, rho=None, ux=None, uy=None, theta=None, vort=None, sums=False):
+    out = (ctypes.c_double * LBM_NSUMS)() if sums else None
+    _check(lib().lbm_moments(ctypes.c_void_p(ctx), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), _ptr(vort),
+                             out))
+    return np.array(list(out)) if sums else None
+
+
+def lbm_populations(ctx, f_out):
+    _check(lib().lbm_populations(ctypes.c_void_p(ctx), _ptr(f_out)))
+
+
+def lbm_destroy(ctx):
+    lib().lbm_destroy(ctypes.c_void_p(ctx))
+
+
+# ---------------------------------------------------------------- helper
+
+class Simulation:
+    """Owns the two population buffers (torch tensors) and one context."""
+
+    def __init__(self, lattice, nx, ny, tau, rho, ux, uy, theta=None, noise=None, noise_amp=0.0,
+                 reg_order=None, flags=0, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.lattice = lattice_id(lattice)
+        self.q, self.reach, self.n_eq, self.cs2 = lbm_lattice_info(self.lattice)
+        self.nx, self.ny, self.tau, self.flags = nx, ny, tau, flags
+        self.reg_order = self.n_eq if reg_order is None else reg_order
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        dtype = (torch.float32 if flags & LBM_STORE_FP32 else
+                 torch.bfloat16 if flags & LBM_STORE_BF16 else torch.float64)
+        n = lbm_buffer_elems(self.lattice, nx, ny)
+        self.bufs = [torch.empty(n, dtype=dtype, device=self.device) for _ in range(2)]
+
+        def dev(a):
+            if a is None:
+                return None
+            t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)) if isinstance(a, np.ndarray) else a
+            return t.to(self.device, torch.float64).contiguous()
+
+        fields = [dev(a) for a in (rho, ux, uy, theta, noise)]
+        self.ctx = lbm_init(self.lattice, nx, ny, tau, self.reg_order, flags, self.bufs[0], self.bufs[1],
+                            *fields, noise_amp=noise_amp, stream=self.stream)
+        self._keep = fields  # inputs must outlive the asynchronous init
+
+    @property
+    def steps(self) -> int:
+        return lbm_step_count(self.ctx)
+
+    def step(self, n: int = 1):
+        lbm_step(self.ctx, n)
+
+    def populations(self):
+        t = self.torch.empty((self.q, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+        lbm_populations(self.ctx, t)
+        return t
+
+    def moments(self, sums=True, vorticity=True):
+        torch = self.torch
+        mk = lambda: torch.empty((self.ny, self.nx), dtype=torch.float64, device=self.device)
+        rho, ux, uy, th = mk(), mk(), mk(), mk()
+        vort = mk() if vorticity else None
+        s = lbm_moments(self.ctx, rho, ux, uy, th, vort, sums=sums)
+        return dict(rho=rho, ux=ux, uy=uy, theta=th, vort=vort, sums=s)
+
+    def close(self):
+        if self.ctx:
+            self.stream.synchronize()
+            lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

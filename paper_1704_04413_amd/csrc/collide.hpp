@@ -1,0 +1,328 @@
+// Per-node regularized collision for the HIP kernels.
+//
+// The node state is held in registers as v[Q], either the plain populations f
+// (FP64 storage) or the weight-shifted g = f - w (FP32/BF16 storage).  The
+// collision follows the paper's regularized operator (Eq. RegularizedCollision
+// with a single tau):
+//   1. moments rho, j and the Hermite moments h_k = sum_i H^k_i v_i
+//      (sum_i w_i H^k_i = 0 for every basis tensor k != 0, so h_k is the same
+//      for f and g);
+//   2. theta from the energy moment (thermal) and the equilibrium
+//      coefficients a0^(kx,ky) = rho m_kx(ux) m_ky(uy), m_n the raw moments of
+//      N(u, (theta-1) c_s^2) -- the closed form of Eq. HermiteCoeffEq, equal to
+//      the recursion of App. B;
+//   3. a1^(2) = h^(2) - a0^(2) (Eq. a12Proj; exact because the quadrature
+//      reproduces sum_i H^(2)_i f^(0)_i = a0^(2) on all three lattices);
+//   4. a1^(3), a1^(4): isothermal closed forms of Eq. MalaspinasRecursiveRelation
+//      (App. C at theta = 1), or the thermal path of App. C (project a1^(3),
+//      average the two estimates of mu c_s^2 grad theta, Eq. TempGradLBM,
+//      rebuild with Eq. a1Rec, then the rank-4 forms of the thermal recursion);
+//      PR projects every rank instead (h_k - a0_k);
+//   5. f_coll_i = w_i sum_k H^k_i [a0^k + (1 - 1/tau) a1^k] / (k_x! k_y! c_s^2|k|)
+//      over the lattice basis (Eq. GenRegCollision), a1 kept for ranks 2..N.
+// Moments and reconstruction are organised by velocity rows (one row per c_y)
+// and by +/- pairs, using H^k_i = He_kx(c_x) He_ky(c_y) (App. C, 2D).
+#pragma once
+
+#include "lattices.hpp"
+
+namespace rr {
+
+enum Coll { COLL_RR = 0, COLL_PR = 1, COLL_BGK = 2 };
+
+// Row moments: r[cy + R][p] = sum over velocities of row c_y of v_i c_x^p, and
+// then s[p][q] = sum_i v_i c_x^p c_y^q for p + q <= 4.
+template <class L, class T>
+__device__ __forceinline__ void raw_moments(const T (&v)[L::Q], T (&s)[5][5])
+{
+    constexpr int R = L::R;
+    T r[2 * R + 1][5];
+    static_for<2 * R + 1>([&](auto YI) {
+        constexpr int cy = int(YI) - R;
+        constexpr int i0 = vel_index<L>(0, cy);
+        static_for<5>([&](auto P) { r[YI][P] = T(0); });
+        if constexpr (i0 >= 0) r[YI][0] = v[i0];
+        static_for<R>([&](auto XI) {
+            constexpr int cx = int(XI) + 1;
+            constexpr int ip = vel_index<L>(cx, cy), im = vel_index<L>(-cx, cy);
+            if constexpr (ip >= 0) {
+                static_assert(im >= 0, "lattice rows are symmetric");
+                const T e = v[ip] + v[im];
+                const T o = v[ip] - v[im];
+                r[YI][0] += e;
+                r[YI][1] += T(cx) * o;
+                r[YI][2] += T(cx * cx) * e;
+                r[YI][3] += T(cx * cx * cx) * o;
+                r[YI][4] += T(cx * cx * cx * cx) * e;
+            }
+        });
+    });
+    static_for<5>([&](auto P) {
+        T re[R + 1], ro[R + 1];
+        static_for<R>([&](auto YI) {
+            constexpr int cy = int(YI) + 1;
+            re[cy] = r[R + cy][P] + r[R - cy][P];
+            ro[cy] = r[R + cy][P] - r[R - cy][P];
+        });
+        static_for<5 - int(P)>([&](auto Qd) {
+            T acc = (int(Qd) == 0) ? r[R][P] : T(0);
+            static_for<R>([&](auto YI) {
+                constexpr int cy = int(YI) + 1;
+                constexpr double m = ipow(double(cy), int(Qd));
+                acc += T(m) * ((int(Qd) % 2 == 0) ? re[cy] : ro[cy]);
+            });
+            s[P][Qd] = acc;
+        });
+    });
+}
+
+// out_i = w_i sum_{kx,ky in basis} He_kx(c_x) He_ky(c_y) C[kx][ky].
+template <class L, class T>
+__device__ __forceinline__ void reconstruct(const T (&C)[5][5], T (&out)[L::Q])
+{
+    constexpr int R = L::R;
+    constexpr double cs2 = L::cs2;
+    static_for<R + 1>([&](auto YI) {
+        constexpr int cy = int(YI);
+        // T_kx(+-cy) = te_kx +- to_kx with te (to) the even (odd) ky part
+        T te[5], to[5];
+        static_for<5>([&](auto KX) {
+            T e = T(0), o = T(0);
+            static_for<5>([&](auto KY) {
+                if constexpr (L::basis(int(KX), int(KY))) {
+                    constexpr double h = he(int(KY), double(cy), cs2);
+                    if constexpr (int(KY) % 2 == 0)
+                        e += T(h) * C[KX][KY];
+                    else
+                        o += T(h) * C[KX][KY];
+                }
+            });
+            te[KX] = e;
+            to[KX] = o;
+        });
+        static_for<(cy == 0) ? 1 : 2>([&](auto SY) {
+            constexpr int yy = (int(SY) == 0) ? cy : -cy;
+            T t[5];
+            static_for<5>([&](auto KX) { t[KX] = (int(SY) == 0) ? te[KX] + to[KX] : te[KX] - to[KX]; });
+            static_for<R + 1>([&](auto XI) {
+                constexpr int cx = int(XI);
+                constexpr int ip = vel_index<L>(cx, yy), im = vel_index<L>(-cx, yy);
+                if constexpr (ip >= 0) {
+                    T e = T(0), o = T(0);
+                    static_for<5>([&](auto KX) {
+                        constexpr double h = he(int(KX), double(cx), cs2);
+                        if constexpr (h != 0.0) {
+                            if constexpr (int(KX) % 2 == 0)
+                                e += T(h) * t[KX];
+                            else
+                                o += T(h) * t[KX];
+                        }
+                    });
+                    constexpr double w = L::v.w[ip];
+                    out[ip] = T(w) * (e + o);
+                    if constexpr (cx != 0) out[im] = T(w) * (e - o);
+                }
+            });
+        });
+    });
+}
+
+// Coefficient C[kx][ky] = value / (kx! ky! c_s^2(kx+ky)) restricted to the basis.
+template <class L, class T>
+__device__ __forceinline__ void zero_coeffs(T (&C)[5][5])
+{
+    static_for<5>([&](auto a) { static_for<5>([&](auto b) { C[a][b] = T(0); }); });
+}
+
+// Equilibrium coefficients a0[kx][ky] = rho m_kx(ux) m_ky(uy).
+template <class T>
+__device__ __forceinline__ void eq_factors(T u, T sig, T (&m)[5])
+{
+    const T u2 = u * u;
+    m[0] = T(1);
+    m[1] = u;
+    m[2] = u2 + sig;
+    m[3] = u * (u2 + T(3) * sig);
+    m[4] = u2 * u2 + T(6) * sig * u2 + T(3) * sig * sig;
+}
+
+// The regularized (or BGK) collision of one node, in place.
+//   keep = 1 - 1/tau, inv_tau = 1/tau, order = N.
+template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
+__device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, int order)
+{
+    constexpr T cs2 = T(L::cs2);
+    T s[5][5];
+    raw_moments<L, T>(v, s);
+
+    const T s00 = s[0][0];
+    const T rho = SHIFTED ? T(1) + s00 : s00;
+    const T drho = SHIFTED ? s00 : s00 - T(1);
+    const T inv_rho = T(1) / rho;
+    const T ux = s[1][0] * inv_rho;
+    const T uy = s[0][1] * inv_rho;
+
+    // Hermite moments h_k = sum_i H^k_i v_i (k != 0)
+    const T h20 = s[2][0] - cs2 * s00;
+    const T h02 = s[0][2] - cs2 * s00;
+    const T h11 = s[1][1];
+
+    T sig = T(0);
+    if constexpr (THERMAL) {
+        // 2 rho c_s^2 (theta - 1) = sum f |c|^2 - 2 c_s^2 rho - rho |u|^2
+        const T thm1 = (h20 + h02 - rho * (ux * ux + uy * uy)) * inv_rho * (T(0.5) / cs2);
+        sig = cs2 * thm1;
+    }
+    T mx[5], my[5];
+    eq_factors<T>(ux, sig, mx);
+    eq_factors<T>(uy, sig, my);
+
+    T C[5][5];
+    zero_coeffs<L, T>(C);
+    // equilibrium part (a1^(0) = a1^(1) = 0)
+    static_for<5>([&](auto KX) {
+        static_for<5>([&](auto KY) {
+            if constexpr (L::basis(int(KX), int(KY)) && int(KX) + int(KY) >= 1)
+                C[KX][KY] = rho * mx[KX] * my[KY];
+        });
+    });
+    C[0][0] = SHIFTED ? drho : rho;
+
+    if constexpr (COLL == COLL_BGK) {
+        static_for<5>([&](auto KX) {
+            static_for<5>([&](auto KY) {
+                if constexpr (L::basis(int(KX), int(KY)) && int(KX) + int(KY) >= 1) {
+                    constexpr double nrm = inv_norm<L>(int(KX), int(KY));
+                    C[KX][KY] *= T(nrm);
+                }
+            });
+        });
+        T eq[L::Q];
+        reconstruct<L, T>(C, eq);
+        static_for<L::Q>([&](auto I) { v[I] = keep * v[I] + inv_tau * eq[I]; });
+        return;
+    }
+
+    // non-equilibrium coefficients
+    T a1[5][5];
+    static_for<5>([&](auto a) { static_for<5>([&](auto b) { a1[a][b] = T(0); }); });
+    a1[2][0] = h20 - C[2][0];
+    a1[1][1] = h11 - C[1][1];
+    a1[0][2] = h02 - C[0][2];
+
+    if constexpr (COLL == COLL_PR) {
+        if constexpr (L::NEQ >= 3) {
+            const T h30 = s[3][0] - T(3) * cs2 * s[1][0];
+            const T h21 = s[2][1] - cs2 * s[0][1];
+            const T h12 = s[1][2] - cs2 * s[1][0];
+            const T h03 = s[0][3] - T(3) * cs2 * s[0][1];
+            if constexpr (L::basis(3, 0)) {
+                a1[3][0] = h30 - C[3][0];
+                a1[0][3] = h03 - C[0][3];
+            }
+            if constexpr (L::basis(2, 1)) {
+                a1[2][1] = h21 - C[2][1];
+                a1[1][2] = h12 - C[1][2];
+            }
+        }
+        if constexpr (L::NEQ >= 4) {
+            constexpr T cs4 = cs2 * cs2;
+            const T h40 = s[4][0] - T(6) * cs2 * s[2][0] + T(3) * cs4 * s00;
+            const T h31 = s[3][1] - T(3) * cs2 * s[1][1];
+            const T h22 = s[2][2] - cs2 * (s[2][0] + s[0][2]) + cs4 * s00;
+            const T h13 = s[1][3] - T(3) * cs2 * s[1][1];
+            const T h04 = s[0][4] - T(6) * cs2 * s[0][2] + T(3) * cs4 * s00;
+            if constexpr (L::basis(4, 0)) {
+                a1[4][0] = h40 - C[4][0];
+                a1[0][4] = h04 - C[0][4];
+            }
+            if constexpr (L::basis(3, 1)) {
+                a1[3][1] = h31 - C[3][1];
+                a1[1][3] = h13 - C[1][3];
+            }
+            if constexpr (L::basis(2, 2)) a1[2][2] = h22 - C[2][2];
+        }
+    } else if constexpr (!THERMAL) {
+        // isothermal recursion, closed forms
+        const T xx = a1[2][0], xy = a1[1][1], yy = a1[0][2];
+        const T uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+        a1[3][0] = T(3) * ux * xx;
+        a1[2][1] = T(2) * ux * xy + uy * xx;
+        a1[1][2] = T(2) * uy * xy + ux * yy;
+        a1[0][3] = T(3) * uy * yy;
+        a1[4][0] = T(6) * uxx * xx;
+        a1[3][1] = T(3) * (uxx * xy + uxy * xx);
+        a1[2][2] = uyy * xx + uxx * yy + T(4) * uxy * xy;
+        a1[1][3] = T(3) * (uyy * xy + uxy * yy);
+        a1[0][4] = T(6) * uyy * yy;
+    } else {
+        // thermal path of App. C
+        const T xx = a1[2][0], xy = a1[1][1], yy = a1[0][2];
+        const T p30 = s[3][0] - T(3) * cs2 * s[1][0] - C[3][0];
+        const T p21 = s[2][1] - cs2 * s[0][1] - C[2][1];
+        const T p12 = s[1][2] - cs2 * s[1][0] - C[1][2];
+        const T p03 = s[0][3] - T(3) * cs2 * s[0][1] - C[0][3];
+        if constexpr (A13P) {
+            a1[3][0] = p30;
+            a1[2][1] = p21;
+            a1[1][2] = p12;
+            a1[0][3] = p03;
+        } else {
+            const T gx = T(0.5) * ((ux * xx - p30 * T(1.0 / 3.0)) + (T(2) * uy * xy + ux * yy - p12));
+            const T gy = T(0.5) * ((uy * yy - p03 * T(1.0 / 3.0)) + (T(2) * ux * xy + uy * xx - p21));
+            a1[3][0] = T(3) * (ux * xx - gx);
+            a1[2][1] = T(2) * ux * xy + uy * xx - gy;
+            a1[1][2] = T(2) * uy * xy + ux * yy - gx;
+            a1[0][3] = T(3) * (uy * yy - gy);
+        }
+        const T bx = sig - ux * ux, by = sig - uy * uy, uxy = ux * uy;
+        a1[4][0] = T(4) * ux * a1[3][0] + T(6) * bx * xx;
+        a1[3][1] = T(3) * ux * a1[2][1] + uy * a1[3][0] + T(3) * bx * xy - T(3) * uxy * xx;
+        a1[2][2] = T(2) * (ux * a1[1][2] + uy * a1[2][1]) + bx * yy + by * xx - T(4) * uxy * xy;
+        a1[1][3] = T(3) * uy * a1[1][2] + ux * a1[0][3] + T(3) * by * xy - T(3) * uxy * yy;
+        a1[0][4] = T(4) * uy * a1[0][3] + T(6) * by * yy;
+    }
+
+    // relax: C = (a0 + k_n a1) / norm over the basis, k_n = keep for 2 <= n <= N
+    const T k3 = order >= 3 ? keep : T(0);
+    const T k4 = order >= 4 ? keep : T(0);
+    static_for<5>([&](auto KX) {
+        static_for<5>([&](auto KY) {
+            constexpr int n = int(KX) + int(KY);
+            if constexpr (L::basis(int(KX), int(KY)) && n >= 1) {
+                T c = C[KX][KY];
+                if constexpr (n == 2) c += keep * a1[KX][KY];
+                if constexpr (n == 3) c += k3 * a1[KX][KY];
+                if constexpr (n == 4) c += k4 * a1[KX][KY];
+                constexpr double nrm = inv_norm<L>(int(KX), int(KY));
+                C[KX][KY] = c * T(nrm);
+            }
+        });
+    });
+    reconstruct<L, T>(C, v);
+}
+
+// Equilibrium populations truncated at Hermite rank `order` (initial state).
+template <class L, class T, bool SHIFTED>
+__device__ __forceinline__ void equilibrium_node(T rho, T ux, T uy, T theta, int order, T (&out)[L::Q])
+{
+    const T sig = T(L::cs2) * (theta - T(1));
+    T mx[5], my[5];
+    eq_factors<T>(ux, sig, mx);
+    eq_factors<T>(uy, sig, my);
+    T C[5][5];
+    zero_coeffs<L, T>(C);
+    static_for<5>([&](auto KX) {
+        static_for<5>([&](auto KY) {
+            constexpr int n = int(KX) + int(KY);
+            if constexpr (L::basis(int(KX), int(KY)) && n >= 1) {
+                constexpr double nrm = inv_norm<L>(int(KX), int(KY));
+                C[KX][KY] = (n <= order) ? rho * mx[KX] * my[KY] * T(nrm) : T(0);
+            }
+        });
+    });
+    C[0][0] = SHIFTED ? rho - T(1) : rho;
+    reconstruct<L, T>(C, out);
+}
+
+} // namespace rr

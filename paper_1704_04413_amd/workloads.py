@@ -40,17 +40,18 @@ def shear_layer_params(cs2: float, n: int, re: float, mach: float = 0.1):
 
 
 def sod_fields(nx: int, ny: int, rho_l=8.0, p_l=10.0, rho_r=1.0, p_r=1.0, x_split=None,
-               theta_ref="left"):
+               theta_left=0.5):
     """Sod tube along x, periodic in y.  Cells i < x_split hold the left state,
-    the rest the right state; u = 0.  Temperatures are normalised by the left
-    state's (theta_ref="left": theta_L = 1) or the right state's
-    (theta_ref="right": theta_R = 1).  Returns rho, ux, uy, theta [y, x]."""
+    the rest the right state; u = 0.  Temperatures are scaled so the left
+    state has theta = theta_left (0.5 makes the left adiabatic sound speed
+    sqrt(gamma theta) c_s equal c_s for gamma = 2); the right state keeps the
+    physical ratio T_R / T_L = (p_r / rho_r) / (p_l / rho_l).
+    Returns rho, ux, uy, theta [y, x]."""
     x_split = nx // 2 if x_split is None else x_split
-    t_l, t_r = p_l / rho_l, p_r / rho_r
-    t0 = t_l if theta_ref == "left" else t_r
+    theta_r = theta_left * (p_r / rho_r) / (p_l / rho_l)
     left = (np.arange(nx) < x_split)[None, :]
     rho = np.broadcast_to(np.where(left, rho_l, rho_r), (ny, nx)).astype(np.float64).copy()
-    theta = np.broadcast_to(np.where(left, t_l / t0, t_r / t0), (ny, nx)).astype(np.float64).copy()
+    theta = np.broadcast_to(np.where(left, theta_left, theta_r), (ny, nx)).astype(np.float64).copy()
     zeros = np.zeros((ny, nx))
     return rho, zeros.copy(), zeros.copy(), theta
 

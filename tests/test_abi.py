@@ -1,0 +1,100 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every symbol the
+header declares, reports the same lattice constants as the oracle (two
+independent tables of Table I), and rejects invalid arguments before touching
+the GPU."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1704_04413_amd import binding as b
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "rrlbm.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = b.lib()
+    syms = declared_symbols()
+    assert syms, "no declarations parsed"
+    assert sorted(syms) == sorted(b.EXPORTS)
+    for s in syms:
+        assert hasattr(L, s), s
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2V17", "D2V37"])
+def test_lattice_tables_agree_with_oracle(orc, name):
+    lat = orc.lattice(name)
+    q, reach, n_eq, cs2 = b.lbm_lattice_info(name)
+    assert (q, reach, n_eq) == (lat.Q, lat.reach, lat.n_eq)
+    assert cs2 == pytest.approx(lat.cs2, rel=2e-16)
+    cx, cy, w = b.lbm_lattice_velocities(name)
+    np.testing.assert_array_equal(np.stack([cx, cy], 1), lat.c)
+    # D2V17's closed-form weights lose a few ulps to cancellation when the
+    # oracle evaluates them in double; the library holds 25-digit decimals
+    np.testing.assert_allclose(w, lat.w, rtol=1e-14, atol=0)
+
+
+def test_buffer_elems_cover_the_grid():
+    for name in ("D2Q9", "D2V17", "D2V37"):
+        q = b.lbm_lattice_info(name)[0]
+        for nx, ny in ((1, 1), (3, 3), (128, 128), (1000, 7), (1024, 1024)):
+            assert b.lbm_buffer_elems(name, nx, ny) >= q * nx * ny
+    with pytest.raises(b.LbmError):
+        b.lbm_buffer_elems(7, 4, 4)
+    with pytest.raises(b.LbmError):
+        b.lbm_buffer_elems("D2Q9", 0, 4)
+
+
+class FakePtr:
+    """Non-null pointer stand-in: validation fails before anything is dereferenced."""
+
+    def __init__(self, v):
+        self.v = v
+
+    def data_ptr(self):
+        return self.v
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(lattice=5), b.LBM_EINVAL),
+    (dict(nx=2), b.LBM_EINVAL),                     # below the D2V37 reach
+    (dict(ny=0), b.LBM_EINVAL),
+    (dict(tau=0.5), b.LBM_ETAU),
+    (dict(tau=float("nan")), b.LBM_ETAU),
+    (dict(reg_order=5), b.LBM_EINVAL),
+    (dict(reg_order=1), b.LBM_EINVAL),
+    (dict(flags=b.LBM_STORE_FP32 | b.LBM_STORE_BF16), b.LBM_EINVAL),
+    (dict(flags=b.LBM_COLL_PR | b.LBM_COLL_BGK), b.LBM_EINVAL),
+    (dict(flags=1 << 20), b.LBM_EINVAL),
+    (dict(lattice=0, flags=b.LBM_THERMAL), b.LBM_EINVAL),  # thermal needs D2V37
+    (dict(lattice=1, reg_order=4), b.LBM_EINVAL),          # D2V17 stops at rank 3
+    (dict(same_buffers=True), b.LBM_EINVAL),
+    (dict(no_rho=True), b.LBM_EINVAL),
+])
+def test_init_rejects_invalid_arguments(args, code):
+    p = dict(lattice=2, nx=8, ny=8, tau=0.6, reg_order=4, flags=0)
+    p.update({k: v for k, v in args.items() if k in p})
+    fa, fb = FakePtr(0x1000), FakePtr(0x2000)
+    if args.get("same_buffers"):
+        fb = fa
+    rho = None if args.get("no_rho") else FakePtr(0x3000)
+    with pytest.raises(b.LbmError) as e:
+        b.lbm_init(p["lattice"], p["nx"], p["ny"], p["tau"], p["reg_order"], p["flags"], fa, fb, rho,
+                   FakePtr(0x4000), FakePtr(0x5000))
+    assert e.value.code == code
+    assert b.lbm_last_error()
+
+
+def test_null_context_is_rejected():
+    for fn in (lambda: b.lbm_step(None, 1), lambda: b.lbm_moments(None), lambda: b.lbm_populations(None, None)):
+        with pytest.raises(b.LbmError):
+            fn()
+    b.lbm_destroy(None)
+    assert b.lbm_step_count(None) == -1
