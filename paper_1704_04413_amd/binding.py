@@ -12,7 +12,7 @@ import os
 
 import numpy as np
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "librrlbm.so")
+LIB_PATH = os.environ.get("RRLBM_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "librrlbm.so")
 
 LBM_D2Q9, LBM_D2V17, LBM_D2V37 = 0, 1, 2
 LATTICES = {"D2Q9": LBM_D2Q9, "D2V17": LBM_D2V17, "D2V37": LBM_D2V37}

@@ -1,19 +1,25 @@
 // librrlbm: fused stream-and-collide recursive-regularized lattice Boltzmann
 // kernels for MI355X (gfx950) and the C-ABI declared in include/rrlbm.h.
 //
-// Data layout in HBM: structure of arrays, one plane per velocity (canonical
-// order), each plane nx*ny values row-major [y][x] followed by padding up to
-// the plane stride, so that a wavefront's 64 lanes touch 64 consecutive
-// values of a plane.  One step is one launch of a pull kernel: the thread of
-// node x gathers f_i(x - c_i) from the source buffer (one fixed offset per
-// plane, so every stored value is read exactly once), collides in registers
-// and writes its Q post-collision values to the destination buffer.  The two
-// buffers alternate; the state kept between steps is post-collision.
+// Data layout in HBM: row-tiled structure of arrays.  The grid is cut into
+// tiles of TY = 4 full rows; a tile stores its Q velocity planes one after the
+// other (plane i of the tile = TY*nx values, row-major), so element
+// (i, y, x) lives at (y / TY) * Q*TY*nx + i * TY*nx + (y % TY) * nx + x.
+// A wavefront's 64 lanes touch 64 consecutive values of one plane, and the
+// 2*Q streams a block reads and writes sit inside about three tiles (a few
+// MiB) instead of 2*Q planes spread over the whole buffer, which keeps the
+// address-translation working set small.  One step is one launch of a pull
+// kernel: the thread of node x gathers f_i(x - c_i) from the source buffer (one
+// fixed offset per plane, so every stored value is read exactly once),
+// collides in registers and writes its Q post-collision values to the
+// destination buffer with non-temporal stores.  The two buffers alternate; the
+// state kept between steps is post-collision.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -31,6 +37,7 @@ struct StoreF64 {
     static constexpr bool shifted = false;
     static __device__ __forceinline__ double load(const double* p) { return *p; }
     static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
+    static __device__ __forceinline__ void store_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
 
 struct StoreF32 {
@@ -39,6 +46,7 @@ struct StoreF32 {
     static constexpr bool shifted = true;
     static __device__ __forceinline__ float load(const float* p) { return *p; }
     static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+    static __device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 
 // bfloat16 = the upper half of an IEEE float; stores round to nearest even.
@@ -50,46 +58,88 @@ struct StoreBF16 {
     {
         return __uint_as_float(uint32_t(*p) << 16);
     }
-    static __device__ __forceinline__ void store(uint16_t* p, float v)
+    static __device__ __forceinline__ uint16_t round(float v)
     {
         uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) {
-            *p = uint16_t((u >> 16) | 0x40u); // quiet NaN
-            return;
-        }
+        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u); // quiet NaN
         u += 0x7fffu + ((u >> 16) & 1u);
-        *p = uint16_t(u >> 16);
+        return uint16_t(u >> 16);
     }
+    static __device__ __forceinline__ void store(uint16_t* p, float v) { *p = round(v); }
+    static __device__ __forceinline__ void store_nt(uint16_t* p, float v) { __builtin_nontemporal_store(round(v), p); }
 };
+
+// ----------------------------------------------------------------- layout
+
+constexpr int TY = 4; // rows per tile
+
+struct Layout {
+    int nx, ny;
+    int te; // elements of one plane of one tile, TY * nx
+    int ts; // elements of one tile, Q * te
+    __host__ __device__ int row(int y) const { return (y / TY) * ts + (y % TY) * nx; }
+    __host__ __device__ int off(int q, int y, int x) const { return row(y) + q * te + x; }
+};
+
+inline Layout make_layout(int q, int nx, int ny) { return Layout{ nx, ny, TY * nx, q * TY * nx }; }
+
+inline int64_t layout_elems(int q, int nx, int ny)
+{
+    return int64_t((ny + TY - 1) / TY) * q * TY * nx;
+}
 
 // ------------------------------------------------------------ step kernel
 
-constexpr int BX = 64, BY = 4;
+constexpr int BX = 64, BY = TY;
+
+// Minimum waves per SIMD the compiler must leave room for in the step
+// kernel (register budget); more resident waves keep more loads in flight
+// while other waves run the collision arithmetic.
+#ifndef RRLBM_WAVES_PER_EU
+#define RRLBM_WAVES_PER_EU 4
+#endif
 
 struct StepArgs {
     const void* fin;
     void* fout;
-    int nx, ny;
-    int64_t plane; // elements between consecutive velocity planes
-    double keep;   // 1 - 1/tau
+    Layout lay;
+    int bx_blocks;  // blocks along x
+    int nblocks;    // total blocks of the 1D grid
+    int xcd_remap;  // 1: give each XCD a contiguous band of blocks
+    double keep;    // 1 - 1/tau
     double inv_tau;
     int order;
 };
 
+// The hardware hands consecutive workgroup ids to the 8 XCDs in turn; with
+// the remap, XCD k works on the k-th contiguous eighth of the tiles, so
+// neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int block_index(const StepArgs& a)
+{
+    const int id = int(blockIdx.x);
+    if (!a.xcd_remap) return id;
+    const int q = a.nblocks / 8, r = a.nblocks % 8;
+    const int xcd = id % 8, local = id / 8;
+    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+}
+
 template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
-__global__ __launch_bounds__(BX* BY) void k_stream_collide(StepArgs a)
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU)))
+void k_stream_collide(StepArgs a)
 {
     using T = typename S::math;
     using E = typename S::elem;
     constexpr int R = L::R;
-    const int x = int(blockIdx.x) * BX + int(threadIdx.x);
-    const int y = int(blockIdx.y) * BY + int(threadIdx.y);
-    if (x >= a.nx || y >= a.ny) return;
+    const int bid = block_index(a);
+    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
+    const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
+    const Layout& lay = a.lay;
+    if (x >= lay.nx || y >= lay.ny) return;
     const E* __restrict__ fin = static_cast<const E*>(a.fin);
     E* __restrict__ fout = static_cast<E*>(a.fout);
-    const int nx = a.nx, ny = a.ny;
+    const int nx = lay.nx, ny = lay.ny;
 
-    // periodic source columns / rows for every shift in [-R, R]
+    // periodic source columns / tile rows for every shift in [-R, R]
     int xs[2 * R + 1], ys[2 * R + 1];
     static_for<2 * R + 1>([&](auto D) {
         constexpr int d = int(D) - R;
@@ -102,28 +152,27 @@ __global__ __launch_bounds__(BX* BY) void k_stream_collide(StepArgs a)
             yy -= (yy >= ny) ? ny : 0;
         }
         xs[D] = xx;
-        ys[D] = yy * nx;
+        ys[D] = lay.row(yy);
     });
 
     T v[L::Q];
-    const int here = y * nx + x;
+    const int here = lay.row(y) + x;
     static_for<L::Q>([&](auto I) {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
-        const int idx = PULL ? ys[cy + R] + xs[cx + R] : here;
-        v[I] = S::load(fin + int64_t(I) * a.plane + idx);
+        const int idx = (PULL ? ys[cy + R] + xs[cx + R] : here) + int(I) * lay.te;
+        v[I] = S::load(fin + idx);
     });
 
     collide_node<L, T, COLL, THERMAL, S::shifted, A13P>(v, T(a.keep), T(a.inv_tau), a.order);
 
-    static_for<L::Q>([&](auto I) { S::store(fout + int64_t(I) * a.plane + here, v[I]); });
+    static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * lay.te, v[I]); });
 }
 
 // ------------------------------------------------------------ init kernel
 
 struct InitArgs {
     void* f;
-    int nx, ny;
-    int64_t plane;
+    Layout lay;
     const double *rho, *ux, *uy, *theta, *noise;
     double noise_amp;
     int eq_order;
@@ -132,9 +181,10 @@ struct InitArgs {
 template <class L, class S>
 __global__ __launch_bounds__(256) void k_init(InitArgs a)
 {
-    const int64_t n = int64_t(a.nx) * a.ny;
+    const int64_t n = int64_t(a.lay.nx) * a.lay.ny;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    const int here = a.lay.row(int(k / a.lay.nx)) + int(k % a.lay.nx);
     double f[L::Q];
     const double th = a.theta ? a.theta[k] : 1.0;
     equilibrium_node<L, double, S::shifted>(a.rho[k], a.ux[k], a.uy[k], th, a.eq_order, f);
@@ -142,21 +192,22 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
     static_for<L::Q>([&](auto I) {
         double v = f[I];
         if (a.noise) v += a.noise_amp * L::v.w[I] * a.noise[int64_t(I) * n + k];
-        S::store(out + int64_t(I) * a.plane + k, typename S::math(v));
+        S::store(out + here + int(I) * a.lay.te, typename S::math(v));
     });
 }
 
 // --------------------------------------------------- populations / moments
 
 template <class L, class S>
-__global__ __launch_bounds__(256) void k_populations(const void* fsrc, int64_t plane, int64_t n,
-                                                     double* out)
+__global__ __launch_bounds__(256) void k_populations(const void* fsrc, Layout lay, double* out)
 {
+    const int64_t n = int64_t(lay.nx) * lay.ny;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
+    const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
     const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
     static_for<L::Q>([&](auto I) {
-        double v = double(S::load(f + int64_t(I) * plane + k));
+        double v = double(S::load(f + here + int(I) * lay.te));
         if (S::shifted) v += L::v.w[I];
         out[int64_t(I) * n + k] = v;
     });
@@ -183,17 +234,18 @@ __device__ __forceinline__ void block_sums(double (&val)[NS], double* partial)
 // rho, u, theta per node (FP64 arithmetic whatever the storage) and block sums
 // of [rho, rho ux, rho uy, sum f|c|^2/2, |u|^2, |u|^4, non-finite, theta].
 template <class L, class S>
-__global__ __launch_bounds__(256) void k_moments(const void* fsrc, int64_t plane, int64_t n, int thermal,
-                                                 double* rho_o, double* ux_o, double* uy_o,
-                                                 double* th_o, double* partial)
+__global__ __launch_bounds__(256) void k_moments(const void* fsrc, Layout lay, int thermal, double* rho_o,
+                                                 double* ux_o, double* uy_o, double* th_o, double* partial)
 {
+    const int64_t n = int64_t(lay.nx) * lay.ny;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double val[MOM_NS] = { 0, 0, 0, 0, 0, 0, 0, 0 };
     if (k < n) {
+        const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
         const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
         double r = 0, jx = 0, jy = 0, e2 = 0;
         static_for<L::Q>([&](auto I) {
-            double v = double(S::load(f + int64_t(I) * plane + k));
+            double v = double(S::load(f + here + int(I) * lay.te));
             if (S::shifted) v += L::v.w[I];
             constexpr double cx = L::v.cx[I], cy = L::v.cy[I];
             r += v;
@@ -295,13 +347,6 @@ bool lattice_info(int lattice, LatInfo* out)
     return false;
 }
 
-int64_t plane_stride(int nx, int ny)
-{
-    // round the plane up to 256 elements and add 256 more, so that plane
-    // strides are never a large power of two
-    const int64_t n = int64_t(nx) * ny;
-    return ((n + 255) / 256) * 256 + 256;
-}
 
 } // namespace
 
@@ -312,7 +357,8 @@ struct lbm_ctx {
     int store = ST_F64, coll = COLL_RR;
     bool thermal = false, a13p = false;
     int q = 0;
-    int64_t plane = 0;
+    Layout lay{};
+    int xcd_remap = 1;
     void* buf[2] = { nullptr, nullptr };
     int cur = 0;
     int64_t steps = 0;
@@ -329,8 +375,9 @@ namespace {
 template <class L, class S, int COLL, bool TH, bool A13P>
 hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
-    StepArgs a{ fin, fout, c->nx, c->ny, c->plane, 1.0 - 1.0 / c->tau, 1.0 / c->tau, c->order };
-    dim3 grid((c->nx + BX - 1) / BX, (c->ny + BY - 1) / BY), block(BX, BY);
+    const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
+    StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, 1.0 - 1.0 / c->tau, 1.0 / c->tau, c->order };
+    dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if (pull)
         k_stream_collide<L, S, COLL, TH, A13P, true><<<grid, block, 0, c->stream>>>(a);
     else
@@ -420,7 +467,7 @@ struct PopOp {
     {
         const int64_t n = int64_t(c->nx) * c->ny;
         k_populations<L, S><<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream>>>(
-            c->buf[c->cur], c->plane, n, out);
+            c->buf[c->cur], c->lay, out);
         return hipGetLastError();
     }
 };
@@ -429,9 +476,8 @@ template <class L, class S>
 struct MomOp {
     static hipError_t run(const lbm_ctx* c, double* r, double* ux, double* uy, double* th)
     {
-        const int64_t n = int64_t(c->nx) * c->ny;
         k_moments<L, S><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(
-            c->buf[c->cur], c->plane, n, c->thermal ? 1 : 0, r, ux, uy, th, c->partial);
+            c->buf[c->cur], c->lay, c->thermal ? 1 : 0, r, ux, uy, th, c->partial);
         return hipGetLastError();
     }
 };
@@ -442,8 +488,7 @@ int validate(int lattice, int nx, int ny, double tau, int reg_order, uint32_t fl
     if (nx < li->reach || ny < li->reach || nx < 1 || ny < 1)
         return fail(LBM_EINVAL, "grid " + std::to_string(nx) + "x" + std::to_string(ny) +
                                     " smaller than the lattice reach " + std::to_string(li->reach));
-    if (int64_t(nx) * ny * li->q >= (int64_t(1) << 31) || plane_stride(nx, ny) * li->q >= (int64_t(1) << 40))
-        return fail(LBM_EINVAL, "grid too large");
+    if (layout_elems(li->q, nx, ny) >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "grid too large");
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_ETAU, "tau must be finite and > 1/2");
     const uint32_t known = LBM_THERMAL | LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_COLL_PR | LBM_COLL_BGK |
                            LBM_EQ_INIT_ORDER2 | LBM_A13_PROJECTED;
@@ -506,7 +551,7 @@ int64_t lbm_buffer_elems(int lattice, int nx, int ny)
     LatInfo li;
     if (!lattice_info(lattice, &li)) return fail(LBM_EINVAL, "unknown lattice");
     if (nx < 1 || ny < 1) return fail(LBM_EINVAL, "empty grid");
-    return plane_stride(nx, ny) * li.q;
+    return layout_elems(li.q, nx, ny);
 }
 
 int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_order, uint32_t flags,
@@ -536,14 +581,16 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     c->thermal = (flags & LBM_THERMAL) != 0;
     c->a13p = (flags & LBM_A13_PROJECTED) != 0;
     c->q = li.q;
-    c->plane = plane_stride(nx, ny);
+    c->lay = make_layout(li.q, nx, ny);
+    // tuning knob: RRLBM_XCD_REMAP=0 keeps the hardware's round-robin block order
+    if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     c->buf[0] = f_a;
     c->buf[1] = f_b;
     c->stream = static_cast<hipStream_t>(stream);
     const int64_t n = int64_t(nx) * ny;
     c->nblk = (n + 255) / 256;
 
-    InitArgs ia{ f_a, nx, ny, c->plane, rho, ux, uy, theta, noise, noise_amp,
+    InitArgs ia{ f_a, c->lay, rho, ux, uy, theta, noise, noise_amp,
                  (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq };
     hipError_t he = dispatch_ls<InitOp>(c, ia);
     if (he == hipSuccess) he = launch_step(c, f_a, f_a, false); // collide in place: post-collision state
