@@ -106,6 +106,77 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
 
 
+def batch_instances(seed=0, count=64):
+    """64 shear-layer instances: side uniform in {128,...,1024}, lattices
+    D2Q9/D2V17/D2V37 with probabilities 0.5/0.3/0.2, Re log-uniform in
+    [1e4, 1e6] (NumPy PCG64 with `seed`)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = np.array([128, 192, 256, 384, 512, 768, 1024])
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(sides))
+        lat = str(rng.choice(["D2Q9", "D2V17", "D2V37"], p=[0.5, 0.3, 0.2]))
+        re = float(10 ** rng.uniform(4, 6))
+        out.append((lat, n, re))
+    return out
+
+
+def batched_suite(torch, b, wl, storage="fp32", steps=40):
+    """All instances advanced by one autotuned, graph-replayed persistent
+    launch per step, against one launch per instance per step."""
+    inst = batch_instances()
+    sims, nodes, nbytes = [], 0, 0
+    for lat, n, re in inst:
+        q, _, _, cs2 = b.lbm_lattice_info(lat)
+        u0, tau = wl.shear_layer_params(cs2, n, re)
+        rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+        sims.append(b.Simulation(lat, n, n, tau, rho, ux, uy, flags=STORAGE_FLAGS[storage]))
+        nodes += n * n
+        nbytes += 2 * q * STORAGE_BYTES[storage] * n * n
+    torch.cuda.synchronize()
+    stream = sims[0].stream
+
+    def timed(fn, k):
+        fn(2)
+        torch.cuda.synchronize()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        fn(k)
+        e.record(stream)
+        torch.cuda.synchronize()
+        return s.elapsed_time(e) * 1e-3
+
+    def per_instance(k):
+        for _ in range(k):
+            for sim in sims:
+                sim.step(1)
+
+    t_sep = timed(per_instance, steps)
+    batch = b.lbm_batch_create([s.ctx for s in sims], 64, 4)
+    tune = b.lbm_batch_autotune(batch, 6)
+    t_bat = timed(lambda k: b.lbm_batch_step(batch, k), steps)
+    cfg = b.lbm_batch_config(batch)
+    b.lbm_batch_destroy(batch)
+    bad = 0
+    for sim in sims:
+        bad += int(sim.moments(vorticity=False)["sums"][8])
+        sim.close()
+    mix = {l: sum(1 for x in inst if x[0] == l) for l in ("D2Q9", "D2V17", "D2V37")}
+    return {
+        "workload": f"{len(inst)} shear-layer instances, sides 128..1024, lattices {mix}, Re 1e4..1e6, "
+                    f"{storage} shifted storage",
+        "nodes": nodes, "bytes_per_step": nbytes, "steps": steps,
+        "batched_MLUPS": round(nodes * steps / t_bat / 1e6, 1),
+        "batched_GBs": round(nbytes * steps / t_bat / 1e9, 1),
+        "batched_frac_hbm": round(nbytes * steps / t_bat / 1e9 / HBM_PEAK_GBS, 4),
+        "per_instance_MLUPS": round(nodes * steps / t_sep / 1e6, 1),
+        "per_instance_GBs": round(nbytes * steps / t_sep / 1e9, 1),
+        "tile_x": cfg[0], "blocks_per_cu": cfg[1],
+        "autotune": [list(r) for r in tune],
+        "nonfinite_nodes": bad,
+    }
+
+
 def cpu_baseline(wl, lattice_name, n, steps, seed=0):
     """The oracle as it stands, timed on the host cores on `steps` steps of
     the full grid (MLUPS)."""
@@ -134,6 +205,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-only", action="store_true", help="only run 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
 
@@ -216,6 +288,8 @@ def main():
                           "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
         out["per_lattice"] = sweep
         out["copy_GBs"] = round(copy_bandwidth(torch), 1)
+    if not args.no_batch:
+        out["batched"] = batched_suite(torch, b, wl)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.lattice, args.n, args.cpu_steps)
     print(json.dumps(out), flush=True)

@@ -78,13 +78,14 @@ int lbm_lattice_info(int lattice, int* q, int* reach, int* n_eq, double* cs2);
 int lbm_lattice_velocities(int lattice, int* cx, int* cy, double* w);
 
 /* Elements (of the storage type) one population buffer must hold for an
- * nx by ny grid: q planes of nx*ny values plus padding.  Negative on error. */
+ * nx by ny grid: q * nx * (ny rounded up to a multiple of 4), the library's
+ * row-tiled layout.  Negative on error. */
 int64_t lbm_buffer_elems(int lattice, int nx, int ny);
 
 /* Creates a context and writes the initial state.
  *   lattice    LBM_D2Q9, LBM_D2V17 or LBM_D2V37.
- *   nx, ny     grid size; each must be >= the lattice reach and nx*ny*q must
- *              stay below 2^31.
+ *   nx, ny     grid size; each must be >= the lattice reach and
+ *              lbm_buffer_elems() must stay below 2^31.
  *   tau        discrete relaxation time (tau-bar of Sec. III.A, > 1/2):
  *              nu = c_s^2 theta (tau - 1/2).
  *   reg_order  regularization order N, 2 <= N <= n_eq; the non-equilibrium
@@ -137,6 +138,112 @@ void lbm_destroy(lbm_ctx* ctx);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* lbm_last_error(void);
+
+/* ---- Batched stepping ----------------------------------------------------
+ * Many independent contexts (any lattice and grid size) advanced together:
+ * one persistent launch per step walks a work list of 4-row tiles that spans
+ * every member, and lbm_batch_step replays a HIP graph holding two such
+ * launches (the two buffer parities).  Members keep working with
+ * lbm_moments / lbm_populations / lbm_destroy; the batch never owns them. */
+typedef struct lbm_batch lbm_batch;
+
+/* ctxs: host array of n (1..4096) contexts from lbm_init.  All members must
+ * use the same storage flag, the recursive-regularized isothermal collision
+ * (no LBM_COLL_PR, LBM_COLL_BGK or LBM_THERMAL) and the same stream (the
+ * batch launches on it).  tile_x (64, 128 or 256) is the width of one work
+ * item in nodes; blocks_per_cu (1..16) sets the persistent grid to that many
+ * blocks per compute unit.  Captures the graph; *out is set on success. */
+int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, int blocks_per_cu);
+
+/* Advances every member by nsteps (>= 0).  If a member was stepped on its
+ * own since the last call, its buffer parity is re-read first (a small
+ * host-to-device copy outside the graph). */
+int lbm_batch_step(lbm_batch* b, int nsteps);
+
+/* Autotuner: times every (tile_x, blocks_per_cu) candidate over
+ * steps_per_trial graph-replayed steps (members are advanced by those
+ * steps), keeps the fastest and recaptures the graph.  report (host, may be
+ * NULL) receives one line per candidate, "tile_x blocks_per_cu ms_per_step",
+ * truncated to report_len bytes.  Synchronizes the stream. */
+int lbm_batch_autotune(lbm_batch* b, int steps_per_trial, char* report, int report_len);
+
+/* Current (tile_x, blocks_per_cu) of the batch (either pointer may be NULL). */
+int lbm_batch_config(const lbm_batch* b, int* tile_x, int* blocks_per_cu);
+
+/* Releases the graph and the work list (not the members).  NULL is a no-op. */
+void lbm_batch_destroy(lbm_batch* b);
+
+/* ---- Learned closure (not part of the paper's method) --------------------
+ * A per-node perceptron 8 -> 64 -> 64 -> 9 (tanh-form GELU), evaluated on the
+ * bfloat16 matrix cores with float32 accumulation, predicts a residual added
+ * to the isothermal recursive a1^(3), a1^(4) of the D2V37 collision; mass and
+ * momentum are unaffected by construction.  Coefficients use the scaling
+ * ahat = (1 - 1/(2 tau)) a1, comparable across grids under acoustic scaling.
+ *
+ * Parameter vector: LBM_MLP_NPARAM float32, row-major [in][out] matrices
+ *   W1 8x64 | b1 64 | W2 64x64 | b2 64 | W3 64x16 | b3 16  (outputs 9..15 unused, keep 0)
+ * Normalisation block: LBM_MLP_NNORM float32
+ *   in_mean[8] in_std[8] in_lo[8] in_hi[8] out_mean[16] out_std[16] out_lo[16] out_hi[16]
+ * Inputs 0..6: rho - 1, ux, uy, theta_kin - 1 (energy moment), ahat_xx,
+ * ahat_xy, ahat_yy; input 7 is the constant 1 (not normalised).  Outputs
+ * 0..8: the ahat^(3..4) residual, order 30, 21, 12, 03, 40, 31, 22, 13, 04
+ * (x and y exponents).  lo/hi bound the training data in normalised units:
+ * a node whose normalised input or output leaves them keeps the plain
+ * recursion (the fallback). */
+#define LBM_MLP_NPARAM 5776
+#define LBM_MLP_NNORM 96
+
+/* Training samples from a fine run, restricted to a grid coarser by
+ * `factor` (1..8, dividing nx and ny): for every coarse node the block
+ * average of the fine nodes' rho, rho u and ahat^(2..4) (ahat computed from
+ * the fine post-collision populations with the fine tau), then
+ *   x[c][0..7] = raw inputs (input 7 = 1), and
+ *   r[c][0..15] = ahat^(3..4) minus the recursion applied to the averaged
+ *                 (rho, u, ahat^(2)) (entries 9..15 = 0).
+ * tau_coarse enters only theta_kin.  fine must be an isothermal RR D2V37
+ * context; x, r are device float32 arrays of (nx/factor)*(ny/factor) rows.
+ * Coarse node c = X + Y * (nx/factor).  Runs on fine's stream. */
+int lbm_closure_samples(lbm_ctx* fine, int factor, double tau_coarse, float* x, float* r);
+
+/* Normalisation block of n samples (x as above, r as above): mean and
+ * standard deviation of inputs 0..6 and outputs 0..8 (a zero deviation is
+ * replaced by 1), and their min/max in normalised units; device `norm` of
+ * LBM_MLP_NNORM floats.  Synchronizes `stream`. */
+int lbm_mlp_stats(const float* x, const float* r, int64_t n, float* norm, void* stream);
+
+/* In place: x[.][0..6] and r[.][0..8] normalised with `norm`, x[.][7] = 1. */
+int lbm_mlp_normalize(float* x, float* r, int64_t n, const float* norm, void* stream);
+
+/* Training state of one network: theta (device, LBM_MLP_NPARAM float32,
+ * caller-owned, updated in place) plus the library's Adam moments, gradient,
+ * matrix-core weight fragments and per-wave partial sums for batches of up
+ * to max_batch samples. */
+typedef struct lbm_mlp lbm_mlp;
+int lbm_mlp_create(lbm_mlp** out, float* theta, int64_t max_batch, void* stream);
+
+/* Network outputs y[n][16] (normalised; 9..15 = padding) for normalised
+ * inputs x[n][8], with the current theta. */
+int lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t n, float* y);
+
+/* Mean squared error over `batch` samples (rows idx[0..batch) of x, t, or
+ * rows 0..batch when idx is NULL; t[.][0..8] normalised targets) and its
+ * gradient.  grad (device, LBM_MLP_NPARAM) may be NULL; loss (host) may be
+ * NULL, otherwise the call synchronizes.  lr > 0 also applies one Adam step
+ * (beta1 0.9, beta2 0.999, eps 1e-8) to theta; lr = 0 leaves theta alone. */
+int lbm_mlp_step(lbm_mlp* m, const float* x, const float* t, const int* idx, int64_t batch, float lr,
+                 float* grad, double* loss);
+
+void lbm_mlp_destroy(lbm_mlp* m);
+
+/* Attaches a trained closure to an isothermal RR D2V37 context (FP64 or FP32
+ * storage): theta and norm are device float32 arrays (copied; the caller may
+ * free them).  Later lbm_step calls run the fused closure kernel.  theta =
+ * NULL detaches.  Resets the fallback counter. */
+int lbm_closure_set(lbm_ctx* ctx, const float* theta, const float* norm);
+
+/* Nodes (summed over steps) that kept the plain recursion since
+ * lbm_closure_set.  Synchronizes the stream. */
+int lbm_closure_fallbacks(lbm_ctx* ctx, int64_t* count);
 
 #ifdef __cplusplus
 }

@@ -62,6 +62,9 @@ def lib():
         L.orc_step.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] + [ctypes.c_int] * 3 + [dp, dp]
         L.orc_moments.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, dp, dp]
         L.orc_threads.argtypes = []
+        L.orc_closure_inputs.argtypes = [ctypes.c_int, ctypes.c_double, i64, dp, dp, dp]
+        L.orc_collide_closure.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, i64, dp, dp, dp]
+        L.orc_noneq_projected.argtypes = [ctypes.c_int, i64, dp, dp]
         _lib = L
     return _lib
 
@@ -205,6 +208,44 @@ def moments(lat: Lattice, f, thermal=False):
            "moments")
     r = [a.reshape(shape) for a in (rho, ux, uy, th)]
     return r[0], r[1], r[2], r[3]
+
+
+def closure_inputs(lat: Lattice, f, tau):
+    """(feat[7, n], rr[9, n]) of pre-collision populations f (Q, ...):
+    feat = (rho-1, ux, uy, theta_kin-1, ahat_xx, ahat_xy, ahat_yy), rr = ahat of
+    the plain recursive a1^(3..4) in the order 30,21,12,03,40,31,22,13,04."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(lat.Q, -1)
+    n = f.shape[1]
+    feat, rr = np.zeros((7, n)), np.zeros((9, n))
+    _check(lib().orc_closure_inputs(lat.id, tau, n, _p(f), _p(feat), _p(rr)), "closure_inputs")
+    return feat, rr
+
+
+def noneq_projected(lat: Lattice, f) -> np.ndarray:
+    """a1 by projection, (12, n): xx, xy, yy, 30, 21, 12, 03, 40, 31, 22, 13, 04."""
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(lat.Q, -1)
+    out = np.zeros((12, f.shape[1]))
+    _check(lib().orc_noneq_projected(lat.id, f.shape[1], _p(f), _p(out)), "noneq_projected")
+    return out
+
+
+def stream(lat: Lattice, g) -> np.ndarray:
+    """Periodic push streaming of (Q, ny, nx) populations: f_i(x + c_i) = g_i(x)."""
+    return np.stack([np.roll(g[i], shift=(int(lat.c[i, 1]), int(lat.c[i, 0])), axis=(0, 1))
+                     for i in range(lat.Q)])
+
+
+def collide_closure(lat: Lattice, f, tau, resid, order=None) -> np.ndarray:
+    """Isothermal RR collision with a residual resid[9, n] (a_hat scaling)
+    added to a1^(3..4)."""
+    shape = f.shape
+    f = np.ascontiguousarray(f, dtype=np.float64).reshape(lat.Q, -1)
+    n = f.shape[1]
+    resid = np.ascontiguousarray(resid, dtype=np.float64).reshape(9, n)
+    out = np.zeros_like(f)
+    order = lat.n_eq if order is None else order
+    _check(lib().orc_collide_closure(lat.id, order, tau, n, _p(f), _p(resid), _p(out)), "collide_closure")
+    return out.reshape(shape)
 
 
 # ---- diagnostics of Sec. III.B ---------------------------------------------

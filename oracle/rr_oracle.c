@@ -580,6 +580,119 @@ int orc_step(int id, int coll, int order, int thermal, int a13_raw, double tau, 
     return 0;
 }
 
+/* ---- Learned-closure support (not part of the paper's method) ----------
+ * The closure replaces nothing of the step above: it adds a learned residual
+ * to the isothermal recursive a1^(3), a1^(4).  Coefficients are exchanged in
+ * the tau-independent scaling a_hat = (1 - 1/(2 tau)) a1 (the viscous stress
+ * is -a_hat^(2)), in the component order 30, 21, 12, 03, 40, 31, 22, 13, 04
+ * (n_x, n_y). */
+
+static const int orc_hi_nx[9] = { 3, 2, 1, 0, 4, 3, 2, 1, 0 };
+
+static int pattern_of(int nx, int ny) { return ((1 << ny) - 1) << nx; }
+
+/* Per node of pre-collision f[Q][n] (isothermal): feat[7][n] =
+ * (rho - 1, ux, uy, theta_kin - 1, ahat_xx, ahat_xy, ahat_yy) with
+ * theta_kin from the energy moment, and rr[9][n] = a_hat of the plain
+ * recursive a1^(3..4). */
+int orc_closure_inputs(int id, double tau, int64_t n, const double* f, double* feat, double* rr)
+{
+    orc_lattice_t L;
+    if (build_lattice(id, &L)) return -1;
+    const double s = 1.0 - 0.5 / tau;
+    orc_cfg_t c = { ORC_RR, L.n_eq, 0, 0, tau };
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        double fl[ORC_MAXQ], a0[ORC_NT], feq[ORC_MAXQ], a1[ORC_NT], rho, u[2], th;
+        for (int i = 0; i < L.Q; ++i) fl[i] = f[(int64_t)i * n + k];
+        node_moments(&L, fl, 1, &rho, &u[0], &u[1], &th);
+        eq_coeffs(&L, rho, u[0], u[1], 1.0, a0);
+        hermite_sum(&L, a0, L.n_eq, feq);
+        noneq_coeffs(&L, &c, fl, feq, rho, u, 1.0, a0, a1);
+        feat[0 * n + k] = rho - 1.0;
+        feat[1 * n + k] = u[0];
+        feat[2 * n + k] = u[1];
+        feat[3 * n + k] = th - 1.0;
+        feat[4 * n + k] = s * a1[toff(2, pattern_of(2, 0))];
+        feat[5 * n + k] = s * a1[toff(2, pattern_of(1, 1))];
+        feat[6 * n + k] = s * a1[toff(2, pattern_of(0, 2))];
+        for (int j = 0; j < 9; ++j) {
+            const int nx = orc_hi_nx[j], ny = (j < 4 ? 3 : 4) - nx;
+            rr[(int64_t)j * n + k] = s * a1[toff(nx + ny, pattern_of(nx, ny))];
+        }
+    }
+    return 0;
+}
+
+/* Projected non-equilibrium coefficients of every node (isothermal
+ * equilibrium at the lattice's full order): out[12][n] = a1 for
+ * xx, xy, yy, 30, 21, 12, 03, 40, 31, 22, 13, 04, each sum_i H^k_i (f_i - f^(0)_i). */
+int orc_noneq_projected(int id, int64_t n, const double* f, double* out)
+{
+    orc_lattice_t L;
+    if (build_lattice(id, &L)) return -1;
+    static const int nxs[12] = { 2, 1, 0, 3, 2, 1, 0, 4, 3, 2, 1, 0 };
+    static const int nys[12] = { 0, 1, 2, 0, 1, 2, 3, 0, 1, 2, 3, 4 };
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        double fl[ORC_MAXQ], a0[ORC_NT], feq[ORC_MAXQ], g[ORC_MAXQ], rho, ux, uy, th;
+        for (int i = 0; i < L.Q; ++i) fl[i] = f[(int64_t)i * n + k];
+        node_moments(&L, fl, 0, &rho, &ux, &uy, &th);
+        eq_coeffs(&L, rho, ux, uy, 1.0, a0);
+        hermite_sum(&L, a0, L.n_eq, feq);
+        for (int i = 0; i < L.Q; ++i) g[i] = fl[i] - feq[i];
+        for (int j = 0; j < 12; ++j) {
+            const int m = nxs[j] + nys[j];
+            const int b = pattern_of(nxs[j], nys[j]);
+            double s = 0;
+            for (int i = 0; i < L.Q; ++i) s += L.H[i][toff(m, b)] * g[i];
+            out[(int64_t)j * n + k] = s;
+        }
+    }
+    return 0;
+}
+
+/* Isothermal RR collision of every node with a1^(3..4) += resid / (1 - 1/(2 tau))
+ * (resid[9][n] in the a_hat scaling; ranks beyond the order are dropped as
+ * in the plain collision).  resid = 0 reproduces orc_collide. */
+int orc_collide_closure(int id, int order, double tau, int64_t n, const double* f, const double* resid,
+                        double* out)
+{
+    orc_lattice_t L;
+    if (build_lattice(id, &L)) return -1;
+    int e = check_cfg(&L, ORC_RR, order, tau);
+    if (e) return e;
+    orc_cfg_t c = { ORC_RR, order, 0, 0, tau };
+    const double inv_s = 1.0 / (1.0 - 0.5 / tau);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        double fl[ORC_MAXQ], a0[ORC_NT], feq[ORC_MAXQ], a1[ORC_NT], rho, u[2], th, a[ORC_NT];
+        for (int i = 0; i < L.Q; ++i) fl[i] = f[(int64_t)i * n + k];
+        node_moments(&L, fl, 0, &rho, &u[0], &u[1], &th);
+        eq_coeffs(&L, rho, u[0], u[1], 1.0, a0);
+        hermite_sum(&L, a0, L.n_eq, feq);
+        noneq_coeffs(&L, &c, fl, feq, rho, u, 1.0, a0, a1);
+        for (int j = 0; j < 9; ++j) {
+            const int nx = orc_hi_nx[j], ny = (j < 4 ? 3 : 4) - nx;
+            const double add = resid[(int64_t)j * n + k] * inv_s;
+            /* every index order of the (nx, ny) component */
+            for (int b = 0; b < (1 << (nx + ny)); ++b)
+                if (popcount5(b) == ny) a1[toff(nx + ny, b)] += add;
+        }
+        const double kk = 1.0 - 1.0 / tau;
+        for (int m = 0; m <= 4; ++m)
+            for (int b = 0; b < (1 << m); ++b) {
+                double v = a0[toff(m, b)];
+                if (m >= 2 && m <= order) v += kk * a1[toff(m, b)];
+                a[toff(m, b)] = v;
+            }
+        double fo[ORC_MAXQ];
+        hermite_sum(&L, a, L.n_eq, fo);
+        for (int i = 0; i < L.Q; ++i) out[(int64_t)i * n + k] = fo[i];
+    }
+    return 0;
+}
+
 /* rho, u (and theta if thermal) of every node of f[Q][n]. */
 int orc_moments(int id, int thermal, int64_t n, const double* f, double* rho, double* ux,
                 double* uy, double* theta)

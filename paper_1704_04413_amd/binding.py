@@ -29,7 +29,12 @@ LBM_OK, LBM_EINVAL, LBM_ETAU, LBM_EDEVICE, LBM_ENOMEM = 0, -1, -2, -3, -4
 
 # every symbol declared in include/rrlbm.h
 EXPORTS = ["lbm_lattice_info", "lbm_lattice_velocities", "lbm_buffer_elems", "lbm_init", "lbm_step",
-           "lbm_step_count", "lbm_moments", "lbm_populations", "lbm_destroy", "lbm_last_error"]
+           "lbm_step_count", "lbm_moments", "lbm_populations", "lbm_destroy", "lbm_last_error",
+           "lbm_batch_create", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_config", "lbm_batch_destroy",
+           "lbm_closure_samples", "lbm_mlp_stats", "lbm_mlp_normalize", "lbm_mlp_create", "lbm_mlp_forward",
+           "lbm_mlp_step", "lbm_mlp_destroy", "lbm_closure_set", "lbm_closure_fallbacks"]
+LBM_MLP_NPARAM = 5776
+LBM_MLP_NNORM = 96
 
 
 class LbmError(RuntimeError):
@@ -64,6 +69,24 @@ def lib():
         L.lbm_destroy.restype = None
         L.lbm_last_error.argtypes = []
         L.lbm_last_error.restype = ctypes.c_char_p
+        L.lbm_batch_create.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int]
+        L.lbm_batch_step.argtypes = [vp, ctypes.c_int]
+        L.lbm_batch_autotune.argtypes = [vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_int]
+        L.lbm_batch_config.argtypes = [vp, ip, ip]
+        L.lbm_batch_destroy.argtypes = [vp]
+        L.lbm_batch_destroy.restype = None
+        i64 = ctypes.c_int64
+        L.lbm_closure_samples.argtypes = [vp, ctypes.c_int, ctypes.c_double, vp, vp]
+        L.lbm_mlp_stats.argtypes = [vp, vp, i64, vp, vp]
+        L.lbm_mlp_normalize.argtypes = [vp, vp, i64, vp, vp]
+        L.lbm_mlp_create.argtypes = [ctypes.POINTER(vp), vp, i64, vp]
+        L.lbm_mlp_forward.argtypes = [vp, vp, i64, vp]
+        L.lbm_mlp_step.argtypes = [vp, vp, vp, vp, i64, ctypes.c_float, vp, ctypes.POINTER(ctypes.c_double)]
+        L.lbm_mlp_destroy.argtypes = [vp]
+        L.lbm_mlp_destroy.restype = None
+        L.lbm_closure_set.argtypes = [vp, vp, vp]
+        L.lbm_closure_fallbacks.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
         _lib = L
     return _lib
 
@@ -138,6 +161,86 @@ def lbm_populations(ctx, f_out):
 
 def lbm_destroy(ctx):
     lib().lbm_destroy(ctypes.c_void_p(ctx))
+
+
+def lbm_batch_create(ctxs, tile_x=64, blocks_per_cu=4):
+    """ctxs: context handles (integers).  Returns the batch handle."""
+    arr = (ctypes.c_void_p * len(ctxs))(*[ctypes.c_void_p(c) for c in ctxs])
+    out = ctypes.c_void_p()
+    _check(lib().lbm_batch_create(ctypes.byref(out), arr, len(ctxs), tile_x, blocks_per_cu))
+    return out.value
+
+
+def lbm_batch_step(batch, nsteps: int):
+    _check(lib().lbm_batch_step(ctypes.c_void_p(batch), nsteps))
+
+
+def lbm_batch_autotune(batch, steps_per_trial: int = 10) -> list:
+    """Returns [(tile_x, blocks_per_cu, ms_per_step), ...] for every candidate."""
+    buf = ctypes.create_string_buffer(4096)
+    _check(lib().lbm_batch_autotune(ctypes.c_void_p(batch), steps_per_trial, buf, len(buf)))
+    rows = []
+    for line in buf.value.decode().splitlines():
+        t, b, ms = line.split()
+        rows.append((int(t), int(b), float(ms)))
+    return rows
+
+
+def lbm_batch_config(batch):
+    t, b = ctypes.c_int(), ctypes.c_int()
+    _check(lib().lbm_batch_config(ctypes.c_void_p(batch), ctypes.byref(t), ctypes.byref(b)))
+    return t.value, b.value
+
+
+def lbm_batch_destroy(batch):
+    lib().lbm_batch_destroy(ctypes.c_void_p(batch))
+
+
+def _stream(stream):
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+
+
+def lbm_closure_samples(ctx, factor, tau_coarse, x, r):
+    _check(lib().lbm_closure_samples(ctypes.c_void_p(ctx), factor, tau_coarse, _ptr(x), _ptr(r)))
+
+
+def lbm_mlp_stats(x, r, n, norm, stream=None):
+    _check(lib().lbm_mlp_stats(_ptr(x), _ptr(r), n, _ptr(norm), _stream(stream)))
+
+
+def lbm_mlp_normalize(x, r, n, norm, stream=None):
+    _check(lib().lbm_mlp_normalize(_ptr(x), _ptr(r), n, _ptr(norm), _stream(stream)))
+
+
+def lbm_mlp_create(theta, max_batch, stream=None):
+    out = ctypes.c_void_p()
+    _check(lib().lbm_mlp_create(ctypes.byref(out), _ptr(theta), max_batch, _stream(stream)))
+    return out.value
+
+
+def lbm_mlp_forward(m, x, n, y):
+    _check(lib().lbm_mlp_forward(ctypes.c_void_p(m), _ptr(x), n, _ptr(y)))
+
+
+def lbm_mlp_step(m, x, t, idx, batch, lr, grad=None, want_loss=False):
+    loss = ctypes.c_double()
+    _check(lib().lbm_mlp_step(ctypes.c_void_p(m), _ptr(x), _ptr(t), _ptr(idx), batch, lr, _ptr(grad),
+                              ctypes.byref(loss) if want_loss else None))
+    return loss.value if want_loss else None
+
+
+def lbm_mlp_destroy(m):
+    lib().lbm_mlp_destroy(ctypes.c_void_p(m))
+
+
+def lbm_closure_set(ctx, theta, norm):
+    _check(lib().lbm_closure_set(ctypes.c_void_p(ctx), _ptr(theta), _ptr(norm)))
+
+
+def lbm_closure_fallbacks(ctx) -> int:
+    n = ctypes.c_int64()
+    _check(lib().lbm_closure_fallbacks(ctypes.c_void_p(ctx), ctypes.byref(n)))
+    return int(n.value)
 
 
 # ---------------------------------------------------------------- helper

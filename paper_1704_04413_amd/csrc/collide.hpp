@@ -146,10 +146,18 @@ __device__ __forceinline__ void eq_factors(T u, T sig, T (&m)[5])
     m[4] = u2 * u2 + T(6) * sig * u2 + T(3) * sig * sig;
 }
 
-// The regularized (or BGK) collision of one node, in place.
-//   keep = 1 - 1/tau, inv_tau = 1/tau, order = N.
+// Moments, equilibrium and non-equilibrium Hermite coefficients of one node
+// (steps 1-4 above).  C holds a0 (not yet normalised), a1 the
+// non-equilibrium coefficients before truncation.
+template <class T>
+struct NodeCoeffs {
+    T rho, drho, ux, uy, sig;
+    T C[5][5];
+    T a1[5][5];
+};
+
 template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
-__device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, int order)
+__device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k)
 {
     constexpr T cs2 = T(L::cs2);
     T s[5][5];
@@ -161,6 +169,10 @@ __device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, in
     const T inv_rho = T(1) / rho;
     const T ux = s[1][0] * inv_rho;
     const T uy = s[0][1] * inv_rho;
+    k.rho = rho;
+    k.drho = drho;
+    k.ux = ux;
+    k.uy = uy;
 
     // Hermite moments h_k = sum_i H^k_i v_i (k != 0)
     const T h20 = s[2][0] - cs2 * s00;
@@ -173,39 +185,25 @@ __device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, in
         const T thm1 = (h20 + h02 - rho * (ux * ux + uy * uy)) * inv_rho * (T(0.5) / cs2);
         sig = cs2 * thm1;
     }
+    k.sig = sig;
     T mx[5], my[5];
     eq_factors<T>(ux, sig, mx);
     eq_factors<T>(uy, sig, my);
 
-    T C[5][5];
-    zero_coeffs<L, T>(C);
+    zero_coeffs<L, T>(k.C);
     // equilibrium part (a1^(0) = a1^(1) = 0)
     static_for<5>([&](auto KX) {
         static_for<5>([&](auto KY) {
             if constexpr (L::basis(int(KX), int(KY)) && int(KX) + int(KY) >= 1)
-                C[KX][KY] = rho * mx[KX] * my[KY];
+                k.C[KX][KY] = rho * mx[KX] * my[KY];
         });
     });
-    C[0][0] = SHIFTED ? drho : rho;
+    k.C[0][0] = SHIFTED ? drho : rho;
 
-    if constexpr (COLL == COLL_BGK) {
-        static_for<5>([&](auto KX) {
-            static_for<5>([&](auto KY) {
-                if constexpr (L::basis(int(KX), int(KY)) && int(KX) + int(KY) >= 1) {
-                    constexpr double nrm = inv_norm<L>(int(KX), int(KY));
-                    C[KX][KY] *= T(nrm);
-                }
-            });
-        });
-        T eq[L::Q];
-        reconstruct<L, T>(C, eq);
-        static_for<L::Q>([&](auto I) { v[I] = keep * v[I] + inv_tau * eq[I]; });
-        return;
-    }
-
-    // non-equilibrium coefficients
-    T a1[5][5];
+    auto& C = k.C;
+    auto& a1 = k.a1;
     static_for<5>([&](auto a) { static_for<5>([&](auto b) { a1[a][b] = T(0); }); });
+    if constexpr (COLL == COLL_BGK) return;
     a1[2][0] = h20 - C[2][0];
     a1[1][1] = h11 - C[1][1];
     a1[0][2] = h02 - C[0][2];
@@ -282,24 +280,53 @@ __device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, in
         a1[1][3] = T(3) * uy * a1[1][2] + ux * a1[0][3] + T(3) * by * xy - T(3) * uxy * yy;
         a1[0][4] = T(4) * uy * a1[0][3] + T(6) * by * yy;
     }
+}
 
-    // relax: C = (a0 + k_n a1) / norm over the basis, k_n = keep for 2 <= n <= N
+// Step 5: relax and rebuild the populations,
+// C = (a0 + k_n a1) / norm over the basis, k_n = keep for 2 <= n <= N.
+template <class L, class T>
+__device__ __forceinline__ void relax_reconstruct(NodeCoeffs<T>& k, T keep, int order, T (&out)[L::Q])
+{
     const T k3 = order >= 3 ? keep : T(0);
     const T k4 = order >= 4 ? keep : T(0);
     static_for<5>([&](auto KX) {
         static_for<5>([&](auto KY) {
             constexpr int n = int(KX) + int(KY);
             if constexpr (L::basis(int(KX), int(KY)) && n >= 1) {
-                T c = C[KX][KY];
-                if constexpr (n == 2) c += keep * a1[KX][KY];
-                if constexpr (n == 3) c += k3 * a1[KX][KY];
-                if constexpr (n == 4) c += k4 * a1[KX][KY];
+                T c = k.C[KX][KY];
+                if constexpr (n == 2) c += keep * k.a1[KX][KY];
+                if constexpr (n == 3) c += k3 * k.a1[KX][KY];
+                if constexpr (n == 4) c += k4 * k.a1[KX][KY];
                 constexpr double nrm = inv_norm<L>(int(KX), int(KY));
-                C[KX][KY] = c * T(nrm);
+                k.C[KX][KY] = c * T(nrm);
             }
         });
     });
-    reconstruct<L, T>(C, v);
+    reconstruct<L, T>(k.C, out);
+}
+
+// The regularized (or BGK) collision of one node, in place.
+//   keep = 1 - 1/tau, inv_tau = 1/tau, order = N.
+template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
+__device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, int order)
+{
+    NodeCoeffs<T> k;
+    node_coeffs<L, T, COLL, THERMAL, SHIFTED, A13P>(v, k);
+    if constexpr (COLL == COLL_BGK) {
+        static_for<5>([&](auto KX) {
+            static_for<5>([&](auto KY) {
+                if constexpr (L::basis(int(KX), int(KY)) && int(KX) + int(KY) >= 1) {
+                    constexpr double nrm = inv_norm<L>(int(KX), int(KY));
+                    k.C[KX][KY] *= T(nrm);
+                }
+            });
+        });
+        T eq[L::Q];
+        reconstruct<L, T>(k.C, eq);
+        static_for<L::Q>([&](auto I) { v[I] = keep * v[I] + inv_tau * eq[I]; });
+        return;
+    }
+    relax_reconstruct<L, T>(k, keep, order, v);
 }
 
 // Equilibrium populations truncated at Hermite rank `order` (initial state).

@@ -21,6 +21,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -123,20 +124,14 @@ __device__ __forceinline__ int block_index(const StepArgs& a)
     return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
 }
 
+// One node: gather (pull, periodic, or local when !PULL), collide, store.
 template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
-__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU)))
-void k_stream_collide(StepArgs a)
+__device__ __forceinline__ void node_update(const typename S::elem* __restrict__ fin,
+                                            typename S::elem* __restrict__ fout, const Layout& lay, int x,
+                                            int y, double keep, double inv_tau, int order)
 {
     using T = typename S::math;
-    using E = typename S::elem;
     constexpr int R = L::R;
-    const int bid = block_index(a);
-    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
-    const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
-    const Layout& lay = a.lay;
-    if (x >= lay.nx || y >= lay.ny) return;
-    const E* __restrict__ fin = static_cast<const E*>(a.fin);
-    E* __restrict__ fout = static_cast<E*>(a.fout);
     const int nx = lay.nx, ny = lay.ny;
 
     // periodic source columns / tile rows for every shift in [-R, R]
@@ -163,10 +158,81 @@ void k_stream_collide(StepArgs a)
         v[I] = S::load(fin + idx);
     });
 
-    collide_node<L, T, COLL, THERMAL, S::shifted, A13P>(v, T(a.keep), T(a.inv_tau), a.order);
+    collide_node<L, T, COLL, THERMAL, S::shifted, A13P>(v, T(keep), T(inv_tau), order);
 
     static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * lay.te, v[I]); });
 }
+
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU)))
+void k_stream_collide(StepArgs a)
+{
+    const int bid = block_index(a);
+    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
+    const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
+    if (x >= a.lay.nx || y >= a.lay.ny) return;
+    node_update<L, S, COLL, THERMAL, A13P, PULL>(static_cast<const typename S::elem*>(a.fin),
+                                                 static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.keep,
+                                                 a.inv_tau, a.order);
+}
+
+// ---------------------------------------------------------- batch kernel
+
+// One member of a batch as the persistent kernel sees it.
+struct InstDesc {
+    void* buf[2];
+    Layout lay;
+    int lattice;
+    int bx_blocks; // work items along x
+    int flip;      // index of the buffer holding the member's current state
+    int order;
+    double keep, inv_tau;
+};
+
+// Persistent kernel: blocks stride over the work list (member, tile); item w
+// belongs to the member i with begin[i] <= w < begin[i+1].  Each item is a
+// tile_x by 4 patch of one member, walked 64 columns at a time.  `parity`
+// selects the buffer direction of this step for every member.
+template <class S>
+__global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ desc, const int* __restrict__ begin,
+                                                  int n, int total, int parity, int tile_x)
+{
+    using E = typename S::elem;
+    for (int w = int(blockIdx.x); w < total; w += int(gridDim.x)) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (begin[mid] <= w)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int i = __builtin_amdgcn_readfirstlane(lo);
+        const InstDesc& d = desc[i];
+        const int local = w - begin[i];
+        const int x0 = (local % d.bx_blocks) * tile_x;
+        const int y = (local / d.bx_blocks) * BY + int(threadIdx.y);
+        const int src = d.flip ^ parity;
+        const E* fin = static_cast<const E*>(d.buf[src]);
+        E* fout = static_cast<E*>(d.buf[src ^ 1]);
+        for (int sub = 0; sub < tile_x; sub += BX) {
+            const int x = x0 + sub + int(threadIdx.x);
+            if (x < d.lay.nx && y < d.lay.ny) {
+                switch (d.lattice) {
+                case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order); break;
+                case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order); break;
+                default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order); break;
+                }
+            }
+        }
+    }
+}
+
+} // namespace rr
+
+#include "closure.hpp"
+
+namespace rr {
 
 // ------------------------------------------------------------ init kernel
 
@@ -368,6 +434,11 @@ struct lbm_ctx {
     double* partial = nullptr;
     double* partial_host = nullptr;
     int64_t nblk = 0;
+    // learned closure (isothermal D2V37 only)
+    bool closure = false;
+    MlpInfer* cl_frags = nullptr;
+    float* cl_norm = nullptr;
+    unsigned long long* cl_fallbacks = nullptr;
 };
 
 namespace {
@@ -378,6 +449,13 @@ hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pul
     const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
     StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, 1.0 - 1.0 / c->tau, 1.0 / c->tau, c->order };
     dim3 grid(unsigned(bxn * byn)), block(BX, BY);
+    if constexpr (L::id == LBM_D2V37 && COLL == COLL_RR && !TH) {
+        if (pull && c->closure) {
+            ClosureArgs ca{ c->cl_frags, c->cl_norm, 1.0 - 0.5 / c->tau, c->cl_fallbacks };
+            k_stream_collide_closure<S><<<grid, block, 0, c->stream>>>(a, ca);
+            return hipGetLastError();
+        }
+    }
     if (pull)
         k_stream_collide<L, S, COLL, TH, A13P, true><<<grid, block, 0, c->stream>>>(a);
     else
@@ -666,9 +744,483 @@ void lbm_destroy(lbm_ctx* c)
     if (c->fields) (void)hipFree(c->fields);
     if (c->partial) (void)hipFree(c->partial);
     if (c->partial_host) (void)hipHostFree(c->partial_host);
+    if (c->cl_frags) (void)hipFree(c->cl_frags);
+    if (c->cl_norm) (void)hipFree(c->cl_norm);
+    if (c->cl_fallbacks) (void)hipFree(c->cl_fallbacks);
     delete c;
 }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
+
+} // extern "C"
+
+// ================================================================ batches
+
+struct lbm_batch {
+    std::vector<lbm_ctx*> members;
+    std::vector<InstDesc> desc;
+    std::vector<int> begin;
+    int store = ST_F64;
+    hipStream_t stream = nullptr;  // members' stream: every replay goes there
+    hipStream_t capture = nullptr; // private stream used only to record the graph
+    InstDesc* d_desc = nullptr;
+    int* d_begin = nullptr;
+    int total = 0;
+    int tile_x = 64, bpc = 4, num_cu = 256;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+template <class S>
+hipError_t launch_batch(const lbm_batch* b, hipStream_t st, int parity)
+{
+    const int grid = std::min(b->total, b->num_cu * b->bpc);
+    k_batch<S><<<dim3(unsigned(grid)), dim3(BX, BY), 0, st>>>(b->d_desc, b->d_begin, int(b->members.size()),
+                                                               b->total, parity, b->tile_x);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_any(const lbm_batch* b, hipStream_t st, int parity)
+{
+    switch (b->store) {
+    case ST_F32: return launch_batch<StoreF32>(b, st, parity);
+    case ST_BF16: return launch_batch<StoreBF16>(b, st, parity);
+    default: return launch_batch<StoreF64>(b, st, parity);
+    }
+}
+
+void batch_release_graph(lbm_batch* b)
+{
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Rebuilds the work list for the current tile width, uploads it with every
+// member's buffer parity, and records the two-step graph.
+int batch_prepare(lbm_batch* b)
+{
+    const int n = int(b->members.size());
+    b->desc.resize(n);
+    b->begin.assign(n + 1, 0);
+    int64_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        const lbm_ctx* c = b->members[i];
+        InstDesc& d = b->desc[i];
+        d.buf[0] = c->buf[0];
+        d.buf[1] = c->buf[1];
+        d.lay = c->lay;
+        d.lattice = c->lattice;
+        d.bx_blocks = (c->nx + b->tile_x - 1) / b->tile_x;
+        d.flip = c->cur;
+        d.order = c->order;
+        d.keep = 1.0 - 1.0 / c->tau;
+        d.inv_tau = 1.0 / c->tau;
+        b->begin[i] = int(total);
+        total += int64_t(d.bx_blocks) * ((c->ny + BY - 1) / BY);
+    }
+    if (total >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "batch work list too long");
+    b->begin[n] = int(total);
+    b->total = int(total);
+    HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_begin, b->begin.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipStreamSynchronize(b->stream));
+    batch_release_graph(b);
+    HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
+    hipError_t e0 = launch_batch_any(b, b->capture, 0);
+    hipError_t e1 = (e0 == hipSuccess) ? launch_batch_any(b, b->capture, 1) : e0;
+    hipError_t ec = hipStreamEndCapture(b->capture, &b->graph);
+    if (e0 != hipSuccess || e1 != hipSuccess || ec != hipSuccess) {
+        batch_release_graph(b);
+        return fail(LBM_EDEVICE, std::string("batch graph capture: ") +
+                                     hipGetErrorString(e0 != hipSuccess ? e0 : e1 != hipSuccess ? e1 : ec));
+    }
+    HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    return LBM_OK;
+}
+
+// If a member was stepped on its own, refresh the parities on the device.
+int batch_sync_parity(lbm_batch* b)
+{
+    bool stale = false;
+    for (size_t i = 0; i < b->members.size(); ++i)
+        if (b->desc[i].flip != b->members[i]->cur) {
+            b->desc[i].flip = b->members[i]->cur;
+            stale = true;
+        }
+    if (stale) {
+        HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(InstDesc) * b->desc.size(),
+                               hipMemcpyHostToDevice, b->stream));
+        HIP_TRY(hipStreamSynchronize(b->stream));
+    }
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, int blocks_per_cu)
+{
+    if (!out || !ctxs) return fail(LBM_EINVAL, "out or ctxs is NULL");
+    if (n < 1 || n > 4096) return fail(LBM_EINVAL, "batch size must be in [1, 4096]");
+    if (tile_x != 64 && tile_x != 128 && tile_x != 256) return fail(LBM_EINVAL, "tile_x must be 64, 128 or 256");
+    if (blocks_per_cu < 1 || blocks_per_cu > 16) return fail(LBM_EINVAL, "blocks_per_cu must be in [1, 16]");
+    for (int i = 0; i < n; ++i) {
+        const lbm_ctx* c = ctxs[i];
+        if (!c) return fail(LBM_EINVAL, "NULL member");
+        if (c->coll != COLL_RR || c->thermal)
+            return fail(LBM_EINVAL, "batch members must use the isothermal recursive regularization");
+        if (c->store != ctxs[0]->store) return fail(LBM_EINVAL, "batch members must share the storage type");
+        if (c->stream != ctxs[0]->stream) return fail(LBM_EINVAL, "batch members must share the stream");
+        for (int j = 0; j < i; ++j)
+            if (ctxs[j] == c) return fail(LBM_EINVAL, "a context appears twice in the batch");
+    }
+    lbm_batch* b = new (std::nothrow) lbm_batch;
+    if (!b) return fail(LBM_ENOMEM, "batch allocation failed");
+    b->members.assign(ctxs, ctxs + n);
+    b->store = ctxs[0]->store;
+    b->stream = ctxs[0]->stream;
+    b->tile_x = tile_x;
+    b->bpc = blocks_per_cu;
+    int dev = 0, ncu = 0;
+    int e = LBM_OK;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
+        e = fail(LBM_EDEVICE, "cannot query the compute-unit count");
+    b->num_cu = ncu;
+    if (!e && (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
+               hipMalloc(&b->d_desc, sizeof(InstDesc) * n) != hipSuccess ||
+               hipMalloc(&b->d_begin, sizeof(int) * (n + 1)) != hipSuccess))
+        e = fail(LBM_EDEVICE, "batch device allocation failed");
+    if (!e) e = batch_prepare(b);
+    if (e) {
+        lbm_batch_destroy(b);
+        return e;
+    }
+    *out = b;
+    return LBM_OK;
+}
+
+int lbm_batch_step(lbm_batch* b, int nsteps)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
+    int e = batch_sync_parity(b);
+    if (e) return e;
+    for (int s = 0; s + 1 < nsteps; s += 2) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    if (nsteps % 2) {
+        HIP_TRY(launch_batch_any(b, b->stream, 0));
+        for (lbm_ctx* c : b->members) c->cur ^= 1;
+    }
+    for (lbm_ctx* c : b->members) c->steps += nsteps;
+    return LBM_OK;
+}
+
+int lbm_batch_autotune(lbm_batch* b, int steps_per_trial, char* report, int report_len)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (steps_per_trial < 2) return fail(LBM_EINVAL, "steps_per_trial must be >= 2");
+    const int steps = steps_per_trial & ~1;
+    static const int tiles[3] = { 64, 128, 256 };
+    static const int bpcs[4] = { 2, 4, 8, 16 };
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    std::string rep;
+    float best = 1e30f;
+    int best_t = b->tile_x, best_b = b->bpc, err = LBM_OK;
+    for (int t : tiles) {
+        for (int bp : bpcs) {
+            b->tile_x = t;
+            b->bpc = bp;
+            if ((err = batch_prepare(b)) != LBM_OK) break;
+            if ((err = lbm_batch_step(b, 2)) != LBM_OK) break; // warm-up
+            float ms = 0;
+            if (hipEventRecord(e0, b->stream) != hipSuccess || lbm_batch_step(b, steps) != LBM_OK ||
+                hipEventRecord(e1, b->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                err = fail(LBM_EDEVICE, "autotune timing failed");
+                break;
+            }
+            const float per = ms / steps;
+            char line[64];
+            std::snprintf(line, sizeof(line), "%d %d %.5f\n", t, bp, per);
+            rep += line;
+            if (per < best) {
+                best = per;
+                best_t = t;
+                best_b = bp;
+            }
+        }
+        if (err) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    b->tile_x = best_t;
+    b->bpc = best_b;
+    const int e2 = batch_prepare(b);
+    if (report && report_len > 0) {
+        std::snprintf(report, size_t(report_len), "%s", rep.c_str());
+    }
+    return err ? err : e2;
+}
+
+int lbm_batch_config(const lbm_batch* b, int* tile_x, int* blocks_per_cu)
+{
+    if (!b) return fail(LBM_EINVAL, "batch is NULL");
+    if (tile_x) *tile_x = b->tile_x;
+    if (blocks_per_cu) *blocks_per_cu = b->bpc;
+    return LBM_OK;
+}
+
+void lbm_batch_destroy(lbm_batch* b)
+{
+    if (!b) return;
+    if (b->stream || b->capture) (void)hipStreamSynchronize(b->stream);
+    batch_release_graph(b);
+    if (b->d_desc) (void)hipFree(b->d_desc);
+    if (b->d_begin) (void)hipFree(b->d_begin);
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
+
+} // extern "C"
+
+// ================================================================ closure
+
+struct lbm_mlp {
+    float* theta = nullptr; // caller-owned
+    hipStream_t stream = nullptr;
+    int64_t max_batch = 0;
+    int nblocks = 0;
+    int t = 0; // Adam steps taken
+    float *m = nullptr, *v = nullptr, *grad = nullptr, *partial = nullptr, *loss = nullptr;
+    MlpInfer* fi = nullptr;
+    MlpBack* fb = nullptr;
+    std::vector<float> loss_host;
+};
+
+namespace {
+
+template <class L, class S>
+struct SampleOp {
+    static hipError_t run(const lbm_ctx* c, int factor, double sf, double sc, float* x, float* r)
+    {
+        const int64_t nc = int64_t(c->nx / factor) * (c->ny / factor);
+        k_closure_samples<S><<<dim3(unsigned((nc + 255) / 256)), dim3(256), 0, c->stream>>>(
+            c->buf[c->cur], c->lay, factor, sf, sc, x, r);
+        return hipGetLastError();
+    }
+};
+
+hipError_t launch_frags(const float* theta, MlpInfer* fi, MlpBack* fb, hipStream_t st)
+{
+    k_mlp_frags<<<dim3(12), dim3(256), 0, st>>>(theta, fi, fb); // 44 * 64 + 144 threads
+    return hipGetLastError();
+}
+
+} // namespace
+
+extern "C" {
+
+int lbm_closure_samples(lbm_ctx* c, int factor, double tau_coarse, float* x, float* r)
+{
+    if (!c || !x || !r) return fail(LBM_EINVAL, "ctx, x or r is NULL");
+    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal)
+        return fail(LBM_EINVAL, "closure samples need an isothermal RR D2V37 context");
+    if (factor < 1 || factor > 8 || c->nx % factor || c->ny % factor)
+        return fail(LBM_EINVAL, "factor must be in [1, 8] and divide nx and ny");
+    if (!std::isfinite(tau_coarse) || !(tau_coarse > 0.5)) return fail(LBM_ETAU, "tau_coarse must be > 1/2");
+    const double sf = (1.0 - 0.5 / c->tau) / (1.0 - 1.0 / c->tau);
+    const double sc = 1.0 - 0.5 / tau_coarse;
+    if (!std::isfinite(sf)) return fail(LBM_ETAU, "fine tau must differ from 1");
+    // fine D2V37 is the only lattice: dispatch on the storage type alone
+    hipError_t he = hipSuccess;
+    switch (c->store) {
+    case ST_F32: he = SampleOp<D2V37, StoreF32>::run(c, factor, sf, sc, x, r); break;
+    case ST_BF16: he = SampleOp<D2V37, StoreBF16>::run(c, factor, sf, sc, x, r); break;
+    default: he = SampleOp<D2V37, StoreF64>::run(c, factor, sf, sc, x, r); break;
+    }
+    if (he != hipSuccess) return fail(LBM_EDEVICE, std::string("samples launch: ") + hipGetErrorString(he));
+    return LBM_OK;
+}
+
+int lbm_mlp_stats(const float* x, const float* r, int64_t n, float* norm, void* stream)
+{
+    if (!x || !r || !norm || n < 1) return fail(LBM_EINVAL, "x, r, norm or n invalid");
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int nb = int(std::min<int64_t>(256, (n + 255) / 256));
+    double* part = nullptr;
+    HIP_TRY(hipMalloc(&part, sizeof(double) * 4 * STAT_COLS * nb));
+    k_col_stats<<<dim3(nb), dim3(256), 0, st>>>(x, r, n, part);
+    hipError_t he = hipGetLastError();
+    std::vector<double> hp(size_t(4 * STAT_COLS * nb));
+    if (he == hipSuccess) he = hipMemcpyAsync(hp.data(), part, sizeof(double) * hp.size(), hipMemcpyDeviceToHost, st);
+    if (he == hipSuccess) he = hipStreamSynchronize(st);
+    (void)hipFree(part);
+    if (he != hipSuccess) return fail(LBM_EDEVICE, std::string("stats: ") + hipGetErrorString(he));
+    std::vector<float> nv(NORM_N, 0.0f);
+    for (int i = 0; i < 8; ++i) {
+        nv[NORM_IN_STD + i] = 1.0f;
+        nv[NORM_IN_LO + i] = -1e30f;
+        nv[NORM_IN_HI + i] = 1e30f;
+    }
+    for (int i = 0; i < 16; ++i) {
+        nv[NORM_OUT_STD + i] = 1.0f;
+        nv[NORM_OUT_LO + i] = -1e30f;
+        nv[NORM_OUT_HI + i] = 1e30f;
+    }
+    for (int col = 0; col < STAT_COLS; ++col) {
+        double s1 = 0, s2 = 0, lo = 1e300, hi = -1e300;
+        for (int b = 0; b < nb; ++b) {
+            const double* p = hp.data() + size_t(b) * 4 * STAT_COLS;
+            s1 += p[col];
+            s2 += p[STAT_COLS + col];
+            lo = std::min(lo, p[2 * STAT_COLS + col]);
+            hi = std::max(hi, p[3 * STAT_COLS + col]);
+        }
+        const double mean = s1 / double(n);
+        const double var = std::max(0.0, s2 / double(n) - mean * mean);
+        const double sd = var > 0 ? std::sqrt(var) : 1.0;
+        const bool in = col < 7;
+        const int j = in ? col : col - 7;
+        nv[(in ? NORM_IN_MEAN : NORM_OUT_MEAN) + j] = float(mean);
+        nv[(in ? NORM_IN_STD : NORM_OUT_STD) + j] = float(sd);
+        nv[(in ? NORM_IN_LO : NORM_OUT_LO) + j] = float((lo - mean) / sd);
+        nv[(in ? NORM_IN_HI : NORM_OUT_HI) + j] = float((hi - mean) / sd);
+    }
+    HIP_TRY(hipMemcpyAsync(norm, nv.data(), sizeof(float) * NORM_N, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return LBM_OK;
+}
+
+int lbm_mlp_normalize(float* x, float* r, int64_t n, const float* norm, void* stream)
+{
+    if (!x || !r || !norm || n < 0) return fail(LBM_EINVAL, "x, r, norm or n invalid");
+    if (n == 0) return LBM_OK;
+    k_normalize<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, static_cast<hipStream_t>(stream)>>>(x, r, n, norm);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+void lbm_mlp_destroy(lbm_mlp* m);
+
+int lbm_mlp_create(lbm_mlp** out, float* theta, int64_t max_batch, void* stream)
+{
+    if (!out || !theta || max_batch < 1) return fail(LBM_EINVAL, "out, theta or max_batch invalid");
+    lbm_mlp* m = new (std::nothrow) lbm_mlp;
+    if (!m) return fail(LBM_ENOMEM, "mlp allocation failed");
+    m->theta = theta;
+    m->stream = static_cast<hipStream_t>(stream);
+    m->max_batch = max_batch;
+    m->nblocks = int(std::min<int64_t>(128, (max_batch + 63) / 64));
+    const int nw = 4 * m->nblocks;
+    bool ok = hipMalloc(&m->m, sizeof(float) * MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&m->v, sizeof(float) * MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&m->grad, sizeof(float) * MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&m->partial, sizeof(float) * MLP_NPARAM * nw) == hipSuccess &&
+              hipMalloc(&m->loss, sizeof(float) * nw) == hipSuccess &&
+              hipMalloc(&m->fi, sizeof(MlpInfer)) == hipSuccess && hipMalloc(&m->fb, sizeof(MlpBack)) == hipSuccess;
+    ok = ok && hipMemsetAsync(m->m, 0, sizeof(float) * MLP_NPARAM, m->stream) == hipSuccess &&
+         hipMemsetAsync(m->v, 0, sizeof(float) * MLP_NPARAM, m->stream) == hipSuccess;
+    if (!ok) {
+        lbm_mlp_destroy(m);
+        return fail(LBM_EDEVICE, "mlp device allocation failed");
+    }
+    m->loss_host.resize(size_t(nw));
+    *out = m;
+    return LBM_OK;
+}
+
+int lbm_mlp_forward(lbm_mlp* m, const float* x, int64_t n, float* y)
+{
+    if (!m || !x || !y || n < 0) return fail(LBM_EINVAL, "mlp, x, y or n invalid");
+    if (n == 0) return LBM_OK;
+    HIP_TRY(launch_frags(m->theta, m->fi, m->fb, m->stream));
+    const int64_t blocks = (n + 63) / 64; // 16 samples per wave, 4 waves per block
+    k_mlp_forward<<<dim3(unsigned(blocks)), dim3(256), 0, m->stream>>>(m->fi, x, n, y);
+    HIP_TRY(hipGetLastError());
+    return LBM_OK;
+}
+
+int lbm_mlp_step(lbm_mlp* m, const float* x, const float* t, const int* idx, int64_t batch, float lr, float* grad,
+                 double* loss)
+{
+    if (!m || !x || !t) return fail(LBM_EINVAL, "mlp, x or t is NULL");
+    if (batch < 1 || batch > m->max_batch) return fail(LBM_EINVAL, "batch must be in [1, max_batch]");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(LBM_EINVAL, "lr must be finite and >= 0");
+    HIP_TRY(launch_frags(m->theta, m->fi, m->fb, m->stream));
+    const int nb = int(std::min<int64_t>(m->nblocks, (batch + 63) / 64));
+    GradArgs ga{ m->fi, m->fb, x, t, idx, batch, float(2.0 / (double(batch) * MLP_OUT)), m->partial, m->loss };
+    k_mlp_grad<<<dim3(unsigned(nb)), dim3(256), 0, m->stream>>>(ga);
+    HIP_TRY(hipGetLastError());
+    float bc1 = 1.0f, bc2 = 1.0f;
+    if (lr > 0.0f) {
+        ++m->t;
+        bc1 = float(1.0 - std::pow(0.9, m->t));
+        bc2 = float(1.0 - std::pow(0.999, m->t));
+    }
+    k_mlp_reduce_adam<<<dim3((MLP_NPARAM + 255) / 256), dim3(256), 0, m->stream>>>(
+        m->partial, 4 * nb, grad ? grad : m->grad, m->theta, m->m, m->v, lr, bc1, bc2);
+    HIP_TRY(hipGetLastError());
+    if (loss) {
+        HIP_TRY(hipMemcpyAsync(m->loss_host.data(), m->loss, sizeof(float) * 4 * nb, hipMemcpyDeviceToHost, m->stream));
+        HIP_TRY(hipStreamSynchronize(m->stream));
+        double sum = 0;
+        for (int w = 0; w < 4 * nb; ++w) sum += m->loss_host[size_t(w)];
+        *loss = sum / (double(batch) * MLP_OUT);
+    }
+    return LBM_OK;
+}
+
+void lbm_mlp_destroy(lbm_mlp* m)
+{
+    if (!m) return;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    for (void* p : { (void*)m->m, (void*)m->v, (void*)m->grad, (void*)m->partial, (void*)m->loss, (void*)m->fi,
+                     (void*)m->fb })
+        if (p) (void)hipFree(p);
+    delete m;
+}
+
+int lbm_closure_set(lbm_ctx* c, const float* theta, const float* norm)
+{
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (!theta) {
+        c->closure = false;
+        return LBM_OK;
+    }
+    if (!norm) return fail(LBM_EINVAL, "norm is NULL");
+    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal)
+        return fail(LBM_EINVAL, "the closure needs an isothermal RR D2V37 context");
+    if (!c->cl_frags) {
+        HIP_TRY(hipMalloc(&c->cl_frags, sizeof(MlpInfer)));
+        HIP_TRY(hipMalloc(&c->cl_norm, sizeof(float) * NORM_N));
+        HIP_TRY(hipMalloc(&c->cl_fallbacks, sizeof(unsigned long long)));
+    }
+    HIP_TRY(launch_frags(theta, c->cl_frags, nullptr, c->stream));
+    HIP_TRY(hipMemcpyAsync(c->cl_norm, norm, sizeof(float) * NORM_N, hipMemcpyDeviceToDevice, c->stream));
+    HIP_TRY(hipMemsetAsync(c->cl_fallbacks, 0, sizeof(unsigned long long), c->stream));
+    c->closure = true;
+    return LBM_OK;
+}
+
+int lbm_closure_fallbacks(lbm_ctx* c, int64_t* count)
+{
+    if (!c || !count) return fail(LBM_EINVAL, "ctx or count is NULL");
+    if (!c->cl_fallbacks) {
+        *count = 0;
+        return LBM_OK;
+    }
+    unsigned long long v = 0;
+    HIP_TRY(hipMemcpyAsync(&v, c->cl_fallbacks, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    *count = int64_t(v);
+    return LBM_OK;
+}
 
 } // extern "C"

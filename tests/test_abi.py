@@ -98,3 +98,15 @@ def test_null_context_is_rejected():
             fn()
     b.lbm_destroy(None)
     assert b.lbm_step_count(None) == -1
+
+
+def test_batch_rejects_invalid_arguments():
+    for args in (([], 64, 4), ([None], 64, 4), ([None], 32, 4), ([None], 64, 0), ([None], 64, 17)):
+        with pytest.raises(b.LbmError) as e:
+            b.lbm_batch_create(*args)
+        assert e.value.code == b.LBM_EINVAL
+    for fn in (lambda: b.lbm_batch_step(None, 1), lambda: b.lbm_batch_config(None),
+               lambda: b.lbm_batch_autotune(None, 4)):
+        with pytest.raises(b.LbmError):
+            fn()
+    b.lbm_batch_destroy(None)

@@ -1,0 +1,114 @@
+"""Batched persistent stepping (one graph-replayed launch for many members)
+against the oracle (FP64 members) and against members stepped on their own
+(reduced precision: same arithmetic, so the same values)."""
+import numpy as np
+import pytest
+
+from paper_1704_04413_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = [("D2Q9", 70, 45), ("D2V17", 64, 33), ("D2V37", 37, 29), ("D2Q9", 128, 128), ("D2V37", 3, 5),
+           ("D2V17", 200, 9)]
+
+
+@pytest.fixture(scope="module")
+def b():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_04413_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def make(orc, b, name, nx, ny, seed, flags=0):
+    lat = orc.lattice(name)
+    u0, tau = wl.shear_layer_params(lat.cs2, max(nx, ny), 1e4 * (1 + seed))
+    rho, ux, uy = wl.shear_layer_fields(nx, ny, u0)
+    noise = wl.uniform_noise(seed, lat.Q, ny, nx)
+    sim = b.Simulation(name, nx, ny, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, flags=flags)
+    f0 = orc.init_populations(lat, rho, ux, uy, None, noise, 1e-8)
+    return sim, lat, tau, f0
+
+
+def check(got, want, atol):
+    err = float(np.abs(np.asarray(got) - np.asarray(want)).max())
+    print(f"[parity] max diff {err:.3e} (bound {atol:.0e})", flush=True)
+    assert err <= atol, err
+
+
+@pytest.mark.parametrize("tile_x,bpc", [(64, 4), (128, 2), (256, 16)])
+def test_batch_fp64_against_oracle(orc, b, tile_x, bpc):
+    print(f"[case] batch fp64 tile_x={tile_x} bpc={bpc}", flush=True)
+    made = [make(orc, b, name, nx, ny, seed) for seed, (name, nx, ny) in enumerate(MEMBERS)]
+    batch = b.lbm_batch_create([m[0].ctx for m in made], tile_x, bpc)
+    b.lbm_batch_step(batch, 4)
+    made[0][0].step(1)        # one member moves on its own in between
+    b.lbm_batch_step(batch, 3)
+    b.lbm_batch_destroy(batch)
+    for i, (sim, lat, tau, f0) in enumerate(made):
+        n = 8 if i == 0 else 7
+        assert sim.steps == n
+        got = sim.populations().cpu().numpy()
+        sim.close()
+        want = orc.collide(lat, orc.step(lat, f0, tau, n), tau)
+        check(got, want, 1e-12)
+
+
+@pytest.mark.parametrize("storage", ["fp32", "bf16"])
+def test_batch_matches_individual_steps(orc, b, storage):
+    print(f"[case] batch {storage} vs individual", flush=True)
+    flags = b.LBM_STORE_FP32 if storage == "fp32" else b.LBM_STORE_BF16
+    batched = [make(orc, b, name, nx, ny, seed, flags)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
+    single = [make(orc, b, name, nx, ny, seed, flags)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
+    batch = b.lbm_batch_create([s.ctx for s in batched], 128, 4)
+    b.lbm_batch_step(batch, 11)
+    b.lbm_batch_destroy(batch)
+    for s in single:
+        s.step(11)
+    for x, y in zip(batched, single):
+        gx, gy = x.populations().cpu().numpy(), y.populations().cpu().numpy()
+        x.close()
+        y.close()
+        # identical arithmetic; allow one rounding of the stored value
+        check(gx, gy, 1e-7 if storage == "fp32" else 2e-3)
+
+
+def test_batch_autotune(orc, b):
+    print("[case] batch autotune", flush=True)
+    made = [make(orc, b, name, nx, ny, seed, b.LBM_STORE_FP32)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
+    ref = [make(orc, b, name, nx, ny, seed, b.LBM_STORE_FP32)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
+    batch = b.lbm_batch_create([s.ctx for s in made], 64, 4)
+    rows = b.lbm_batch_autotune(batch, 4)
+    assert len(rows) == 12 and all(ms > 0 for _, _, ms in rows)
+    best = min(rows, key=lambda r: r[2])
+    assert b.lbm_batch_config(batch) == (best[0], best[1])
+    b.lbm_batch_step(batch, 3)
+    b.lbm_batch_destroy(batch)
+    n = made[0].steps
+    assert n == 12 * 6 + 3
+    for x, y in zip(made, ref):
+        y.step(n)
+        check(x.populations().cpu().numpy(), y.populations().cpu().numpy(), 1e-7)
+        x.close()
+        y.close()
+
+
+def test_batch_rejects_mixed_members(orc, b):
+    s1 = make(orc, b, "D2Q9", 16, 16, 0)[0]
+    s2 = make(orc, b, "D2Q9", 16, 16, 1, b.LBM_STORE_FP32)[0]
+    with pytest.raises(b.LbmError):
+        b.lbm_batch_create([s1.ctx, s2.ctx])
+    with pytest.raises(b.LbmError):
+        b.lbm_batch_create([s1.ctx, s1.ctx])
+    lat = orc.lattice("D2V37")
+    rho, ux, uy, th = wl.sod_fields(16, 4)
+    s3 = b.Simulation("D2V37", 16, 4, 0.8, rho, ux, uy, theta=th, flags=b.LBM_THERMAL)
+    with pytest.raises(b.LbmError):
+        b.lbm_batch_create([s3.ctx])
+    for s in (s1, s2, s3):
+        s.close()
+    assert lat.Q == 37

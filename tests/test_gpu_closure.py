@@ -1,0 +1,290 @@
+"""Learned closure on the GPU against the CPU references of oracle/ and
+oracle/mlp.py: the matrix-core network forward pass, its gradient, Adam, the
+fused closure collision (component order, range fallback, conservation), the
+fine-to-coarse training samples and the normalisation statistics.
+
+Tolerances: the GPU rounds inputs, weights and hidden activations to
+bfloat16 exactly where the reference emulates it, and accumulates in float32
+instead of float64; a hidden activation landing on the other side of a
+bfloat16 rounding boundary moves an output by ~2^-8 of one of its 64 terms,
+so outputs of order 1 agree to ~1e-2 and gradients (which also round the
+back-propagated errors to bfloat16) to a few percent in norm."""
+import numpy as np
+import pytest
+
+from oracle import mlp
+from paper_1704_04413_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_04413_amd import binding
+
+    binding.lib()
+    return binding, torch
+
+
+def dev(torch, a, dtype=None):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype).cuda()
+
+
+def random_theta(seed, bias_scale=0.1):
+    rng = np.random.default_rng(seed)
+    th = mlp.init_params(seed)
+    p = mlp.unpack(th)
+    p["b1"] = rng.normal(0, bias_scale, mlp.NH)
+    p["b2"] = rng.normal(0, bias_scale, mlp.NH)
+    p["b3"][:mlp.NOUT] = rng.normal(0, bias_scale, mlp.NOUT)
+    return mlp.pack(p).astype(np.float32).astype(np.float64)
+
+
+def inputs(seed, n):
+    X = np.random.default_rng(seed).normal(size=(n, mlp.NIN)).astype(np.float32).astype(np.float64)
+    X[:, -1] = 1.0
+    return X
+
+
+def test_mlp_forward_matches_reference(env):
+    b, torch = env
+    print("[case] mlp forward", flush=True)
+    th = random_theta(1)
+    X = inputs(2, 1000)  # not a multiple of 16: a ragged last group
+    theta = dev(torch, th, torch.float32)
+    m = b.lbm_mlp_create(theta, 1024)
+    y = torch.zeros((1000, 16), dtype=torch.float32, device="cuda")
+    b.lbm_mlp_forward(m, dev(torch, X, torch.float32), 1000, y)
+    b.lbm_mlp_destroy(m)
+    got = y.cpu().numpy().astype(np.float64)
+    want, _ = mlp.forward(th, X, emulate_bf16=True)
+    err = np.abs(got[:, :9] - want).max()
+    print(f"[parity] mlp forward max |dy| {err:.3e}, |y| max {np.abs(want).max():.2f}", flush=True)
+    assert err <= 2e-2
+    assert np.all(got[:, 9:] == 0)
+
+
+@pytest.mark.parametrize("use_idx", [False, True])
+def test_mlp_gradient_matches_reference(env, use_idx):
+    b, torch = env
+    print(f"[case] mlp gradient idx={use_idx}", flush=True)
+    th = random_theta(3)
+    n = 777
+    X = inputs(4, n)
+    T = np.random.default_rng(5).normal(size=(n, mlp.NOUT))
+    T16 = np.zeros((n, 16))
+    T16[:, :9] = T
+    if use_idx:
+        idx = np.random.default_rng(6).permutation(n)[:500].astype(np.int32)
+        Xs, Ts = X[idx], T[idx]
+    else:
+        idx, Xs, Ts = None, X, T
+    batch = len(Xs)
+    theta = dev(torch, th, torch.float32)
+    m = b.lbm_mlp_create(theta, 1024)
+    grad = torch.zeros(mlp.NPARAM, dtype=torch.float32, device="cuda")
+    loss = b.lbm_mlp_step(m, dev(torch, X, torch.float32), dev(torch, T16, torch.float32),
+                          None if idx is None else dev(torch, idx), batch, 0.0, grad, want_loss=True)
+    b.lbm_mlp_destroy(m)
+    assert np.array_equal(theta.cpu().numpy().astype(np.float64), th)  # lr = 0 leaves theta alone
+    want_loss, want = mlp.loss_and_grad(th, Xs, Ts, emulate_bf16=True)
+    got = grad.cpu().numpy().astype(np.float64)
+    print(f"[parity] loss {loss:.6f} vs {want_loss:.6f}", flush=True)
+    assert loss == pytest.approx(want_loss, rel=1e-2)
+    o = 0
+    for name, shape in mlp.SHAPES:
+        k = int(np.prod(shape))
+        gg, ww = got[o:o + k], want[o:o + k]
+        rel = np.linalg.norm(gg - ww) / max(np.linalg.norm(ww), 1e-30)
+        print(f"[parity] grad {name}: rel err {rel:.3e}", flush=True)
+        assert rel <= 5e-2, name
+        o += k
+
+
+def test_adam_step_and_training(env):
+    b, torch = env
+    print("[case] adam + training", flush=True)
+    th = random_theta(7)
+    teacher = random_theta(8)
+    n = 4096
+    X = inputs(9, n)
+    T, _ = mlp.forward(teacher, X, emulate_bf16=False)
+    T16 = np.zeros((n, 16))
+    T16[:, :9] = T
+    theta = dev(torch, th, torch.float32)
+    m = b.lbm_mlp_create(theta, n)
+    xg, tg = dev(torch, X, torch.float32), dev(torch, T16, torch.float32)
+    grad = torch.zeros(mlp.NPARAM, dtype=torch.float32, device="cuda")
+    l0 = b.lbm_mlp_step(m, xg, tg, None, n, 1e-3, grad, want_loss=True)
+    g = grad.cpu().numpy().astype(np.float64)
+    want, _, _ = mlp.adam(th, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    got = theta.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-7)
+    for _ in range(300):
+        loss = b.lbm_mlp_step(m, xg, tg, None, n, 2e-3, None, want_loss=False)
+    loss = b.lbm_mlp_step(m, xg, tg, None, n, 0.0, None, want_loss=True)
+    b.lbm_mlp_destroy(m)
+    print(f"[train] loss {l0:.4e} -> {loss:.4e}", flush=True)
+    assert loss < 0.2 * l0
+
+
+def norm_block(in_mean, in_std, out_mean, out_std, in_lo=-1e30, in_hi=1e30, out_lo=-1e30, out_hi=1e30):
+    nv = np.zeros(96)
+    nv[0:7], nv[8:15] = in_mean, in_std
+    nv[7], nv[15] = 0.0, 1.0
+    nv[16:24], nv[24:32] = in_lo, in_hi
+    nv[32:41], nv[48:57] = out_mean, out_std
+    nv[57:64] = 1.0
+    nv[64:80], nv[80:96] = out_lo, out_hi
+    return nv
+
+
+def oracle_closure_run(orc, lat, f0, tau, steps, th, nv):
+    """Plain RR at initialization, then `steps` closure steps; returns the
+    post-collision state (what the library keeps)."""
+    f = orc.stream(lat, orc.collide(lat, f0, tau))
+    shape = f.shape
+    for s in range(steps):
+        feat, _ = orc.closure_inputs(lat, f, tau)
+        z = (feat.T - nv[0:7]) / nv[8:15]
+        inr = np.all((z >= nv[16:23]) & (z <= nv[24:31]), axis=1)
+        X = np.concatenate([z, np.ones((z.shape[0], 1))], axis=1)
+        y, _ = mlp.forward(th, X, emulate_bf16=True)
+        outr = np.all((y >= nv[64:73]) & (y <= nv[80:89]), axis=1)
+        r = y * nv[48:57] + nv[32:41]
+        r[~(inr & outr)] = 0.0
+        g = orc.collide_closure(lat, f, tau, r.T).reshape(shape)
+        if s == steps - 1:
+            return g, int(np.sum(~(inr & outr)))
+        f = orc.stream(lat, g)
+
+
+def closure_case(orc, b, torch, th, nv, steps, nx=70, ny=45, flags=0):
+    lat = orc.lattice("D2V37")
+    u0, tau = wl.shear_layer_params(lat.cs2, max(nx, ny), 3e4)
+    rho, ux, uy = wl.shear_layer_fields(nx, ny, u0)
+    noise = wl.uniform_noise(3, lat.Q, ny, nx)
+    sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, flags=flags)
+    b.lbm_closure_set(sim.ctx, dev(torch, th, torch.float32), dev(torch, nv, torch.float32))
+    s0 = sim.moments(vorticity=False)["sums"]
+    sim.step(steps)
+    got = sim.populations().cpu().numpy()
+    s1 = sim.moments(vorticity=False)["sums"]
+    fb = b.lbm_closure_fallbacks(sim.ctx)
+    sim.close()
+    f0 = orc.init_populations(lat, rho, ux, uy, None, noise, 1e-8)
+    return lat, tau, f0, got, s0, s1, fb
+
+
+def test_closure_collision_component_order(orc, env):
+    """Network with zero weights: every output is its bias, so the residual of
+    each of the 9 components is known exactly on both sides."""
+    b, torch = env
+    print("[case] closure bias-only network", flush=True)
+    p = {k: np.zeros(s) for k, s in mlp.SHAPES}
+    p["b3"][:9] = np.arange(1, 10) * 0.25 - 1.0
+    th = mlp.pack(p)
+    # out_std a power of two and zero mean: the float32 residual is exact
+    nv = norm_block(np.zeros(7), np.ones(7), np.zeros(9), np.full(9, 2.0 ** -20))
+    lat, tau, f0, got, s0, s1, fb = closure_case(orc, b, torch, th, nv, 3)
+    want, nfb = oracle_closure_run(orc, lat, f0, tau, 3, th, nv)
+    err = np.abs(got - want).max()
+    print(f"[parity] closure (bias-only) max |df| {err:.3e}", flush=True)
+    assert err <= 1e-12
+    assert fb == 0 and nfb == 0
+    plain = orc.collide(lat, orc.step(lat, f0, tau, 3), tau)
+    assert np.abs(got - plain).max() > 1e-9  # the residual did act
+
+
+def test_closure_collision_full_network(orc, env):
+    b, torch = env
+    print("[case] closure random network", flush=True)
+    th = random_theta(11)
+    lat = orc.lattice("D2V37")
+    # normalise the inputs by rough scales of the flow so z is of order 1
+    nv = norm_block(np.zeros(7), np.array([1e-3, 0.05, 0.01, 1e-3, 1e-5, 1e-5, 1e-5]), np.zeros(9),
+                    np.full(9, 1e-7))
+    lat, tau, f0, got, s0, s1, fb = closure_case(orc, b, torch, th, nv, 2)
+    want, _ = oracle_closure_run(orc, lat, f0, tau, 2, th, nv)
+    plain = orc.collide(lat, orc.step(lat, f0, tau, 2), tau)
+    err, eff = np.abs(got - want).max(), np.abs(want - plain).max()
+    print(f"[parity] closure (random net) max |df| {err:.3e}; closure effect {eff:.3e}", flush=True)
+    # outputs agree to ~1e-2 (bfloat16), so the closure's effect is reproduced to ~1e-2 of itself
+    assert err <= 3e-2 * eff + 1e-12
+    # mass and momentum are untouched whatever the network says
+    assert abs(s1[0] - s0[0]) <= 1e-13 * s0[0]
+    assert abs(s1[1] - s0[1]) <= 1e-13 * np.abs(s0[0]) and abs(s1[2] - s0[2]) <= 1e-13 * np.abs(s0[0])
+
+
+def test_closure_fallback_is_plain_rr(orc, env):
+    b, torch = env
+    print("[case] closure fallback", flush=True)
+    th = random_theta(12)
+    nv = norm_block(np.zeros(7), np.ones(7), np.zeros(9), np.ones(9), in_hi=-1.0)  # every input out of range
+    lat, tau, f0, got, s0, s1, fb = closure_case(orc, b, torch, th, nv, 4, nx=40, ny=36)
+    plain = orc.collide(lat, orc.step(lat, f0, tau, 4), tau)
+    err = np.abs(got - plain).max()
+    print(f"[parity] fallback vs plain RR {err:.3e}, fallbacks {fb}", flush=True)
+    assert err <= 1e-12
+    assert fb == 4 * 40 * 36
+
+
+def test_closure_samples_and_stats(orc, env):
+    b, torch = env
+    print("[case] closure samples", flush=True)
+    lat = orc.lattice("D2V37")
+    n, factor, steps = 64, 4, 6
+    u0, tau_f = wl.shear_layer_params(lat.cs2, n, 3e4)
+    _, tau_c = wl.shear_layer_params(lat.cs2, n // factor, 3e4)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    sim = b.Simulation("D2V37", n, n, tau_f, rho, ux, uy)
+    sim.step(steps)
+    nc = (n // factor) ** 2
+    x = torch.zeros((nc, 8), dtype=torch.float32, device="cuda")
+    r = torch.zeros((nc, 16), dtype=torch.float32, device="cuda")
+    b.lbm_closure_samples(sim.ctx, factor, tau_c, x, r)
+    g = sim.populations().cpu().numpy()
+    sim.close()
+    # reference: projections of the fine post-collision populations, block averages
+    a = orc.noneq_projected(lat, g).reshape(12, n, n)
+    sf = (1 - 0.5 / tau_f) / (1 - 1 / tau_f)
+    rr_, vx, vy, _ = orc.moments(lat, g)
+    blk = lambda q: q.reshape(n // factor, factor, n // factor, factor).mean(axis=(1, 3)).reshape(-1)
+    rc = blk(rr_)
+    uxc, uyc = blk(rr_ * vx) / rc, blk(rr_ * vy) / rc
+    ah = np.stack([blk(sf * a[j]) for j in range(12)])
+    xx, xy, yy = ah[0], ah[1], ah[2]
+    rec = np.stack([3 * uxc * xx, 2 * uxc * xy + uyc * xx, 2 * uyc * xy + uxc * yy, 3 * uyc * yy,
+                    6 * uxc ** 2 * xx, 3 * (uxc ** 2 * xy + uxc * uyc * xx),
+                    uyc ** 2 * xx + uxc ** 2 * yy + 4 * uxc * uyc * xy,
+                    3 * (uyc ** 2 * xy + uxc * uyc * yy), 6 * uyc ** 2 * yy])
+    want_r = (ah[3:] - rec).T
+    want_x = np.stack([rc - 1, uxc, uyc, (xx + yy) / (1 - 0.5 / tau_c) / (2 * rc * lat.cs2), xx, xy, yy]).T
+    gx, gr = x.cpu().numpy().astype(np.float64), r.cpu().numpy().astype(np.float64)
+    scale_x = np.abs(want_x).max(axis=0)
+    # the residual is a difference of two float64 quantities that nearly
+    # cancel: measure its error against the size of those terms
+    scale_r = np.maximum(np.abs(ah[3:]).max(axis=1), np.abs(rec).max(axis=1))
+    ex = (np.abs(gx[:, :7] - want_x) / scale_x).max()
+    er = (np.abs(gr[:, :9] - want_r) / scale_r).max()
+    print(f"[parity] samples: inputs rel {ex:.3e}, residuals rel {er:.3e}", flush=True)
+    assert ex <= 1e-6 and er <= 1e-5  # float32 outputs of float64 arithmetic
+    assert np.all(gx[:, 7] == 1) and np.all(gr[:, 9:] == 0)
+    # statistics and normalisation
+    norm = torch.zeros(96, dtype=torch.float32, device="cuda")
+    b.lbm_mlp_stats(x, r, nc, norm)
+    nvh = norm.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(nvh[0:7], gx[:, :7].mean(0), rtol=1e-5, atol=1e-12)
+    np.testing.assert_allclose(nvh[8:15], gx[:, :7].std(0), rtol=1e-4)
+    np.testing.assert_allclose(nvh[32:41], gr[:, :9].mean(0), rtol=1e-5, atol=1e-14)
+    np.testing.assert_allclose(nvh[48:57], gr[:, :9].std(0), rtol=1e-4)
+    b.lbm_mlp_normalize(x, r, nc, norm)
+    zx = x.cpu().numpy().astype(np.float64)
+    np.testing.assert_allclose(zx[:, :7].mean(0), 0, atol=1e-4)
+    np.testing.assert_allclose(zx[:, :7].std(0), 1, rtol=1e-3)
+    np.testing.assert_allclose(zx[:, :7].min(0), nvh[16:23], rtol=1e-4, atol=1e-4)
+    np.testing.assert_allclose(zx[:, :7].max(0), nvh[24:31], rtol=1e-4, atol=1e-4)
