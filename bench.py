@@ -206,6 +206,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--closure", choices=["full", "small", "none"], default="none",
+                    help="learned-closure study: D2V37 256^2 coarse / 1024^2 fine (full) or 64^2 / 256^2")
     ap.add_argument("--copy-only", action="store_true", help="only run 1 GiB device copies (counter calibration)")
     args = ap.parse_args()
 
@@ -290,6 +292,14 @@ def main():
         out["copy_GBs"] = round(copy_bandwidth(torch), 1)
     if not args.no_batch:
         out["batched"] = batched_suite(torch, b, wl)
+    if args.closure != "none":
+        from paper_1704_04413_amd import closure as cl
+
+        if args.closure == "full":
+            out["closure"] = cl.experiment(torch)
+        else:
+            out["closure"] = cl.experiment(torch, range(6), range(6, 8), 64, 4, 3e4, tuple(range(50, 401, 50)),
+                                           1500, 8192)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.lattice, args.n, args.cpu_steps)
     print(json.dumps(out), flush=True)
