@@ -52,19 +52,24 @@ __device__ __forceinline__ short f2bf(float v)
 
 __device__ __forceinline__ float bf2f(short b) { return __uint_as_float(uint32_t(uint16_t(b)) << 16); }
 
-// tanh-form GELU and its derivative (Hendrycks & Gimpel), tanh(u) = 1 - 2/(e^2u + 1)
-__device__ __forceinline__ float gelu_f(float z)
+// tanh-form GELU and its derivative (Hendrycks & Gimpel), written with
+// 0.5 (1 + tanh(u)) = 1 / (1 + e^(-2u)) and the hardware exp2 and reciprocal
+// (the results are rounded to bfloat16 or feed bfloat16 products).
+__device__ __forceinline__ float sigmoid2u(float z)
 {
-    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * u) + 1.0f);
-    return 0.5f * z * (1.0f + t);
+    // e^(-2u) = 2^(-2 log2(e) c (z + a z^3)), c = sqrt(2/pi), a = 0.044715
+    const float k = -2.0f * 1.4426950408889634f * 0.7978845608028654f;
+    const float e = __builtin_amdgcn_exp2f(k * z * (1.0f + 0.044715f * z * z));
+    return __builtin_amdgcn_rcpf(1.0f + e);
 }
+
+__device__ __forceinline__ float gelu_f(float z) { return z * sigmoid2u(z); }
 
 __device__ __forceinline__ float gelu_prime_f(float z)
 {
-    const float u = 0.7978845608028654f * (z + 0.044715f * z * z * z);
-    const float t = 1.0f - 2.0f / (__expf(2.0f * u) + 1.0f);
-    return 0.5f * (1.0f + t) + 0.5f * z * (1.0f - t * t) * 0.7978845608028654f * (1.0f + 0.134145f * z * z);
+    const float s = sigmoid2u(z);
+    // d/dz [z s(v)] = s + z s (1 - s) v',  v = 2c (z + a z^3)
+    return s + z * s * (1.0f - s) * (2.0f * 0.7978845608028654f) * (1.0f + 0.134145f * z * z);
 }
 
 __device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c)
