@@ -60,6 +60,112 @@ def read_traffic(name: str):
         return None
 
 
+# ------------------------------------------------------------------ profiles
+# Turning rocprofv3 output into the summaries under profiles/ (runs on any
+# host, after the profiled runs on the GPU).
+
+PROFILE_RUN = "python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline --no-sweep --no-batch --no-studies --closure none"
+
+
+def _pmc_per_kernel(csv_dir: str, counter: str):
+    """{kernel name: [values per dispatch]} of one rocprofv3 --pmc run (csv)."""
+    import csv
+
+    out = {}
+    for path in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] == counter:
+                    out.setdefault(row["Kernel_Name"], []).append(float(row["Counter_Value"]))
+    return out
+
+
+def _busiest(d):
+    name = max(d, key=lambda k: len(d[k]))
+    return name, float(np.mean(d[name]))
+
+
+def summarize_pmc(args) -> str:
+    """Writes profiles/<lattice>_<storage>_<n>_traffic.txt from the four PMC runs
+    (step FETCH_SIZE, step WRITE_SIZE, copy FETCH_SIZE, copy WRITE_SIZE)."""
+    fetch_dir, write_dir, cfetch_dir, cwrite_dir = args.summarize_pmc
+    kname, fetch = _busiest(_pmc_per_kernel(fetch_dir, "FETCH_SIZE"))
+    kname2, write = _busiest(_pmc_per_kernel(write_dir, "WRITE_SIZE"))
+    assert kname == kname2, (kname, kname2)
+    ndisp = len(_pmc_per_kernel(fetch_dir, "FETCH_SIZE")[kname])
+    cname, cfetch = _busiest(_pmc_per_kernel(cfetch_dir, "FETCH_SIZE"))
+    _, cwrite = _busiest(_pmc_per_kernel(cwrite_dir, "WRITE_SIZE"))
+    copy_kib = float(1 << 20)  # 1 GiB read and written by the calibration copy
+    fs, ws = copy_kib / cfetch, copy_kib / cwrite
+    q = {"D2Q9": 9, "D2V17": 17, "D2V37": 37}[args.lattice]
+    alg = 2 * q * STORAGE_BYTES[args.storage] * args.n * args.n
+    rd, wr = fetch * fs * 1024, write * ws * 1024
+    name = f"{args.lattice.lower()}_{args.storage}_{args.n}_traffic.txt"
+    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    lines = [
+        f"# HBM traffic of the {args.lattice} {args.storage.upper()} {args.n}x{args.n} pull stream-collide step (rocprofv3 PMC)",
+        "#",
+        "# Commands (repo root on an MI355X; one counter per run):",
+        f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- {PROFILE_RUN} --lattice {args.lattice} --n {args.n}{flag}",
+        f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d {write_dir} -o run -- {PROFILE_RUN} --lattice {args.lattice} --n {args.n}{flag}",
+        f"# Calibration with a device copy of 1 GiB (torch copy_, kernel {cname}):",
+        f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d {cfetch_dir} -o run -- python3 bench.py --copy-only",
+        f"#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d {cwrite_dir} -o run -- python3 bench.py --copy-only",
+        f"# Summary: python3 bench.py --lattice {args.lattice} --n {args.n}{flag} --summarize-pmc {fetch_dir} {write_dir} {cfetch_dir} {cwrite_dir}",
+        "#",
+        f"# copy: FETCH_SIZE {cfetch:.1f} KiB, WRITE_SIZE {cwrite:.1f} KiB per dispatch for {copy_kib:.0f} KiB read and written",
+        f"#   -> scale factors fetch {fs:.4f}, write {ws:.4f}",
+        f"# step kernel ({ndisp} dispatches): FETCH_SIZE {fetch:.1f} KiB, WRITE_SIZE {write:.1f} KiB per dispatch",
+        f"#   -> read {rd / 1e6:.1f} MB, written {wr / 1e6:.1f} MB per launch; algorithmic 2*{q}*{STORAGE_BYTES[args.storage]}*{args.n}^2 = {alg / 1e6:.1f} MB",
+        f"#   -> measured / algorithmic = {(rd + wr) / alg:.4f}",
+        f"kernel: {kname}",
+        f"kernel_source_hash: {kernel_source_hash()}",
+        f"fetch_scale: {fs:.6f}",
+        f"write_scale: {ws:.6f}",
+        f"read_bytes_per_launch: {rd:.0f}",
+        f"write_bytes_per_launch: {wr:.0f}",
+        f"hbm_bytes_per_launch: {rd + wr:.0f}",
+    ]
+    path = os.path.join(ROOT, "profiles", name)
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
+
+
+def summarize_trace(args) -> str:
+    """Writes profiles/<lattice>_<storage>_<n>_kernel_trace.md from the rocpd
+    database of a --kernel-trace --stats run, plus the live HIP-event timing
+    of the bench JSON line printed by the same run."""
+    import sqlite3
+
+    db, bench_json = args.summarize_trace
+    rows = sqlite3.connect(db).execute(
+        "select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    line = [ln for ln in open(bench_json) if ln.startswith("{")][-1]
+    live = json.loads(line)
+    roof = live["roofline"]
+    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    name = f"{args.lattice.lower()}_{args.storage}_{args.n}_kernel_trace.md"
+    out = [f"# rocprofv3 kernel trace: {args.lattice} {args.storage.upper()} {args.n}x{args.n} shear layer (pull stream-collide)",
+           "", "Command (repo root on an MI355X):", "",
+           f"    rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o run -- python3 bench.py --steps 50 --warmup 5 "
+           f"--no-cpu-baseline --no-sweep --no-batch --no-studies --closure none --lattice {args.lattice} --n {args.n}{flag}",
+           "", f"Summary: `python3 bench.py --lattice {args.lattice} --n {args.n}{flag} --summarize-trace <run_results.db> <bench output>`",
+           "", "From the `top_kernels` view of the run's database (durations in microseconds):", "",
+           "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for n, c, tot, avg, pct in rows:
+        out.append(f"| `{n}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
+    out += ["", f"Live HIP-event timing of the step kernel inside the same run ({live['steps']} timed steps): "
+                f"average {roof['kernel_ms_avg'] * 1e3:.2f} us, min {roof['kernel_ms_min'] * 1e3:.2f} us per launch.",
+            "", f"Algorithmic bytes per launch: {roof['bytes_per_launch']} B -> {roof['achieved']:.1f} GB/s = "
+                f"{roof['frac'] * 100:.1f}% of the 8 TB/s HBM3E peak.",
+            f"kernel_source_hash: {kernel_source_hash()}"]
+    path = os.path.join(ROOT, "profiles", name)
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    return path
+
+
 def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0):
     q, reach, n_eq, cs2 = b.lbm_lattice_info(lattice)
     u0, tau = wl.shear_layer_params(cs2, n, re)
@@ -206,10 +312,23 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--closure", choices=["full", "small", "none"], default="none",
+    ap.add_argument("--no-studies", action="store_true", help="skip the precision and Sod studies")
+    ap.add_argument("--closure", choices=["full", "small", "none"], default="full",
                     help="learned-closure study: D2V37 256^2 coarse / 1024^2 fine (full) or 64^2 / 256^2")
     ap.add_argument("--copy-only", action="store_true", help="only run 1 GiB device copies (counter calibration)")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar="DIR",
+                    help="write the traffic summary from rocprofv3 --pmc csv dirs: step FETCH_SIZE, step WRITE_SIZE, "
+                         "copy FETCH_SIZE, copy WRITE_SIZE (no GPU needed)")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "BENCH_OUT"),
+                    help="write the kernel-trace summary from a rocprofv3 database and that run's output")
     args = ap.parse_args()
+
+    if args.summarize_pmc:
+        print(summarize_pmc(args))
+        return
+    if args.summarize_trace:
+        print(summarize_trace(args))
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -292,6 +411,11 @@ def main():
         out["copy_GBs"] = round(copy_bandwidth(torch), 1)
     if not args.no_batch:
         out["batched"] = batched_suite(torch, b, wl)
+    if not args.no_studies:
+        from paper_1704_04413_amd import studies
+
+        out["precision"] = studies.precision_study(torch)
+        out["sod"] = studies.sod_study(torch)
     if args.closure != "none":
         from paper_1704_04413_amd import closure as cl
 

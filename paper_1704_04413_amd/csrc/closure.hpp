@@ -253,6 +253,8 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(StepArgs a, Clos
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
         v[I] = S::load(fin + ys[cy + R] + xs[cx + R] + int(I) * lay.te);
     });
+    Invariants<L, T, false, S::conserve_in_double> inv;
+    inv.take(v);
     NodeCoeffs<T> k;
     node_coeffs<L, T, COLL_RR, false, S::shifted, false>(v, k);
 
@@ -307,6 +309,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(StepArgs a, Clos
         k.a1[0][4] += T(r[8]) * inv_s;
     }
     relax_reconstruct<L, T>(k, T(a.keep), a.order, v);
+    inv.restore(v);
     if (valid) {
         const int here = lay.row(y) + x;
         static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * lay.te, v[I]); });

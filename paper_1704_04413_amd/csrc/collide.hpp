@@ -305,11 +305,80 @@ __device__ __forceinline__ void relax_reconstruct(NodeCoeffs<T>& k, T keep, int 
     reconstruct<L, T>(k.C, out);
 }
 
+// Conservation in float arithmetic.  Two float effects move the conserved
+// moments at every step: the lattice identities behind conservation (for
+// instance sum_i w_i c_ix^2 = c_s^2) hold only to the rounding of the folded
+// constants, so the rebuild returns rho u (1 + eps) with a fixed eps of a few
+// 1e-8; and float sums of 37 populations carry a few ulps of error, which a
+// correction towards float-summed input moments would write back into the
+// state.  Both act coherently over thousands of steps wherever the flow is
+// nearly uniform.  So the mass and momentum (and energy when thermal) of the
+// input and of the rebuilt populations are summed in double, where every term
+// c_i v_i of a float v_i is exact, and the difference is put back along
+// w_i, w_i c_i and w_i (|c_i|^2 - 2 c_s^2), which carry mass, momentum and
+// energy only (orthogonality on every lattice).  All Hermite moments, the
+// equilibrium and the recursion stay in float.
+template <class L, bool THERMAL>
+__device__ __forceinline__ void conserved_sums(const float (&v)[L::Q], double (&m)[4])
+{
+    double m0 = 0.0, mx = 0.0, my = 0.0, me = 0.0;
+    static_for<L::Q>([&](auto I) {
+        constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
+        const double x = double(v[I]);
+        m0 += x;
+        if constexpr (cx != 0) mx += double(cx) * x;
+        if constexpr (cy != 0) my += double(cy) * x;
+        if constexpr (THERMAL) me += double(cx * cx + cy * cy) * x;
+    });
+    m[0] = m0;
+    m[1] = mx;
+    m[2] = my;
+    m[3] = me;
+}
+
+// Off (FP64 populations, which conserve to ~1e-16, and BF16 storage, whose
+// rounding at the store outweighs all of the above): nothing to do.
+template <class L, class T, bool THERMAL, bool ON>
+struct Invariants {
+    __device__ __forceinline__ void take(const T (&)[L::Q]) {}
+    __device__ __forceinline__ void restore(T (&)[L::Q]) const {}
+};
+
+template <class L, bool THERMAL>
+struct Invariants<L, float, THERMAL, true> {
+    double m[4];
+    __device__ __forceinline__ void take(const float (&v)[L::Q]) { conserved_sums<L, THERMAL>(v, m); }
+    __device__ __forceinline__ void restore(float (&out)[L::Q]) const
+    {
+        constexpr double cs2 = L::cs2;
+        double o[4];
+        conserved_sums<L, THERMAL>(out, o);
+        const double d0 = m[0] - o[0];
+        const float dx = float((m[1] - o[1]) * (1.0 / cs2)), dy = float((m[2] - o[2]) * (1.0 / cs2));
+        // energy: the mode w (|c|^2 - 2 c_s^2) has sum w (|c|^2 - 2c_s^2)|c|^2 = 4 c_s^4;
+        // the mass correction d0 itself adds 2 c_s^2 d0 to sum |c|^2 v
+        const float de = THERMAL ? float((m[3] - o[3] - 2.0 * cs2 * d0) * (1.0 / (4.0 * cs2 * cs2))) : 0.0f;
+        const float t0 = float(d0);
+        static_for<L::Q>([&](auto I) {
+            constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
+            constexpr float w = float(L::v.w[I]);
+            float c = t0;
+            if constexpr (cx != 0) c += float(cx) * dx;
+            if constexpr (cy != 0) c += float(cy) * dy;
+            if constexpr (THERMAL) c += float(double(cx * cx + cy * cy) - 2.0 * cs2) * de;
+            out[I] += w * c;
+        });
+    }
+};
+
 // The regularized (or BGK) collision of one node, in place.
-//   keep = 1 - 1/tau, inv_tau = 1/tau, order = N.
-template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
+//   keep = 1 - 1/tau, inv_tau = 1/tau, order = N; CONS: restore the conserved
+//   moments summed in double (float storage).
+template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P, bool CONS>
 __device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, int order)
 {
+    Invariants<L, T, THERMAL, CONS> inv;
+    inv.take(v);
     NodeCoeffs<T> k;
     node_coeffs<L, T, COLL, THERMAL, SHIFTED, A13P>(v, k);
     if constexpr (COLL == COLL_BGK) {
@@ -324,9 +393,11 @@ __device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, in
         T eq[L::Q];
         reconstruct<L, T>(k.C, eq);
         static_for<L::Q>([&](auto I) { v[I] = keep * v[I] + inv_tau * eq[I]; });
+        inv.restore(v);
         return;
     }
     relax_reconstruct<L, T>(k, keep, order, v);
+    inv.restore(v);
 }
 
 // Equilibrium populations truncated at Hermite rank `order` (initial state).

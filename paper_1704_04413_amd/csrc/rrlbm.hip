@@ -36,6 +36,7 @@ struct StoreF64 {
     using elem = double;
     using math = double;
     static constexpr bool shifted = false;
+    static constexpr bool conserve_in_double = false;
     static __device__ __forceinline__ double load(const double* p) { return *p; }
     static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
     static __device__ __forceinline__ void store_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
@@ -45,6 +46,7 @@ struct StoreF32 {
     using elem = float;
     using math = float;
     static constexpr bool shifted = true;
+    static constexpr bool conserve_in_double = true;
     static __device__ __forceinline__ float load(const float* p) { return *p; }
     static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
     static __device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
@@ -55,6 +57,7 @@ struct StoreBF16 {
     using elem = uint16_t;
     using math = float;
     static constexpr bool shifted = true;
+    static constexpr bool conserve_in_double = false;
     static __device__ __forceinline__ float load(const uint16_t* p)
     {
         return __uint_as_float(uint32_t(*p) << 16);
@@ -158,7 +161,7 @@ __device__ __forceinline__ void node_update(const typename S::elem* __restrict__
         v[I] = S::load(fin + idx);
     });
 
-    collide_node<L, T, COLL, THERMAL, S::shifted, A13P>(v, T(keep), T(inv_tau), order);
+    collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, T(keep), T(inv_tau), order);
 
     static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * lay.te, v[I]); });
 }

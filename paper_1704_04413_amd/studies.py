@@ -1,0 +1,123 @@
+"""Workload studies on the GPU: reduced-precision storage against the FP64
+plain form on the paper's shear layer (Sec. III.B), and the thermal D2V37
+Sod tube (Sec. III.C).  Every step runs in the HIP library; these functions
+only set up seeded inputs, step, and reduce the library's diagnostics.
+
+Stability follows the paper's criterion (Sec. III.B): a run is unstable once
+<|u|^2> exceeds its initial value (checked every `every` steps, within two
+convective times t_c = N/u0) or a non-finite node appears.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import binding as b
+from . import workloads as wl
+
+STORE = {"fp64": 0, "fp32": b.LBM_STORE_FP32, "bf16": b.LBM_STORE_BF16}
+
+
+def _flow_stats(s, n, u0):
+    """KE and enstrophy mean/std from the library's sums (KE = |u|^2/2/u0^2,
+    enstrophy = omega^2/2 (n/u0)^2)."""
+    nodes = n * n
+    ke_m = 0.5 * s[4] / nodes / u0 ** 2
+    ke_s = np.sqrt(max(0.0, 0.25 * s[5] / nodes / u0 ** 4 - ke_m ** 2))
+    en_scale = 0.5 * (n / u0) ** 2
+    en_m = en_scale * s[6] / nodes
+    en_s = np.sqrt(max(0.0, en_scale ** 2 * s[7] / nodes - en_m ** 2))
+    return ke_m, ke_s, en_m, en_s
+
+
+def shear_run(torch, lattice, n, re, storage, steps, every, keep_fields_at=()):
+    """Shear layer at Mach 0.1; returns the diagnostic history, the blow-up
+    step (None if stable) and velocity fields at the requested steps."""
+    q, _, _, cs2 = b.lbm_lattice_info(lattice)
+    u0, tau = wl.shear_layer_params(cs2, n, re)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    noise = wl.uniform_noise(0, q, n, n)
+    sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, flags=STORE[storage])
+    tc = n / u0
+    hist, fields, blow = [], {}, None
+    u2_0 = None
+    while sim.steps <= steps:
+        m = sim.moments()
+        s = m["sums"]
+        u2 = s[4] / (n * n)
+        u2_0 = u2 if u2_0 is None else u2_0
+        hist.append((sim.steps,) + tuple(float(v) for v in _flow_stats(s, n, u0)))
+        if sim.steps in keep_fields_at:
+            fields[sim.steps] = (m["ux"].clone(), m["uy"].clone())
+        if blow is None and (s[8] > 0 or (sim.steps <= 2 * tc and u2 > u2_0 * (1 + 1e-12))):
+            blow = sim.steps
+        if s[8] > 0 or sim.steps == steps:
+            break
+        sim.step(min(every, steps - sim.steps))
+    sim.close()
+    return dict(history=hist, blow_up_step=blow, tau=tau, u0=u0), fields
+
+
+def precision_study(torch, lattices=("D2V17", "D2V37"), sizes=(512, 1024), res=(3e4, 1e5, 1e6), steps=10000,
+                    every=500):
+    """FP32 and BF16 weight-shifted storage against the FP64 plain form:
+    blow-up steps, velocity relative L2 error at the last common checkpoint,
+    largest relative deviation of the KE / enstrophy means."""
+    out = []
+    t0 = time.perf_counter()
+    for lat in lattices:
+        for n in sizes:
+            for re in res:
+                ref, fref = shear_run(torch, lat, n, re, "fp64", steps, every, keep_fields_at=range(0, steps + 1, every))
+                row = dict(lattice=lat, n=n, re=re, tau=ref["tau"], blow_up_fp64=ref["blow_up_step"])
+                for st in ("fp32", "bf16"):
+                    r, f = shear_run(torch, lat, n, re, st, steps, every, keep_fields_at=range(0, steps + 1, every))
+                    common = sorted(set(fref) & set(f))
+                    k = common[-1]
+                    ux, uy = f[k]
+                    rx, ry = fref[k]
+                    err = float(torch.sqrt(((ux - rx) ** 2 + (uy - ry) ** 2).sum() / (rx ** 2 + ry ** 2).sum()))
+                    h, hr = np.array(r["history"]), np.array(ref["history"])
+                    m = min(len(h), len(hr))
+                    dke = float(np.max(np.abs(h[:m, 1] - hr[:m, 1]) / np.abs(hr[:m, 1])))
+                    den = float(np.max(np.abs(h[:m, 3] - hr[:m, 3]) / np.abs(hr[:m, 3])))
+                    row[st] = dict(blow_up_step=r["blow_up_step"], compared_at=k, velocity_rel_l2=err,
+                                   ke_mean_rel_dev=dke, enstrophy_mean_rel_dev=den)
+                del fref
+                out.append(row)
+    return dict(rows=out, steps=steps, seconds=round(time.perf_counter() - t0, 1))
+
+
+def sod_run(torch, tau, storage="fp64", nx=2000, ny=4, steps=800, snap=None, theta_left=0.5, every=50):
+    """Thermal D2V37 Sod tube (rho, p)_L = (8, 10), (1, 1)_R, u = 0, interface
+    at nx/2, periodic.  Returns the blow-up step (first check with a
+    non-finite node or theta <= 0) and y-averaged rho, u, theta at `snap`."""
+    q, _, _, cs2 = b.lbm_lattice_info("D2V37")
+    rho, ux, uy, th = wl.sod_fields(nx, ny, theta_left=theta_left)
+    sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_THERMAL | STORE[storage])
+    blow, prof = None, None
+    marks = sorted(set(range(0, steps + 1, every)) | ({snap} if snap else set()))
+    for k in marks:
+        sim.step(k - sim.steps)
+        m = sim.moments(vorticity=False)
+        if k == snap:
+            prof = {key: m[key].mean(0).double().cpu().numpy() for key in ("rho", "ux", "theta")}
+        if blow is None and (m["sums"][8] > 0 or float(m["theta"].min()) <= 0.0):
+            blow = k
+            break
+    sim.close()
+    return dict(blow_up_step=blow, profile=prof, cs2=cs2)
+
+
+def sod_study(torch, taus=(0.5005, 0.51, 0.55, 0.595), steps=800):
+    """Blow-up steps over `steps` and MLUPS, FP64 and FP32 storage."""
+    rows = []
+    for tau in taus:
+        row = dict(tau=tau)
+        for st in ("fp64", "fp32"):
+            t0 = time.perf_counter()
+            r = sod_run(torch, tau, st, steps=steps)
+            row[st] = dict(blow_up_step=r["blow_up_step"], seconds=round(time.perf_counter() - t0, 2))
+        rows.append(row)
+    return rows
