@@ -312,7 +312,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(StepArgs a, Clos
     inv.restore(v);
     if (valid) {
         const int here = lay.row(y) + x;
-        static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * lay.te, v[I]); });
+        store_node<L, S>(fout, here, lay.te, v, uint32_t(y) * uint32_t(nx) + uint32_t(x), a.seq);
     }
 }
 

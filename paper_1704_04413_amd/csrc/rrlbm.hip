@@ -37,6 +37,7 @@ struct StoreF64 {
     using math = double;
     static constexpr bool shifted = false;
     static constexpr bool conserve_in_double = false;
+    static constexpr bool dithered = false;
     static __device__ __forceinline__ double load(const double* p) { return *p; }
     static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
     static __device__ __forceinline__ void store_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
@@ -47,17 +48,23 @@ struct StoreF32 {
     using math = float;
     static constexpr bool shifted = true;
     static constexpr bool conserve_in_double = true;
+    static constexpr bool dithered = false;
     static __device__ __forceinline__ float load(const float* p) { return *p; }
     static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
     static __device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 
-// bfloat16 = the upper half of an IEEE float; stores round to nearest even.
+// bfloat16 = the upper half of an IEEE float.  The initial state is rounded
+// to nearest even; every step rounds stochastically (store_nt_sr): with
+// deterministic rounding a near-uniform region sits at a fixed point of the
+// rounded update and its 2^-9 rounding bias acts coherently over thousands of
+// steps, while a rounding that is unbiased in expectation turns it into noise.
 struct StoreBF16 {
     using elem = uint16_t;
     using math = float;
     static constexpr bool shifted = true;
     static constexpr bool conserve_in_double = false;
+    static constexpr bool dithered = true;
     static __device__ __forceinline__ float load(const uint16_t* p)
     {
         return __uint_as_float(uint32_t(*p) << 16);
@@ -71,7 +78,56 @@ struct StoreBF16 {
     }
     static __device__ __forceinline__ void store(uint16_t* p, float v) { *p = round(v); }
     static __device__ __forceinline__ void store_nt(uint16_t* p, float v) { __builtin_nontemporal_store(round(v), p); }
+    // r: 16 uniform random bits; |v| rounds up with probability (dropped bits) / 2^16
+    static __device__ __forceinline__ uint16_t round_sr(float v, uint32_t r)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u); // quiet NaN
+        return uint16_t((u + r) >> 16);
+    }
+    static __device__ __forceinline__ void store_nt_sr(uint16_t* p, float v, uint32_t r)
+    {
+        __builtin_nontemporal_store(round_sr(v, r), p);
+    }
 };
+
+// Counter-based random bits for stochastic rounding: a function of the node
+// (y nx + x of its own grid) and of the index of the state being written (0 for
+// the initial state, n after n steps) only, so results do not depend on launch
+// shape or batching.  The key is Wellons' "lowbias32" integer hash; the stream
+// per node is the 32-bit LCG of PCG (O'Neill), of which the top 16 bits are used.
+struct Dither {
+    uint32_t s;
+    static __device__ __forceinline__ uint32_t mix(uint32_t x)
+    {
+        x ^= x >> 16;
+        x *= 0x7feb352du;
+        x ^= x >> 15;
+        x *= 0x846ca68bu;
+        x ^= x >> 16;
+        return x;
+    }
+    __device__ __forceinline__ Dither(uint32_t node, uint32_t seq) : s(mix(node ^ mix(seq * 0x9e3779b9u + 0x6a09e667u))) {}
+    __device__ __forceinline__ uint32_t next16()
+    {
+        s = s * 747796405u + 2891336453u;
+        return s >> 16;
+    }
+};
+
+// Writes the Q post-collision values of one node (stochastic rounding where
+// the storage asks for it).
+template <class L, class S, class T>
+__device__ __forceinline__ void store_node(typename S::elem* __restrict__ fout, int here, int te, const T (&v)[L::Q],
+                                           uint32_t node, uint32_t seq)
+{
+    if constexpr (S::dithered) {
+        Dither dz(node, seq);
+        static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + here + int(I) * te, v[I], dz.next16()); });
+    } else {
+        static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * te, v[I]); });
+    }
+}
 
 // ----------------------------------------------------------------- layout
 
@@ -113,6 +169,7 @@ struct StepArgs {
     double keep;    // 1 - 1/tau
     double inv_tau;
     int order;
+    uint32_t seq;   // index of the state written (0: initial state), keys the BF16 dither
 };
 
 // The hardware hands consecutive workgroup ids to the 8 XCDs in turn; with
@@ -131,7 +188,7 @@ __device__ __forceinline__ int block_index(const StepArgs& a)
 template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
 __device__ __forceinline__ void node_update(const typename S::elem* __restrict__ fin,
                                             typename S::elem* __restrict__ fout, const Layout& lay, int x,
-                                            int y, double keep, double inv_tau, int order)
+                                            int y, double keep, double inv_tau, int order, uint32_t seq)
 {
     using T = typename S::math;
     constexpr int R = L::R;
@@ -163,7 +220,7 @@ __device__ __forceinline__ void node_update(const typename S::elem* __restrict__
 
     collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, T(keep), T(inv_tau), order);
 
-    static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * lay.te, v[I]); });
+    store_node<L, S>(fout, here, lay.te, v, uint32_t(y) * uint32_t(nx) + uint32_t(x), seq);
 }
 
 template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
@@ -176,7 +233,7 @@ void k_stream_collide(StepArgs a)
     if (x >= a.lay.nx || y >= a.lay.ny) return;
     node_update<L, S, COLL, THERMAL, A13P, PULL>(static_cast<const typename S::elem*>(a.fin),
                                                  static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.keep,
-                                                 a.inv_tau, a.order);
+                                                 a.inv_tau, a.order, a.seq);
 }
 
 // ---------------------------------------------------------- batch kernel
@@ -190,6 +247,7 @@ struct InstDesc {
     int flip;      // index of the buffer holding the member's current state
     int order;
     double keep, inv_tau;
+    uint32_t seq;  // index of the state the parity-0 launch writes (BF16 dither key)
 };
 
 // Persistent kernel: blocks stride over the work list (member, tile); item w
@@ -222,9 +280,9 @@ __global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ d
             const int x = x0 + sub + int(threadIdx.x);
             if (x < d.lay.nx && y < d.lay.ny) {
                 switch (d.lattice) {
-                case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order); break;
-                case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order); break;
-                default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order); break;
+                case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order, d.seq + uint32_t(parity)); break;
+                case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order, d.seq + uint32_t(parity)); break;
+                default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order, d.seq + uint32_t(parity)); break;
                 }
             }
         }
@@ -450,7 +508,8 @@ template <class L, class S, int COLL, bool TH, bool A13P>
 hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
     const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
-    StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, 1.0 - 1.0 / c->tau, 1.0 / c->tau, c->order };
+    StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, 1.0 - 1.0 / c->tau, 1.0 / c->tau, c->order,
+                pull ? uint32_t(c->steps + 1) : 0u };
     dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if constexpr (L::id == LBM_D2V37 && COLL == COLL_RR && !TH) {
         if (pull && c->closure) {
@@ -759,6 +818,14 @@ const char* lbm_last_error(void) { return g_err.c_str(); }
 
 // ================================================================ batches
 
+// Moves every member's dither key on by the two steps of one graph replay
+// (BF16 batches: the replayed launches read it from the descriptors).
+__global__ void k_batch_advance(InstDesc* desc, int n)
+{
+    const int i = int(blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) desc[i].seq += 2u;
+}
+
 struct lbm_batch {
     std::vector<lbm_ctx*> members;
     std::vector<InstDesc> desc;
@@ -822,6 +889,7 @@ int batch_prepare(lbm_batch* b)
         d.order = c->order;
         d.keep = 1.0 - 1.0 / c->tau;
         d.inv_tau = 1.0 / c->tau;
+        d.seq = uint32_t(c->steps + 1);
         b->begin[i] = int(total);
         total += int64_t(d.bx_blocks) * ((c->ny + BY - 1) / BY);
     }
@@ -835,6 +903,10 @@ int batch_prepare(lbm_batch* b)
     HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
     hipError_t e0 = launch_batch_any(b, b->capture, 0);
     hipError_t e1 = (e0 == hipSuccess) ? launch_batch_any(b, b->capture, 1) : e0;
+    if (e1 == hipSuccess && b->store == ST_BF16) {
+        k_batch_advance<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, b->capture>>>(b->d_desc, n);
+        e1 = hipGetLastError();
+    }
     hipError_t ec = hipStreamEndCapture(b->capture, &b->graph);
     if (e0 != hipSuccess || e1 != hipSuccess || ec != hipSuccess) {
         batch_release_graph(b);
@@ -845,15 +917,24 @@ int batch_prepare(lbm_batch* b)
     return LBM_OK;
 }
 
-// If a member was stepped on its own, refresh the parities on the device.
+// If a member was stepped on its own (or an odd step count left the device's
+// dither keys behind), refresh the parities and keys on the device.
 int batch_sync_parity(lbm_batch* b)
 {
+    const bool dither = b->store == ST_BF16;
     bool stale = false;
-    for (size_t i = 0; i < b->members.size(); ++i)
-        if (b->desc[i].flip != b->members[i]->cur) {
-            b->desc[i].flip = b->members[i]->cur;
+    for (size_t i = 0; i < b->members.size(); ++i) {
+        InstDesc& d = b->desc[i];
+        const lbm_ctx* c = b->members[i];
+        if (d.flip != c->cur) {
+            d.flip = c->cur;
             stale = true;
         }
+        if (dither && d.seq != uint32_t(c->steps + 1)) {
+            d.seq = uint32_t(c->steps + 1);
+            stale = true;
+        }
+    }
     if (stale) {
         HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(InstDesc) * b->desc.size(),
                                hipMemcpyHostToDevice, b->stream));
@@ -915,6 +996,8 @@ int lbm_batch_step(lbm_batch* b, int nsteps)
     int e = batch_sync_parity(b);
     if (e) return e;
     for (int s = 0; s + 1 < nsteps; s += 2) HIP_TRY(hipGraphLaunch(b->exec, b->stream));
+    if (b->store == ST_BF16) // the graph advanced the device copies of the keys
+        for (InstDesc& d : b->desc) d.seq += uint32_t(nsteps & ~1);
     if (nsteps % 2) {
         HIP_TRY(launch_batch_any(b, b->stream, 0));
         for (lbm_ctx* c : b->members) c->cur ^= 1;
