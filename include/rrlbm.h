@@ -184,8 +184,8 @@ void lbm_batch_destroy(lbm_batch* b);
  *   W1 8x64 | b1 64 | W2 64x64 | b2 64 | W3 64x16 | b3 16  (outputs 9..15 unused, keep 0)
  * Normalisation block: LBM_MLP_NNORM float32
  *   in_mean[8] in_std[8] in_lo[8] in_hi[8] out_mean[16] out_std[16] out_lo[16] out_hi[16]
- * Inputs 0..6: rho - 1, ux, uy, theta_kin - 1 (energy moment), ahat_xx,
- * ahat_xy, ahat_yy; input 7 is the constant 1 (not normalised).  Outputs
+ * Inputs 0..6: rho - 1, ux, uy, |u|^2 / c_s^2 (local Mach number squared),
+ * ahat_xx, ahat_xy, ahat_yy; input 7 is the constant 1 (not normalised).  Outputs
  * 0..8: the ahat^(3..4) residual, order 30, 21, 12, 03, 40, 31, 22, 13, 04
  * (x and y exponents).  lo/hi bound the training data in normalised units:
  * a node whose normalised input or output leaves them keeps the plain
@@ -200,10 +200,11 @@ void lbm_batch_destroy(lbm_batch* b);
  *   x[c][0..7] = raw inputs (input 7 = 1), and
  *   r[c][0..15] = ahat^(3..4) minus the recursion applied to the averaged
  *                 (rho, u, ahat^(2)) (entries 9..15 = 0).
- * tau_coarse enters only theta_kin.  fine must be an isothermal RR D2V37
- * context; x, r are device float32 arrays of (nx/factor)*(ny/factor) rows.
+ * Every input is tau-independent, so the coarse run's tau is not needed.
+ * fine must be an isothermal RR D2V37 context; x, r are device float32
+ * arrays of (nx/factor)*(ny/factor) rows.
  * Coarse node c = X + Y * (nx/factor).  Runs on fine's stream. */
-int lbm_closure_samples(lbm_ctx* fine, int factor, double tau_coarse, float* x, float* r);
+int lbm_closure_samples(lbm_ctx* fine, int factor, float* x, float* r);
 
 /* Normalisation block of n samples (x as above, r as above): mean and
  * standard deviation of inputs 0..6 and outputs 0..8 (a zero deviation is

@@ -212,7 +212,7 @@ def moments(lat: Lattice, f, thermal=False):
 
 def closure_inputs(lat: Lattice, f, tau):
     """(feat[7, n], rr[9, n]) of pre-collision populations f (Q, ...):
-    feat = (rho-1, ux, uy, theta_kin-1, ahat_xx, ahat_xy, ahat_yy), rr = ahat of
+    feat = (rho-1, ux, uy, |u|^2/cs2, ahat_xx, ahat_xy, ahat_yy), rr = ahat of
     the plain recursive a1^(3..4) in the order 30,21,12,03,40,31,22,13,04."""
     f = np.ascontiguousarray(f, dtype=np.float64).reshape(lat.Q, -1)
     n = f.shape[1]

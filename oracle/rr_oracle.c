@@ -592,9 +592,8 @@ static const int orc_hi_nx[9] = { 3, 2, 1, 0, 4, 3, 2, 1, 0 };
 static int pattern_of(int nx, int ny) { return ((1 << ny) - 1) << nx; }
 
 /* Per node of pre-collision f[Q][n] (isothermal): feat[7][n] =
- * (rho - 1, ux, uy, theta_kin - 1, ahat_xx, ahat_xy, ahat_yy) with
- * theta_kin from the energy moment, and rr[9][n] = a_hat of the plain
- * recursive a1^(3..4). */
+ * (rho - 1, ux, uy, |u|^2 / c_s^2, ahat_xx, ahat_xy, ahat_yy), and
+ * rr[9][n] = a_hat of the plain recursive a1^(3..4). */
 int orc_closure_inputs(int id, double tau, int64_t n, const double* f, double* feat, double* rr)
 {
     orc_lattice_t L;
@@ -612,7 +611,7 @@ int orc_closure_inputs(int id, double tau, int64_t n, const double* f, double* f
         feat[0 * n + k] = rho - 1.0;
         feat[1 * n + k] = u[0];
         feat[2 * n + k] = u[1];
-        feat[3 * n + k] = th - 1.0;
+        feat[3 * n + k] = (u[0] * u[0] + u[1] * u[1]) / L.cs2;
         feat[4 * n + k] = s * a1[toff(2, pattern_of(2, 0))];
         feat[5 * n + k] = s * a1[toff(2, pattern_of(1, 1))];
         feat[6 * n + k] = s * a1[toff(2, pattern_of(0, 2))];

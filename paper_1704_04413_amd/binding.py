@@ -77,7 +77,7 @@ def lib():
         L.lbm_batch_destroy.argtypes = [vp]
         L.lbm_batch_destroy.restype = None
         i64 = ctypes.c_int64
-        L.lbm_closure_samples.argtypes = [vp, ctypes.c_int, ctypes.c_double, vp, vp]
+        L.lbm_closure_samples.argtypes = [vp, ctypes.c_int, vp, vp]
         L.lbm_mlp_stats.argtypes = [vp, vp, i64, vp, vp]
         L.lbm_mlp_normalize.argtypes = [vp, vp, i64, vp, vp]
         L.lbm_mlp_create.argtypes = [ctypes.POINTER(vp), vp, i64, vp]
@@ -200,8 +200,8 @@ def _stream(stream):
     return ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
 
 
-def lbm_closure_samples(ctx, factor, tau_coarse, x, r):
-    _check(lib().lbm_closure_samples(ctypes.c_void_p(ctx), factor, tau_coarse, _ptr(x), _ptr(r)))
+def lbm_closure_samples(ctx, factor, x, r):
+    _check(lib().lbm_closure_samples(ctypes.c_void_p(ctx), factor, _ptr(x), _ptr(r)))
 
 
 def lbm_mlp_stats(x, r, n, norm, stream=None):

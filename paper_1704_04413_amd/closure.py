@@ -5,7 +5,9 @@ Adam kernels, and evaluation against the restricted fine reference.
 
 Shear layers follow the paper's doubly periodic case (Sec. III.B); fine and
 coarse grids share Re and Mach (acoustic scaling), so coarse step k matches
-fine step factor*k.  A seed fixes the phase of the transverse perturbation.
+fine step factor*k.  A seed draws the layer's steepness k in [60, 100], the
+perturbation amplitude delta in [0.03, 0.08] and its phase (a phase alone
+would only translate the same flow), so held-out seeds are different flows.
 """
 from __future__ import annotations
 
@@ -19,8 +21,10 @@ from . import workloads as wl
 NPARAM = b.LBM_MLP_NPARAM
 
 
-def phase_of(seed: int) -> float:
-    return float(np.random.Generator(np.random.PCG64(seed)).uniform())
+def flow_of(seed: int) -> dict:
+    """Shear-layer parameters of one seed: steepness k, amplitude delta, phase."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return dict(k=float(rng.uniform(60.0, 100.0)), delta=float(rng.uniform(0.03, 0.08)), phase=float(rng.uniform()))
 
 
 def grid_params(n_coarse: int, factor: int, re: float, mach: float = 0.1):
@@ -47,18 +51,18 @@ def generate_samples(torch, seeds, n_coarse=256, factor=4, re=3e4, snaps=tuple(r
     """Runs the plain method on the fine grid for each seed and restricts it
     at coarse steps `snaps`.  Returns raw x [N, 8], r [N, 16] (device
     float32), the per-snapshot restricted velocities and timing."""
-    u0, tau_f, tau_c = grid_params(n_coarse, factor, re)
+    u0, tau_f, _ = grid_params(n_coarse, factor, re)
     nf, nc = n_coarse * factor, n_coarse * n_coarse
     xs, rs, ref = [], [], {}
     t0 = time.perf_counter()
     for seed in seeds:
-        rho, ux, uy = wl.shear_layer_fields(nf, nf, u0, phase=phase_of(seed))
+        rho, ux, uy = wl.shear_layer_fields(nf, nf, u0, **flow_of(seed))
         sim = b.Simulation("D2V37", nf, nf, tau_f, rho, ux, uy)
         for k in snaps:
             sim.step(factor * k - sim.steps)
             x = torch.empty((nc, 8), dtype=torch.float32, device=sim.device)
             r = torch.empty((nc, 16), dtype=torch.float32, device=sim.device)
-            b.lbm_closure_samples(sim.ctx, factor, tau_c, x, r)
+            b.lbm_closure_samples(sim.ctx, factor, x, r)
             xs.append(x)
             rs.append(r)
             ref[(seed, k)] = (x[:, 1].reshape(n_coarse, n_coarse).double().cpu().numpy(),
@@ -125,7 +129,7 @@ def a_priori(torch, theta, norm, x_raw, r_raw):
 def coarse_run(torch, seed, snaps, n_coarse=256, factor=4, re=3e4, theta=None, norm=None):
     """Coarse plain (theta None) or closure run; velocities at `snaps`."""
     u0, tau_f, tau_c = grid_params(n_coarse, factor, re)
-    rho, ux, uy = wl.shear_layer_fields(n_coarse, n_coarse, u0, phase=phase_of(seed))
+    rho, ux, uy = wl.shear_layer_fields(n_coarse, n_coarse, u0, **flow_of(seed))
     sim = b.Simulation("D2V37", n_coarse, n_coarse, tau_c, rho, ux, uy)
     if theta is not None:
         b.lbm_closure_set(sim.ctx, theta, norm)

@@ -22,7 +22,7 @@
 //   in_mean[8] in_std[8] in_lo[8] in_hi[8] out_mean[16] out_std[16] out_lo[16] out_hi[16]
 // (inputs 0..6 used, input 7 is the constant 1; outputs 0..8 used; lo/hi are
 // the training range in normalised units).  Inputs: rho - 1, ux, uy,
-// theta_kin - 1, ahat_xx, ahat_xy, ahat_yy with ahat = (1 - 1/(2 tau)) a1
+// |u|^2 / c_s^2, ahat_xx, ahat_xy, ahat_yy with ahat = (1 - 1/(2 tau)) a1
 // (tau-independent: the viscous stress is -ahat^(2)); outputs: the residual
 // of ahat^(3..4) in the order 30, 21, 12, 03, 40, 31, 22, 13, 04.
 #pragma once
@@ -188,7 +188,7 @@ __device__ __forceinline__ v4f mlp_fwd16(const MlpInfer& F, v4s xb, int lane, Fw
 // ------------------------------------------------- fused closure collision
 
 // Closure inputs of one node from its coefficients (isothermal, a1 before
-// truncation): rho - 1, ux, uy, theta_kin - 1, s a1_xx, s a1_xy, s a1_yy.
+// truncation): rho - 1, ux, uy, |u|^2 / c_s^2, s a1_xx, s a1_xy, s a1_yy.
 template <class L, class T>
 __device__ __forceinline__ void closure_features(const NodeCoeffs<T>& k, T s, float (&f)[7])
 {
@@ -196,7 +196,7 @@ __device__ __forceinline__ void closure_features(const NodeCoeffs<T>& k, T s, fl
     f[0] = float(k.drho);
     f[1] = float(k.ux);
     f[2] = float(k.uy);
-    f[3] = float((k.a1[2][0] + k.a1[0][2]) / (T(2) * k.rho * cs2));
+    f[3] = float((k.ux * k.ux + k.uy * k.uy) / cs2);
     f[4] = float(s * k.a1[2][0]);
     f[5] = float(s * k.a1[1][1]);
     f[6] = float(s * k.a1[0][2]);
@@ -525,7 +525,7 @@ __global__ __launch_bounds__(256) void k_mlp_reduce_adam(const float* __restrict
 // r[c][0..8] = ahat^(3..4) - recursion(rho, u, ahat^(2)) (r[c][9..15] = 0).
 template <class S>
 __global__ __launch_bounds__(256) void k_closure_samples(const void* fsrc, Layout lay, int factor, double sf,
-                                                         double sc, float* __restrict__ xo, float* __restrict__ ro)
+                                                         float* __restrict__ xo, float* __restrict__ ro)
 {
     using L = D2V37;
     using T = double;
@@ -563,7 +563,7 @@ __global__ __launch_bounds__(256) void k_closure_samples(const void* fsrc, Layou
     x[0] = float(rho - 1.0);
     x[1] = float(ux);
     x[2] = float(uy);
-    x[3] = float((xx + yy) / sc / (2.0 * rho * L::cs2));
+    x[3] = float((ux * ux + uy * uy) / L::cs2);
     x[4] = float(xx);
     x[5] = float(xy);
     x[6] = float(yy);

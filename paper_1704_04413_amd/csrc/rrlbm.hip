@@ -1094,11 +1094,11 @@ namespace {
 
 template <class L, class S>
 struct SampleOp {
-    static hipError_t run(const lbm_ctx* c, int factor, double sf, double sc, float* x, float* r)
+    static hipError_t run(const lbm_ctx* c, int factor, double sf, float* x, float* r)
     {
         const int64_t nc = int64_t(c->nx / factor) * (c->ny / factor);
         k_closure_samples<S><<<dim3(unsigned((nc + 255) / 256)), dim3(256), 0, c->stream>>>(
-            c->buf[c->cur], c->lay, factor, sf, sc, x, r);
+            c->buf[c->cur], c->lay, factor, sf, x, r);
         return hipGetLastError();
     }
 };
@@ -1113,23 +1113,21 @@ hipError_t launch_frags(const float* theta, MlpInfer* fi, MlpBack* fb, hipStream
 
 extern "C" {
 
-int lbm_closure_samples(lbm_ctx* c, int factor, double tau_coarse, float* x, float* r)
+int lbm_closure_samples(lbm_ctx* c, int factor, float* x, float* r)
 {
     if (!c || !x || !r) return fail(LBM_EINVAL, "ctx, x or r is NULL");
     if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal)
         return fail(LBM_EINVAL, "closure samples need an isothermal RR D2V37 context");
     if (factor < 1 || factor > 8 || c->nx % factor || c->ny % factor)
         return fail(LBM_EINVAL, "factor must be in [1, 8] and divide nx and ny");
-    if (!std::isfinite(tau_coarse) || !(tau_coarse > 0.5)) return fail(LBM_ETAU, "tau_coarse must be > 1/2");
     const double sf = (1.0 - 0.5 / c->tau) / (1.0 - 1.0 / c->tau);
-    const double sc = 1.0 - 0.5 / tau_coarse;
     if (!std::isfinite(sf)) return fail(LBM_ETAU, "fine tau must differ from 1");
     // fine D2V37 is the only lattice: dispatch on the storage type alone
     hipError_t he = hipSuccess;
     switch (c->store) {
-    case ST_F32: he = SampleOp<D2V37, StoreF32>::run(c, factor, sf, sc, x, r); break;
-    case ST_BF16: he = SampleOp<D2V37, StoreBF16>::run(c, factor, sf, sc, x, r); break;
-    default: he = SampleOp<D2V37, StoreF64>::run(c, factor, sf, sc, x, r); break;
+    case ST_F32: he = SampleOp<D2V37, StoreF32>::run(c, factor, sf, x, r); break;
+    case ST_BF16: he = SampleOp<D2V37, StoreBF16>::run(c, factor, sf, x, r); break;
+    default: he = SampleOp<D2V37, StoreF64>::run(c, factor, sf, x, r); break;
     }
     if (he != hipSuccess) return fail(LBM_EDEVICE, std::string("samples launch: ") + hipGetErrorString(he));
     return LBM_OK;

@@ -1,8 +1,9 @@
 """What the trained closure gains over the plain recursion, at reduced scale
 (coarse 64^2 D2V37, fine 256^2, Re 3e4, six training and two held-out
-perturbation phases), trained on the GPU by the library's kernels.
+seeds, each a different shear layer: steepness, amplitude and phase of the
+perturbation), trained on the GPU by the library's kernels.
 
-A priori (held-out phases): the share of the plain recursion's squared error
+A priori (held-out flows): the share of the plain recursion's squared error
 in a_hat^(3..4) (against the restricted fine run) that the closure removes.
 A posteriori: the coarse run with the closure must conserve mass and momentum
 and stay at least as close to the restricted fine velocity as the plain run

@@ -95,3 +95,5 @@ def test_closure_inputs_are_the_rr_coefficients(orc):
     r, vx, vy, _ = orc.moments(lat, f)
     np.testing.assert_allclose(feat[0], r - 1, rtol=1e-12)
     np.testing.assert_allclose(feat[1], vx, rtol=1e-12)
+    np.testing.assert_allclose(feat[2], vy, rtol=1e-12)
+    np.testing.assert_allclose(feat[3], (vx ** 2 + vy ** 2) / lat.cs2, rtol=1e-12)
