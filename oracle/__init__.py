@@ -58,6 +58,7 @@ def lib():
         L.orc_noneq_coeffs.argtypes = [ctypes.c_int] * 4 + [dp, dp]
         L.orc_recursion.argtypes = [ctypes.c_int] + [ctypes.c_double] * 5 + [dp, dp]
         L.orc_equilibrium.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, dp, dp, dp]
+        L.orc_noneq_init.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, dp, dp, ctypes.c_double, dp]
         L.orc_collide.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double, i64, dp, dp]
         L.orc_step.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] + [ctypes.c_int] * 3 + [dp, dp]
         L.orc_moments.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, dp, dp]
@@ -179,10 +180,27 @@ def collide(lat: Lattice, f, tau, coll=RR, order=None, thermal=False, a13_raw=Fa
     return out
 
 
+def noneq_init(lat: Lattice, rho, ux, uy, grad, tau, order=None) -> np.ndarray:
+    """f^(1) of the isothermal initial state from velocity gradients
+    grad[4, ...] = (dux/dx, dux/dy, duy/dx, duy/dy) (Sec. III.B, App. C)."""
+    order = lat.n_eq if order is None else order
+    rho, ux, uy = (np.ascontiguousarray(a, dtype=np.float64) for a in (rho, ux, uy))
+    g = np.ascontiguousarray(grad, dtype=np.float64).reshape(4, -1)
+    n = rho.size
+    f1 = np.zeros((lat.Q, n))
+    _check(lib().orc_noneq_init(lat.id, order, n, _p(rho), _p(ux), _p(uy), _p(g), tau, _p(f1)), "noneq_init")
+    return f1.reshape((lat.Q,) + rho.shape)
+
+
 def init_populations(lat: Lattice, rho, ux, uy, theta=None, noise=None, noise_amp=0.0,
-                     eq_order=None) -> np.ndarray:
-    """f = f^(0) (truncated at eq_order) + noise_amp * w_i * noise_i."""
+                     eq_order=None, grad=None, tau=None) -> np.ndarray:
+    """f = f^(0) (truncated at eq_order) [+ f^(1) from the velocity gradients
+    `grad` at relaxation time `tau`, same truncation] + noise_amp * w_i * noise_i."""
     f = equilibrium(lat, rho, ux, uy, theta, eq_order)
+    if grad is not None:
+        if theta is not None:
+            raise ValueError("the f^(1) initial state is isothermal")
+        f = f + noneq_init(lat, rho, ux, uy, grad, tau, eq_order)
     if noise is not None:
         f = f + noise_amp * lat.w.reshape((-1,) + (1,) * (f.ndim - 1)) * noise
     return np.ascontiguousarray(f)

@@ -502,6 +502,41 @@ int orc_recursion(int thermal, double rho, double ux, double uy, double theta, d
     return 0;
 }
 
+/* First-order part of the isothermal initial state (Sec. III.B:
+ * f ~ f^(0) + f^(1), f^(1) from analytic velocity gradients, expanded over the
+ * same Hermite terms as f^(0)).  grad[4][n] = (du_x/dx, du_x/dy, du_y/dx,
+ * du_y/dy) per node in lattice units; tau is the discrete relaxation time.
+ * a1^(2) = -tau [d_t a0^(2) + div a0^(3)] (Sec. II.E), which with the
+ * isothermal equilibrium and the Euler equations is -rho c_s^2 tau S,
+ * S = grad u + grad u^T (the traceless form of App. C is the thermal one;
+ * both agree for a divergence-free field); a1^(3), a1^(4) follow the
+ * isothermal recursion; f1[i*n + k] = w_i sum_{2 <= |k| <= order} ... */
+int orc_noneq_init(int id, int order, int64_t n, const double* rho, const double* ux, const double* uy,
+                   const double* grad, double tau, double* f1)
+{
+    orc_lattice_t L;
+    if (build_lattice(id, &L)) return -1;
+    if (order < 2 || order > L.n_eq) return -2;
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        double a0[ORC_NT], a1[ORC_NT], fl[ORC_MAXQ];
+        const double u[2] = { ux[k], uy[k] };
+        /* du[a][b] = d u_b / d x_a */
+        const double du[2][2] = { { grad[0 * n + k], grad[2 * n + k] }, { grad[1 * n + k], grad[3 * n + k] } };
+        eq_coeffs(&L, rho[k], u[0], u[1], 1.0, a0);
+        for (int t = 0; t < ORC_NT; ++t) a1[t] = 0.0;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                a1[toff(2, pair_bits(a, b))] = -rho[k] * L.cs2 * tau * (du[a][b] + du[b][a]);
+        rr_isothermal(u, rho[k], a0, a1);
+        for (int t = 0; t < ORC_NT; ++t)
+            if (t >= toff(order + 1, 0)) a1[t] = 0.0;
+        hermite_sum(&L, a1, order, fl);
+        for (int i = 0; i < L.Q; ++i) f1[(int64_t)i * n + k] = fl[i];
+    }
+    return 0;
+}
+
 /* Equilibrium populations truncated at Hermite order `order` for n_nodes
  * nodes: feq[i*n + k].  theta may be NULL (isothermal). */
 int orc_equilibrium(int id, int order, int64_t n, const double* rho, const double* ux,

@@ -31,6 +31,20 @@ def shear_layer_fields(nx: int, ny: int, u0: float, k: float = 80.0, delta: floa
     return rho, ux, uy
 
 
+def shear_layer_gradients(nx: int, ny: int, u0: float, k: float = 80.0, delta: float = 0.05,
+                          phase: float = 0.0):
+    """Analytic velocity gradients of `shear_layer_fields` in lattice units
+    (per node spacing): array [4, ny, nx] = (dux/dx, dux/dy, duy/dx, duy/dy)."""
+    x = cell_centres(nx)[None, :]
+    y = cell_centres(ny)[:, None]
+    dux_dy = np.where(y <= 0.5, u0 * k / np.cosh(k * (y - 0.25)) ** 2, -u0 * k / np.cosh(k * (0.75 - y)) ** 2) / ny
+    duy_dx = u0 * delta * 2.0 * np.pi * np.cos(2.0 * np.pi * (x + 0.25 + phase)) / nx
+    g = np.zeros((4, ny, nx))
+    g[1] = np.broadcast_to(dux_dy, (ny, nx))
+    g[2] = np.broadcast_to(duy_dx, (ny, nx))
+    return g
+
+
 def shear_layer_params(cs2: float, n: int, re: float, mach: float = 0.1):
     """Characteristic speed u0 = Mach * c_s and the discrete relaxation time
     giving Re = u0 n / nu with nu = c_s^2 (tau - 1/2) (isothermal)."""
