@@ -313,7 +313,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
-    ap.add_argument("--no-studies", action="store_true", help="skip the precision and Sod studies")
+    ap.add_argument("--no-studies", action="store_true", help="skip the precision, Sod and stability studies")
     ap.add_argument("--closure", choices=["full", "small", "none"], default="full",
                     help="learned-closure study: D2V37 256^2 coarse / 1024^2 fine (full) or 64^2 / 256^2")
     ap.add_argument("--copy-only", action="store_true", help="only run 1 GiB device copies (counter calibration)")
@@ -416,6 +416,7 @@ def main():
 
         out["precision"] = studies.precision_study(torch)
         out["sod"] = studies.sod_study(torch)
+        out["stability"] = studies.stability_range(torch)
     if args.closure != "none":
         from paper_1704_04413_amd import closure as cl
 

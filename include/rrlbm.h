@@ -97,14 +97,20 @@ int64_t lbm_buffer_elems(int lattice, int nx, int ny);
  *              must stay valid until lbm_destroy.
  *   rho,ux,uy  device FP64 fields of the initial state.
  *   theta      device FP64 field of theta = T/T_0 (thermal), or NULL (= 1).
+ *   grad       device FP64 array [4][y][x] of the velocity gradients
+ *              (du_x/dx, du_x/dy, du_y/dx, du_y/dy) in lattice units, or NULL.
+ *              When given (isothermal only, else LBM_EINVAL) the initial
+ *              state is f^(0) + f^(1) (Sec. III.B): f^(1) expands
+ *              a1^(2) = -rho c_s^2 tau (grad u + grad u^T) and the recursive
+ *              a1^(3), a1^(4) over the same Hermite terms as f^(0).
  *   noise      device FP64 array [i][y][x] or NULL; the initial populations are
- *              f^(0)(rho, u, theta) + noise_amp * w_i * noise.
+ *              f^(0)(rho, u, theta) [+ f^(1)] + noise_amp * w_i * noise.
  *   stream     hipStream_t for every launch of this context.
  * The buffer then holds the post-collision populations of step 0.  *out is
  * set only on success. */
 int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_order, uint32_t flags,
              void* f_a, void* f_b, const double* rho, const double* ux, const double* uy,
-             const double* theta, const double* noise, double noise_amp, void* stream);
+             const double* theta, const double* grad, const double* noise, double noise_amp, void* stream);
 
 /* Advances nsteps (>= 0) time steps: each is one fused launch that gathers
  * f_i(x - c_i) (periodic pull), regularizes, relaxes and stores.  Returns

@@ -59,7 +59,7 @@ def lib():
         L.lbm_buffer_elems.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
         L.lbm_buffer_elems.restype = ctypes.c_int64
         L.lbm_init.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                               ctypes.c_int, ctypes.c_uint32, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp]
+                               ctypes.c_int, ctypes.c_uint32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp]
         L.lbm_step.argtypes = [vp, ctypes.c_int]
         L.lbm_step_count.argtypes = [vp]
         L.lbm_step_count.restype = ctypes.c_int64
@@ -130,13 +130,14 @@ def lbm_buffer_elems(lattice, nx, ny) -> int:
     return int(n)
 
 
-def lbm_init(lattice, nx, ny, tau, reg_order, flags, f_a, f_b, rho, ux, uy, theta=None, noise=None,
+def lbm_init(lattice, nx, ny, tau, reg_order, flags, f_a, f_b, rho, ux, uy, theta=None, grad=None, noise=None,
              noise_amp=0.0, stream=None):
     """Returns the context handle (an integer)."""
     ctx = ctypes.c_void_p()
     s = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
     _check(lib().lbm_init(ctypes.byref(ctx), lattice_id(lattice), nx, ny, tau, reg_order, flags, _ptr(f_a),
-                          _ptr(f_b), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), _ptr(noise), noise_amp, s))
+                          _ptr(f_b), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), _ptr(grad), _ptr(noise),
+                          noise_amp, s))
     return ctx.value
 
 
@@ -249,7 +250,7 @@ class Simulation:
     """Owns the two population buffers (torch tensors) and one context."""
 
     def __init__(self, lattice, nx, ny, tau, rho, ux, uy, theta=None, noise=None, noise_amp=0.0,
-                 reg_order=None, flags=0, device="cuda:0", stream=None):
+                 reg_order=None, flags=0, device="cuda:0", stream=None, grad=None):
         import torch
 
         self.torch = torch
@@ -270,7 +271,7 @@ class Simulation:
             t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)) if isinstance(a, np.ndarray) else a
             return t.to(self.device, torch.float64).contiguous()
 
-        fields = [dev(a) for a in (rho, ux, uy, theta, noise)]
+        fields = [dev(a) for a in (rho, ux, uy, theta, grad, noise)]
         self.ctx = lbm_init(self.lattice, nx, ny, tau, self.reg_order, flags, self.bufs[0], self.bufs[1],
                             *fields, noise_amp=noise_amp, stream=self.stream)
         self._keep = fields  # inputs must outlive the asynchronous init

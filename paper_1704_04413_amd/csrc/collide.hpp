@@ -156,6 +156,24 @@ struct NodeCoeffs {
     T a1[5][5];
 };
 
+// Isothermal recursion (Eq. MalaspinasRecursiveRelation at theta = 1, in the
+// 2D closed forms of App. C): a1^(3), a1^(4) from u and a1^(2).
+template <class T>
+__device__ __forceinline__ void iso_recursion(T ux, T uy, T (&a1)[5][5])
+{
+    const T xx = a1[2][0], xy = a1[1][1], yy = a1[0][2];
+    const T uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
+    a1[3][0] = T(3) * ux * xx;
+    a1[2][1] = T(2) * ux * xy + uy * xx;
+    a1[1][2] = T(2) * uy * xy + ux * yy;
+    a1[0][3] = T(3) * uy * yy;
+    a1[4][0] = T(6) * uxx * xx;
+    a1[3][1] = T(3) * (uxx * xy + uxy * xx);
+    a1[2][2] = uyy * xx + uxx * yy + T(4) * uxy * xy;
+    a1[1][3] = T(3) * (uyy * xy + uxy * yy);
+    a1[0][4] = T(6) * uyy * yy;
+}
+
 template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
 __device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k)
 {
@@ -241,18 +259,7 @@ __device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k
             if constexpr (L::basis(2, 2)) a1[2][2] = h22 - C[2][2];
         }
     } else if constexpr (!THERMAL) {
-        // isothermal recursion, closed forms
-        const T xx = a1[2][0], xy = a1[1][1], yy = a1[0][2];
-        const T uxx = ux * ux, uyy = uy * uy, uxy = ux * uy;
-        a1[3][0] = T(3) * ux * xx;
-        a1[2][1] = T(2) * ux * xy + uy * xx;
-        a1[1][2] = T(2) * uy * xy + ux * yy;
-        a1[0][3] = T(3) * uy * yy;
-        a1[4][0] = T(6) * uxx * xx;
-        a1[3][1] = T(3) * (uxx * xy + uxy * xx);
-        a1[2][2] = uyy * xx + uxx * yy + T(4) * uxy * xy;
-        a1[1][3] = T(3) * (uyy * xy + uxy * yy);
-        a1[0][4] = T(6) * uyy * yy;
+        iso_recursion<T>(ux, uy, a1);
     } else {
         // thermal path of App. C
         const T xx = a1[2][0], xy = a1[1][1], yy = a1[0][2];
@@ -398,6 +405,37 @@ __device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, in
     }
     relax_reconstruct<L, T>(k, keep, order, v);
     inv.restore(v);
+}
+
+// First-order (Chapman-Enskog) part of an isothermal initial state (Sec.
+// III.B): f^(1)_i = w_i sum_{2 <= |k| <= order} H^k_i a1^k / norm_k with
+// a1^(2) = -rho c_s^2 tau (grad u + grad u^T) (the relation of Sec. II.E for
+// the isothermal equilibrium; du[a][b] = d u_b / d x_a in lattice units) and
+// a1^(3), a1^(4) from the isothermal recursion, over the terms of f^(0).
+template <class L, class T>
+__device__ __forceinline__ void noneq_init_node(T rho, T ux, T uy, const T (&du)[2][2], T tau, int order,
+                                                T (&out)[L::Q])
+{
+    constexpr T cs2 = T(L::cs2);
+    const T m = -rho * cs2 * tau;
+    T a1[5][5];
+    static_for<5>([&](auto a) { static_for<5>([&](auto b) { a1[a][b] = T(0); }); });
+    a1[2][0] = m * T(2) * du[0][0];
+    a1[1][1] = m * (du[0][1] + du[1][0]);
+    a1[0][2] = m * T(2) * du[1][1];
+    iso_recursion<T>(ux, uy, a1);
+    T C[5][5];
+    zero_coeffs<L, T>(C);
+    static_for<5>([&](auto KX) {
+        static_for<5>([&](auto KY) {
+            constexpr int n = int(KX) + int(KY);
+            if constexpr (L::basis(int(KX), int(KY)) && n >= 2) {
+                constexpr double nrm = inv_norm<L>(int(KX), int(KY));
+                C[KX][KY] = (n <= order) ? a1[KX][KY] * T(nrm) : T(0);
+            }
+        });
+    });
+    reconstruct<L, T>(C, out);
 }
 
 // Equilibrium populations truncated at Hermite rank `order` (initial state).

@@ -300,9 +300,10 @@ namespace rr {
 struct InitArgs {
     void* f;
     Layout lay;
-    const double *rho, *ux, *uy, *theta, *noise;
+    const double *rho, *ux, *uy, *theta, *grad, *noise;
     double noise_amp;
     int eq_order;
+    double tau;
 };
 
 template <class L, class S>
@@ -315,6 +316,12 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
     double f[L::Q];
     const double th = a.theta ? a.theta[k] : 1.0;
     equilibrium_node<L, double, S::shifted>(a.rho[k], a.ux[k], a.uy[k], th, a.eq_order, f);
+    if (a.grad) {
+        const double du[2][2] = { { a.grad[k], a.grad[2 * n + k] }, { a.grad[n + k], a.grad[3 * n + k] } };
+        double f1[L::Q];
+        noneq_init_node<L, double>(a.rho[k], a.ux[k], a.uy[k], du, a.tau, a.eq_order, f1);
+        static_for<L::Q>([&](auto I) { f[I] += f1[I]; });
+    }
     typename S::elem* out = static_cast<typename S::elem*>(a.f);
     static_for<L::Q>([&](auto I) {
         double v = f[I];
@@ -696,7 +703,7 @@ int64_t lbm_buffer_elems(int lattice, int nx, int ny)
 
 int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_order, uint32_t flags,
              void* f_a, void* f_b, const double* rho, const double* ux, const double* uy,
-             const double* theta, const double* noise, double noise_amp, void* stream)
+             const double* theta, const double* grad, const double* noise, double noise_amp, void* stream)
 {
     if (!out) return fail(LBM_EINVAL, "out is NULL");
     LatInfo li;
@@ -706,6 +713,8 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     if (!rho || !ux || !uy) return fail(LBM_EINVAL, "rho, ux and uy are required");
     if ((flags & LBM_THERMAL) == 0 && theta)
         return fail(LBM_EINVAL, "theta given for an isothermal run");
+    if ((flags & LBM_THERMAL) && grad)
+        return fail(LBM_EINVAL, "the f^(1) initial state from velocity gradients is isothermal");
     if (!std::isfinite(noise_amp)) return fail(LBM_EINVAL, "noise_amp not finite");
 
     lbm_ctx* c = new (std::nothrow) lbm_ctx;
@@ -730,8 +739,8 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     const int64_t n = int64_t(nx) * ny;
     c->nblk = (n + 255) / 256;
 
-    InitArgs ia{ f_a, c->lay, rho, ux, uy, theta, noise, noise_amp,
-                 (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq };
+    InitArgs ia{ f_a, c->lay, rho, ux, uy, theta, grad, noise, noise_amp,
+                 (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq, tau };
     hipError_t he = dispatch_ls<InitOp>(c, ia);
     if (he == hipSuccess) he = launch_step(c, f_a, f_a, false); // collide in place: post-collision state
     if (he != hipSuccess) {

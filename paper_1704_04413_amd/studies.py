@@ -121,3 +121,81 @@ def sod_study(torch, taus=(0.5005, 0.51, 0.55, 0.595), steps=800):
             row[st] = dict(blow_up_step=r["blow_up_step"], seconds=round(time.perf_counter() - t0, 2))
         rows.append(row)
     return rows
+
+
+def shear_stable(torch, lattice, n, re, mach, flags, order, every=25, noneq_start=True):
+    """The paper's stability criterion for the doubly periodic shear layer
+    (Sec. III.B): stable if <|u|^2>(t) < <|u|^2>(0) for every t <= 2 t_c,
+    t_c = n / (M0 c_s), and no node turns non-finite (checked every `every`
+    steps).  The run starts from f^(0) + f^(1) with the analytic velocity
+    gradients, as in the paper (from f^(0) alone if not `noneq_start`)."""
+    q, _, _, cs2 = b.lbm_lattice_info(lattice)
+    u0, tau = wl.shear_layer_params(cs2, n, re, mach)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    grad = wl.shear_layer_gradients(n, n, u0) if noneq_start else None
+    sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, noise=wl.uniform_noise(0, q, n, n), noise_amp=1e-8,
+                       reg_order=order, flags=flags, grad=grad)
+    horizon = int(np.ceil(2.0 * n / u0))
+    u2_0 = None
+    ok = True
+    while True:
+        s = sim.moments(vorticity=False)["sums"]
+        u2 = s[4]
+        u2_0 = u2 if u2_0 is None else u2_0
+        if s[8] > 0 or not np.isfinite(u2) or (sim.steps > 0 and u2 >= u2_0):
+            ok = False
+            break
+        if sim.steps >= horizon:
+            break
+        sim.step(min(every, horizon - sim.steps))
+    sim.close()
+    return ok
+
+
+COLLISIONS = {"BGK": b.LBM_COLL_BGK, "PR": b.LBM_COLL_PR, "RR": 0}
+
+
+def max_stable_mach(torch, lattice, coll, order, re, n=128, lo=0.05, hi=1.6, tol=0.01, noneq_start=True):
+    """Largest M0 (to `tol`, Fig. 5 uses 0.01) for which the shear layer at
+    Re on n^2 nodes stays stable, by bisection between `lo` and `hi`.
+    Returns (M0max, runs); M0max = 0 if `lo` already fails, `hi` if it holds."""
+    flags, runs = COLLISIONS[coll], 0
+
+    def stable(m):
+        nonlocal runs
+        runs += 1
+        return shear_stable(torch, lattice, n, re, m, flags, order, noneq_start=noneq_start)
+
+    if not stable(lo):
+        return 0.0, runs
+    if stable(hi):
+        return hi, runs
+    while hi - lo > tol + 1e-9:
+        mid = round(0.5 * (lo + hi), 4)
+        if stable(mid):
+            lo = mid
+        else:
+            hi = mid
+    return round(lo, 4), runs
+
+
+def stability_range(torch, res=(1e4, 3e4, 1e5, 3e5, 1e6), n=128, noneq_start=True):
+    """M0max against Re for BGK, PR at the lattice's full order and RR at every
+    order 2..N_eq, on D2Q9, D2V17 and D2V37 (the study of Fig. 5)."""
+    variants = []
+    for lat in ("D2Q9", "D2V17", "D2V37"):
+        n_eq = b.lbm_lattice_info(lat)[2]
+        variants.append((lat, "BGK", 2))
+        variants.append((lat, "PR", n_eq))
+        variants += [(lat, "RR", k) for k in range(2, n_eq + 1)]
+    rows = []
+    t0 = time.perf_counter()
+    for lat, coll, order in variants:
+        row = dict(lattice=lat, collision=coll, order=order, m0_max={})
+        for re in res:
+            m, runs = max_stable_mach(torch, lat, coll, order, re, n, noneq_start=noneq_start)
+            row["m0_max"][f"{re:.0e}"] = m
+        rows.append(row)
+    return dict(n=n, criterion="<u^2>(t) < <u^2>(0) for t <= 2 n/(M0 c_s), no non-finite node",
+                start="f0+f1" if noneq_start else "f0", resolution=0.01, rows=rows,
+                seconds=round(time.perf_counter() - t0, 1))

@@ -77,6 +77,7 @@ class FakePtr:
     (dict(lattice=1, reg_order=4), b.LBM_EINVAL),          # D2V17 stops at rank 3
     (dict(same_buffers=True), b.LBM_EINVAL),
     (dict(no_rho=True), b.LBM_EINVAL),
+    (dict(flags=b.LBM_THERMAL, grad=True), b.LBM_EINVAL),  # the f^(1) start is isothermal
 ])
 def test_init_rejects_invalid_arguments(args, code):
     p = dict(lattice=2, nx=8, ny=8, tau=0.6, reg_order=4, flags=0)
@@ -87,7 +88,7 @@ def test_init_rejects_invalid_arguments(args, code):
     rho = None if args.get("no_rho") else FakePtr(0x3000)
     with pytest.raises(b.LbmError) as e:
         b.lbm_init(p["lattice"], p["nx"], p["ny"], p["tau"], p["reg_order"], p["flags"], fa, fb, rho,
-                   FakePtr(0x4000), FakePtr(0x5000))
+                   FakePtr(0x4000), FakePtr(0x5000), grad=FakePtr(0x6000) if args.get("grad") else None)
     assert e.value.code == code
     assert b.lbm_last_error()
 
