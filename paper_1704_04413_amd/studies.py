@@ -89,12 +89,13 @@ def precision_study(torch, lattices=("D2V17", "D2V37"), sizes=(512, 1024), res=(
     return dict(rows=out, steps=steps, seconds=round(time.perf_counter() - t0, 1))
 
 
-def sod_run(torch, tau, storage="fp64", nx=2000, ny=4, steps=800, snap=None, theta_left=0.5, every=50):
-    """Thermal D2V37 Sod tube (rho, p)_L = (8, 10), (1, 1)_R, u = 0, interface
-    at nx/2, periodic.  Returns the blow-up step (first check with a
+def sod_run(torch, tau, storage="fp64", nx=2000, ny=4, steps=800, snap=None, theta_left=0.5, every=50,
+            rho_l=8.0, p_l=10.0):
+    """Thermal D2V37 Sod tube (rho, p)_L = (rho_l, p_l), (1, 1)_R, u = 0,
+    interface at nx/2, periodic.  Returns the blow-up step (first check with a
     non-finite node or theta <= 0) and y-averaged rho, u, theta at `snap`."""
     q, _, _, cs2 = b.lbm_lattice_info("D2V37")
-    rho, ux, uy, th = wl.sod_fields(nx, ny, theta_left=theta_left)
+    rho, ux, uy, th = wl.sod_fields(nx, ny, rho_l=rho_l, p_l=p_l, theta_left=theta_left)
     sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_THERMAL | STORE[storage])
     blow, prof = None, None
     marks = sorted(set(range(0, steps + 1, every)) | ({snap} if snap else set()))
@@ -110,8 +111,50 @@ def sod_run(torch, tau, storage="fp64", nx=2000, ny=4, steps=800, snap=None, the
     return dict(blow_up_step=blow, profile=prof, cs2=cs2)
 
 
+# The paper's two Sod cases (Sec. III.C, Fig. 6): left state, tau, time of
+# the comparison in t_c = L_x / c_R, left temperature of the lattice scaling.
+SOD_CASES = {
+    "P10_rho8": dict(rho_l=8.0, p_l=10.0, tau=0.595, t_over_tc=0.2, theta_left=0.5),
+    "P10_rho2": dict(rho_l=2.0, p_l=10.0, tau=0.760, t_over_tc=0.1, theta_left=1.0),
+}
+
+
+def sod_profiles(torch, case, storage="fp64", nx=2000, ny=4, exact=None):
+    """One of the paper's Sod cases at t = t_over_tc * L_x / c_R, L_x = nx / 2
+    (before the waves of the two interfaces meet).  Returns the step, the
+    blow-up step and the y-averaged profiles; with `exact` (a callable
+    (rho_l, p_l, u_l, rho_r, p_r, u_r, gamma, xi) -> (rho, u, p, ...), the
+    exact Riemann solution) also L1 errors over the cells [nx/4, 3nx/4) of rho
+    and p (relative to the mean exact value) and of u (relative to the
+    largest exact |u|)."""
+    c = SOD_CASES[case]
+    cs2 = b.lbm_lattice_info("D2V37")[3]
+    th_r = c["theta_left"] * c["rho_l"] / c["p_l"]
+    c_r = np.sqrt(2.0 * th_r * cs2)
+    t = int(round(c["t_over_tc"] * (nx / 2) / c_r))
+    r = sod_run(torch, c["tau"], storage, nx=nx, ny=ny, steps=t, snap=t, theta_left=c["theta_left"],
+                rho_l=c["rho_l"], p_l=c["p_l"])
+    out = dict(case=case, storage=storage, tau=c["tau"], theta_left=c["theta_left"], theta_right=th_r, step=t,
+               blow_up_step=r["blow_up_step"])
+    if r["blow_up_step"] is not None:
+        return out
+    pr = out["profile"] = r["profile"]
+    if exact is not None:
+        x = np.arange(nx) + 0.5
+        rho_e, u_e, p_e = exact(c["rho_l"], c["rho_l"] * cs2 * c["theta_left"], 0.0, 1.0, cs2 * th_r, 0.0, 2.0,
+                                (x - nx / 2) / t)[:3]
+        w = slice(nx // 4, 3 * nx // 4)
+        p = pr["rho"] * cs2 * pr["theta"]
+        l1 = lambda a, e: float(np.abs(a[w] - e[w]).mean() / np.abs(e[w]).mean())
+        out.update(l1_rho=l1(pr["rho"], rho_e), l1_p=l1(p, p_e),
+                   l1_u=float(np.abs(pr["ux"][w] - u_e[w]).mean() / np.abs(u_e[w]).max()))
+    return out
+
+
 def sod_study(torch, taus=(0.5005, 0.51, 0.55, 0.595), steps=800):
-    """Blow-up steps over `steps` and MLUPS, FP64 and FP32 storage."""
+    """Blow-up steps of the (8, 10) case over `steps` at each tau, FP64 and
+    FP32 storage, and both paper cases at their comparison time (blow-up,
+    FP32 against FP64)."""
     rows = []
     for tau in taus:
         row = dict(tau=tau)
@@ -120,7 +163,17 @@ def sod_study(torch, taus=(0.5005, 0.51, 0.55, 0.595), steps=800):
             r = sod_run(torch, tau, st, steps=steps)
             row[st] = dict(blow_up_step=r["blow_up_step"], seconds=round(time.perf_counter() - t0, 2))
         rows.append(row)
-    return rows
+    cases = []
+    for case in SOD_CASES:
+        r64 = sod_profiles(torch, case, "fp64")
+        r32 = sod_profiles(torch, case, "fp32")
+        row = {k: v for k, v in r64.items() if k not in ("profile", "storage")}
+        row["fp32_blow_up_step"] = r32["blow_up_step"]
+        if "profile" in r64 and "profile" in r32:
+            row["fp32_vs_fp64_max_rel_rho"] = float(np.abs(r32["profile"]["rho"] - r64["profile"]["rho"]).max()
+                                                    / r64["profile"]["rho"].max())
+        cases.append(row)
+    return dict(blow_up=rows, paper_cases=cases)
 
 
 def shear_stable(torch, lattice, n, re, mach, flags, order, every=25, noneq_start=True):

@@ -54,3 +54,21 @@ def test_sod_profiles_against_exact_solution(orc, env, tau):
           flush=True)
     assert e_rho <= 0.03 and e_p <= 0.03 and e_u <= 0.03
     assert d32 <= 1e-4
+
+
+@pytest.mark.parametrize("case", ["P10_rho8", "P10_rho2"])
+def test_sod_paper_cases(orc, env, case):
+    """Both Sod cases of the paper at their own tau and comparison time (Fig. 6:
+    (10, 8) at tau 0.595, t/t_c = 0.2; (10, 2) at tau 0.760, t/t_c = 0.1), on
+    the 2000 x 4 tube (L_x = 1000), against the exact solution."""
+    torch, st = env
+    print(f"[case] sod paper case {case}", flush=True)
+    r64 = st.sod_profiles(torch, case, "fp64", exact=orc.riemann_exact)
+    r32 = st.sod_profiles(torch, case, "fp32", exact=orc.riemann_exact)
+    assert r64["blow_up_step"] is None and r32["blow_up_step"] is None
+    d32 = float(np.abs(r32["profile"]["rho"] - r64["profile"]["rho"]).max() / r64["profile"]["rho"].max())
+    print(f"[sod] {case}: step {r64['step']}, theta L/R {r64['theta_left']}/{r64['theta_right']:.2f}: L1 rel rho "
+          f"{r64['l1_rho']:.4f} p {r64['l1_p']:.4f} u {r64['l1_u']:.4f}; FP32 L1 rho {r32['l1_rho']:.4f}; "
+          f"fp32 vs fp64 max rho {d32:.2e}", flush=True)
+    assert r64["l1_rho"] <= 0.03 and r64["l1_p"] <= 0.03 and r64["l1_u"] <= 0.03
+    assert d32 <= 1e-4
