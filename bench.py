@@ -28,8 +28,14 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS and % of HBM roofline per lattice; closure/low-precision vs plain at stated error"
-STORAGE_FLAGS = {"fp64": 0, "fp32": 0x2, "bf16": 0x4}
+STORAGE_FLAGS = {"fp64": 0, "fp32": 0x2, "bf16": 0x4, "moments": 0x8}
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+
+
+def bytes_per_node(q: int, storage: str) -> int:
+    """Algorithmic HBM bytes of one node update: every stored value read once
+    and written once (Q populations, or the six FP64 moments)."""
+    return 2 * 6 * 8 if storage == "moments" else 2 * q * STORAGE_BYTES[storage]
 
 
 def kernel_source_hash() -> str:
@@ -358,7 +364,7 @@ def main():
     sim.close()
     nodes = args.n * args.n
     mlups = nodes * args.steps / wall / 1e6
-    bytes_per_launch = 2 * meta["q"] * STORAGE_BYTES[args.storage] * nodes
+    bytes_per_launch = bytes_per_node(meta["q"], args.storage) * nodes
     kavg = kms * 1e-3
     achieved = bytes_per_launch / kavg / 1e9
     traffic = read_traffic(f"{args.lattice.lower()}_{args.storage}_{args.n}_traffic.txt")
@@ -398,12 +404,13 @@ def main():
         sweep = []
         cases = [("D2Q9", "fp64", False), ("D2V17", "fp64", False), ("D2V37", "fp64", False),
                  ("D2V37", "fp64", True), ("D2Q9", "fp32", False), ("D2V17", "fp32", False),
-                 ("D2V37", "fp32", False), ("D2V37", "bf16", False)]
+                 ("D2V37", "fp32", False), ("D2V37", "bf16", False), ("D2Q9", "moments", False),
+                 ("D2V17", "moments", False), ("D2V37", "moments", False)]
         for lat, st, th in cases:
             s2, m2 = make_sim(b, wl, lat, args.n, st, thermal=th)
             w2, k2 = time_steps(torch, s2, 50, 5)
             s2.close()
-            bpl = 2 * m2["q"] * STORAGE_BYTES[st] * nodes
+            bpl = bytes_per_node(m2["q"], st) * nodes
             gbs = bpl / (k2 * 1e-3) / 1e9
             sweep.append({"lattice": lat, "storage": st, "thermal": th, "MLUPS": round(nodes * 50 / w2 / 1e6, 1),
                           "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})

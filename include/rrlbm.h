@@ -33,7 +33,13 @@
  *   LBM_STORE_FP64 (default) keeps the plain populations f_i in double and does
  *   all arithmetic in double.  LBM_STORE_FP32 / LBM_STORE_BF16 keep the
  *   weight-shifted populations g_i = f_i - w_i in float / bfloat16 and do all
- *   arithmetic in float.
+ *   arithmetic in float.  LBM_STORE_MOMENTS (isothermal recursive
+ *   regularization only) keeps, per node, the six values (rho, u_x, u_y,
+ *   a1^(2)_xx, a1^(2)_xy, a1^(2)_yy) of the pre-collision populations in
+ *   double: with the recursion the post-collision populations are a function
+ *   of these alone (Eq. GenRegCollision, Eq. MalaspinasRecursiveRelation), so
+ *   a step rebuilds each pulled population from its source node's moments.
+ *   The sequence of states equals that of LBM_STORE_FP64 up to rounding.
  */
 #ifndef RRLBM_H
 #define RRLBM_H
@@ -55,6 +61,7 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_THERMAL 0x1u        /* thermal/compressible form; D2V37 only          */
 #define LBM_STORE_FP32 0x2u     /* store f - w in float, float arithmetic          */
 #define LBM_STORE_BF16 0x4u     /* store f - w in bfloat16, float arithmetic       */
+#define LBM_STORE_MOMENTS 0x8u  /* store (rho, u, a1^(2)) in double; isothermal RR */
 #define LBM_COLL_PR 0x10u       /* projection-based regularization (Sec. II.E)     */
 #define LBM_COLL_BGK 0x20u      /* BGK collision (Sec. III.A)                      */
 #define LBM_EQ_INIT_ORDER2 0x100u /* initial f^(0) truncated at Hermite order 2    */
@@ -77,10 +84,12 @@ int lbm_lattice_info(int lattice, int* q, int* reach, int* n_eq, double* cs2);
  * (any may be NULL). */
 int lbm_lattice_velocities(int lattice, int* cx, int* cy, double* w);
 
-/* Elements (of the storage type) one population buffer must hold for an
- * nx by ny grid: q * nx * (ny rounded up to a multiple of 4), the library's
- * row-tiled layout.  Negative on error. */
-int64_t lbm_buffer_elems(int lattice, int nx, int ny);
+/* Elements (of the storage type) one state buffer must hold for an nx by ny
+ * grid with the given LBM_STORE_* flags (other flag bits are ignored):
+ * q * nx * (ny rounded up to a multiple of 4) for populations, the library's
+ * row-tiled layout; 6 * nx * ny doubles for LBM_STORE_MOMENTS (six planes
+ * [m][y][x]).  Negative on error. */
+int64_t lbm_buffer_elems(int lattice, int nx, int ny, uint32_t flags);
 
 /* Creates a context and writes the initial state.
  *   lattice    LBM_D2Q9, LBM_D2V17 or LBM_D2V37.

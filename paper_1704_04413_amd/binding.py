@@ -19,6 +19,7 @@ LATTICES = {"D2Q9": LBM_D2Q9, "D2V17": LBM_D2V17, "D2V37": LBM_D2V37}
 LBM_THERMAL = 0x1
 LBM_STORE_FP32 = 0x2
 LBM_STORE_BF16 = 0x4
+LBM_STORE_MOMENTS = 0x8
 LBM_COLL_PR = 0x10
 LBM_COLL_BGK = 0x20
 LBM_EQ_INIT_ORDER2 = 0x100
@@ -56,7 +57,7 @@ def lib():
         vp, dp, ip = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int)
         L.lbm_lattice_info.argtypes = [ctypes.c_int, ip, ip, ip, dp]
         L.lbm_lattice_velocities.argtypes = [ctypes.c_int, ip, ip, dp]
-        L.lbm_buffer_elems.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int]
+        L.lbm_buffer_elems.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_uint32]
         L.lbm_buffer_elems.restype = ctypes.c_int64
         L.lbm_init.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                ctypes.c_int, ctypes.c_uint32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp]
@@ -123,8 +124,8 @@ def lbm_lattice_velocities(lattice):
     return np.array(list(cx)), np.array(list(cy)), np.array(list(w))
 
 
-def lbm_buffer_elems(lattice, nx, ny) -> int:
-    n = lib().lbm_buffer_elems(lattice_id(lattice), nx, ny)
+def lbm_buffer_elems(lattice, nx, ny, flags=0) -> int:
+    n = lib().lbm_buffer_elems(lattice_id(lattice), nx, ny, flags)
     if n < 0:
         raise LbmError(int(n), lbm_last_error())
     return int(n)
@@ -262,7 +263,7 @@ class Simulation:
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         dtype = (torch.float32 if flags & LBM_STORE_FP32 else
                  torch.bfloat16 if flags & LBM_STORE_BF16 else torch.float64)
-        n = lbm_buffer_elems(self.lattice, nx, ny)
+        n = lbm_buffer_elems(self.lattice, nx, ny, flags)
         self.bufs = [torch.empty(n, dtype=dtype, device=self.device) for _ in range(2)]
 
         def dev(a):

@@ -330,6 +330,12 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
     });
 }
 
+} // namespace rr
+
+#include "moments.hpp"
+
+namespace rr {
+
 // --------------------------------------------------- populations / moments
 
 template <class L, class S>
@@ -365,6 +371,50 @@ __device__ __forceinline__ void block_sums(double (&val)[NS], double* partial)
     if (t < NS) partial[int64_t(blockIdx.x) * NS + t] = red[t][0];
 }
 
+template <class L, int ORDER>
+__global__ __launch_bounds__(256) void k_mom_populations(const double* m, int64_t n, double keep, double* out)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    double v[L::Q];
+    mom_node_populations<L, ORDER>(m, n, k, keep, v);
+    static_for<L::Q>([&](auto I) { out[int64_t(I) * n + k] = v[I]; });
+}
+
+// Diagnostics of one node from its post-collision populations v.
+template <class L>
+__device__ __forceinline__ void node_diag(const double (&v)[L::Q], int thermal, int64_t k, double* rho_o,
+                                          double* ux_o, double* uy_o, double* th_o, double (&val)[MOM_NS])
+{
+    double r = 0, jx = 0, jy = 0, e2 = 0;
+    static_for<L::Q>([&](auto I) {
+        constexpr double cx = L::v.cx[I], cy = L::v.cy[I];
+        r += v[I];
+        jx += cx * v[I];
+        jy += cy * v[I];
+        e2 += (cx * cx + cy * cy) * v[I];
+    });
+    const double ux = jx / r, uy = jy / r;
+    const double u2 = ux * ux + uy * uy;
+    const double th = thermal ? (e2 - r * u2) / (2.0 * r * L::cs2) : 1.0;
+    rho_o[k] = r;
+    ux_o[k] = ux;
+    uy_o[k] = uy;
+    th_o[k] = th;
+    const bool finite = std::isfinite(r) && std::isfinite(ux) && std::isfinite(uy) && std::isfinite(th);
+    if (finite) {
+        val[0] = r;
+        val[1] = jx;
+        val[2] = jy;
+        val[3] = 0.5 * e2;
+        val[4] = u2;
+        val[5] = u2 * u2;
+        val[7] = th;
+    } else {
+        val[6] = 1.0;
+    }
+}
+
 // rho, u, theta per node (FP64 arithmetic whatever the storage) and block sums
 // of [rho, rho ux, rho uy, sum f|c|^2/2, |u|^2, |u|^4, non-finite, theta].
 template <class L, class S>
@@ -377,35 +427,27 @@ __global__ __launch_bounds__(256) void k_moments(const void* fsrc, Layout lay, i
     if (k < n) {
         const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
         const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
-        double r = 0, jx = 0, jy = 0, e2 = 0;
+        double v[L::Q];
         static_for<L::Q>([&](auto I) {
-            double v = double(S::load(f + here + int(I) * lay.te));
-            if (S::shifted) v += L::v.w[I];
-            constexpr double cx = L::v.cx[I], cy = L::v.cy[I];
-            r += v;
-            jx += cx * v;
-            jy += cy * v;
-            e2 += (cx * cx + cy * cy) * v;
+            v[I] = double(S::load(f + here + int(I) * lay.te));
+            if (S::shifted) v[I] += L::v.w[I];
         });
-        const double ux = jx / r, uy = jy / r;
-        const double u2 = ux * ux + uy * uy;
-        const double th = thermal ? (e2 - r * u2) / (2.0 * r * L::cs2) : 1.0;
-        rho_o[k] = r;
-        ux_o[k] = ux;
-        uy_o[k] = uy;
-        th_o[k] = th;
-        const bool finite = std::isfinite(r) && std::isfinite(ux) && std::isfinite(uy) && std::isfinite(th);
-        if (finite) {
-            val[0] = r;
-            val[1] = jx;
-            val[2] = jy;
-            val[3] = 0.5 * e2;
-            val[4] = u2;
-            val[5] = u2 * u2;
-            val[7] = th;
-        } else {
-            val[6] = 1.0;
-        }
+        node_diag<L>(v, thermal, k, rho_o, ux_o, uy_o, th_o, val);
+    }
+    block_sums<MOM_NS>(val, partial);
+}
+
+// The same from the moment representation.
+template <class L, int ORDER>
+__global__ __launch_bounds__(256) void k_mom_moments(const double* m, int64_t n, double keep, double* rho_o,
+                                                     double* ux_o, double* uy_o, double* th_o, double* partial)
+{
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double val[MOM_NS] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    if (k < n) {
+        double v[L::Q];
+        mom_node_populations<L, ORDER>(m, n, k, keep, v);
+        node_diag<L>(v, 0, k, rho_o, ux_o, uy_o, th_o, val);
     }
     block_sums<MOM_NS>(val, partial);
 }
@@ -458,7 +500,7 @@ int fail(int code, const std::string& msg)
         if (e_ != hipSuccess) return fail(LBM_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
 
-enum StoreKind { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2 };
+enum StoreKind { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_MOM = 3 };
 
 struct LatInfo {
     int q, reach, n_eq;
@@ -510,6 +552,54 @@ struct lbm_ctx {
 };
 
 namespace {
+
+// ---- moment representation: per-lattice launches (order as a template argument)
+template <class L, int ORDER>
+hipError_t mom_launch(const lbm_ctx* c, int what, const void* fin, void* fout, InitArgs* ia, double* out, double* r,
+                      double* ux, double* uy, double* th)
+{
+    const int64_t n = int64_t(c->nx) * c->ny;
+    const double keep = 1.0 - 1.0 / c->tau;
+    const double* m = static_cast<const double*>(c->buf[c->cur]);
+    const dim3 grid(unsigned((n + 255) / 256)), block(256);
+    switch (what) {
+    case 0: k_mom_init<L><<<grid, block, 0, c->stream>>>(*ia); break;
+    case 1: k_mom_populations<L, ORDER><<<grid, block, 0, c->stream>>>(m, n, keep, out); break;
+    case 2:
+        k_mom_moments<L, ORDER><<<dim3(unsigned(c->nblk)), block, 0, c->stream>>>(m, n, keep, r, ux, uy, th,
+                                                                                 c->partial);
+        break;
+    default: {
+        const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
+        k_mom_step<L, ORDER><<<dim3(unsigned(bxn * byn)), dim3(BX, BY), 0, c->stream>>>(
+            static_cast<const double*>(fin), static_cast<double*>(fout), c->nx, c->ny, bxn, keep);
+    }
+    }
+    return hipGetLastError();
+}
+
+template <class L>
+hipError_t mom_launch_l(const lbm_ctx* c, int what, const void* fin, void* fout, InitArgs* ia, double* out,
+                        double* r, double* ux, double* uy, double* th)
+{
+    switch (c->order) {
+    case 2: return mom_launch<L, 2>(c, what, fin, fout, ia, out, r, ux, uy, th);
+    case 3: return mom_launch<L, 3>(c, what, fin, fout, ia, out, r, ux, uy, th);
+    default: return mom_launch<L, 4>(c, what, fin, fout, ia, out, r, ux, uy, th);
+    }
+}
+
+// what: 0 initial state (ia), 1 populations (out), 2 diagnostics (r, ux, uy, th), 3 step (fin -> fout)
+hipError_t mom_launch_any(const lbm_ctx* c, int what, const void* fin = nullptr, void* fout = nullptr,
+                          InitArgs* ia = nullptr, double* out = nullptr, double* r = nullptr, double* ux = nullptr,
+                          double* uy = nullptr, double* th = nullptr)
+{
+    switch (c->lattice) {
+    case LBM_D2Q9: return mom_launch_l<D2Q9>(c, what, fin, fout, ia, out, r, ux, uy, th);
+    case LBM_D2V17: return mom_launch_l<D2V17>(c, what, fin, fout, ia, out, r, ux, uy, th);
+    default: return mom_launch_l<D2V37>(c, what, fin, fout, ia, out, r, ux, uy, th);
+    }
+}
 
 template <class L, class S, int COLL, bool TH, bool A13P>
 hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
@@ -565,6 +655,7 @@ hipError_t launch_step_l(const lbm_ctx* c, const void* fin, void* fout, bool pul
 
 hipError_t launch_step(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
+    if (c->store == ST_MOM) return mom_launch_any(c, 3, fin, fout);
     switch (c->lattice) {
     case LBM_D2Q9: return launch_step_l<D2Q9>(c, fin, fout, pull);
     case LBM_D2V17: return launch_step_l<D2V17>(c, fin, fout, pull);
@@ -637,10 +728,13 @@ int validate(int lattice, int nx, int ny, double tau, int reg_order, uint32_t fl
                                     " smaller than the lattice reach " + std::to_string(li->reach));
     if (layout_elems(li->q, nx, ny) >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "grid too large");
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_ETAU, "tau must be finite and > 1/2");
-    const uint32_t known = LBM_THERMAL | LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_COLL_PR | LBM_COLL_BGK |
-                           LBM_EQ_INIT_ORDER2 | LBM_A13_PROJECTED;
+    const uint32_t known = LBM_THERMAL | LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS | LBM_COLL_PR |
+                           LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_A13_PROJECTED;
     if (flags & ~known) return fail(LBM_EINVAL, "unknown flag bits");
-    if ((flags & LBM_STORE_FP32) && (flags & LBM_STORE_BF16)) return fail(LBM_EINVAL, "two storage flags");
+    const uint32_t stores = flags & (LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS);
+    if (stores & (stores - 1)) return fail(LBM_EINVAL, "two storage flags");
+    if ((flags & LBM_STORE_MOMENTS) && (flags & (LBM_THERMAL | LBM_COLL_PR | LBM_COLL_BGK | LBM_A13_PROJECTED)))
+        return fail(LBM_EINVAL, "the moment representation is isothermal recursive regularization only");
     if ((flags & LBM_COLL_PR) && (flags & LBM_COLL_BGK)) return fail(LBM_EINVAL, "two collision flags");
     if ((flags & LBM_THERMAL) && lattice != LBM_D2V37)
         return fail(LBM_EINVAL, "the thermal form needs the D2V37 lattice");
@@ -693,11 +787,12 @@ int lbm_lattice_velocities(int lattice, int* cx, int* cy, double* w)
     return LBM_OK;
 }
 
-int64_t lbm_buffer_elems(int lattice, int nx, int ny)
+int64_t lbm_buffer_elems(int lattice, int nx, int ny, uint32_t flags)
 {
     LatInfo li;
     if (!lattice_info(lattice, &li)) return fail(LBM_EINVAL, "unknown lattice");
     if (nx < 1 || ny < 1) return fail(LBM_EINVAL, "empty grid");
+    if (flags & LBM_STORE_MOMENTS) return int64_t(MOM_K) * nx * ny;
     return layout_elems(li.q, nx, ny);
 }
 
@@ -725,7 +820,10 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     c->tau = tau;
     c->order = (flags & LBM_COLL_BGK) ? 2 : reg_order;
     c->flags = flags;
-    c->store = (flags & LBM_STORE_FP32) ? ST_F32 : (flags & LBM_STORE_BF16) ? ST_BF16 : ST_F64;
+    c->store = (flags & LBM_STORE_FP32)      ? ST_F32
+               : (flags & LBM_STORE_BF16)    ? ST_BF16
+               : (flags & LBM_STORE_MOMENTS) ? ST_MOM
+                                             : ST_F64;
     c->coll = (flags & LBM_COLL_PR) ? COLL_PR : (flags & LBM_COLL_BGK) ? COLL_BGK : COLL_RR;
     c->thermal = (flags & LBM_THERMAL) != 0;
     c->a13p = (flags & LBM_A13_PROJECTED) != 0;
@@ -741,8 +839,13 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
 
     InitArgs ia{ f_a, c->lay, rho, ux, uy, theta, grad, noise, noise_amp,
                  (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq, tau };
-    hipError_t he = dispatch_ls<InitOp>(c, ia);
-    if (he == hipSuccess) he = launch_step(c, f_a, f_a, false); // collide in place: post-collision state
+    hipError_t he = hipSuccess;
+    if (c->store == ST_MOM) {
+        he = mom_launch_any(c, 0, nullptr, nullptr, &ia); // the moments are the state: no collision here
+    } else {
+        he = dispatch_ls<InitOp>(c, ia);
+        if (he == hipSuccess) he = launch_step(c, f_a, f_a, false); // collide in place: post-collision state
+    }
     if (he != hipSuccess) {
         delete c;
         return fail(LBM_EDEVICE, std::string("init launch: ") + hipGetErrorString(he));
@@ -779,7 +882,10 @@ int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* theta, 
     double* vx = ux ? ux : c->fields + n;
     double* vy = uy ? uy : c->fields + 2 * n;
     double* th = theta ? theta : c->fields + 3 * n;
-    HIP_TRY(dispatch_ls<MomOp>(c, r, vx, vy, th));
+    if (c->store == ST_MOM)
+        HIP_TRY(mom_launch_any(c, 2, nullptr, nullptr, nullptr, nullptr, r, vx, vy, th));
+    else
+        HIP_TRY(dispatch_ls<MomOp>(c, r, vx, vy, th));
     if (vort || sums) {
         k_vorticity<<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(vx, vy, c->nx, c->ny, vort,
                                                                           c->partial + MOM_NS * c->nblk);
@@ -805,7 +911,10 @@ int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* theta, 
 int lbm_populations(lbm_ctx* c, double* f_out)
 {
     if (!c || !f_out) return fail(LBM_EINVAL, "ctx or f_out is NULL");
-    HIP_TRY(dispatch_ls<PopOp>(c, f_out));
+    if (c->store == ST_MOM)
+        HIP_TRY(mom_launch_any(c, 1, nullptr, nullptr, nullptr, f_out));
+    else
+        HIP_TRY(dispatch_ls<PopOp>(c, f_out));
     return LBM_OK;
 }
 
@@ -967,6 +1076,7 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, i
         if (!c) return fail(LBM_EINVAL, "NULL member");
         if (c->coll != COLL_RR || c->thermal)
             return fail(LBM_EINVAL, "batch members must use the isothermal recursive regularization");
+        if (c->store == ST_MOM) return fail(LBM_EINVAL, "batch members must store populations");
         if (c->store != ctxs[0]->store) return fail(LBM_EINVAL, "batch members must share the storage type");
         if (c->stream != ctxs[0]->stream) return fail(LBM_EINVAL, "batch members must share the stream");
         for (int j = 0; j < i; ++j)
@@ -1125,8 +1235,8 @@ extern "C" {
 int lbm_closure_samples(lbm_ctx* c, int factor, float* x, float* r)
 {
     if (!c || !x || !r) return fail(LBM_EINVAL, "ctx, x or r is NULL");
-    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal)
-        return fail(LBM_EINVAL, "closure samples need an isothermal RR D2V37 context");
+    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal || c->store == ST_MOM)
+        return fail(LBM_EINVAL, "closure samples need an isothermal RR D2V37 context storing populations");
     if (factor < 1 || factor > 8 || c->nx % factor || c->ny % factor)
         return fail(LBM_EINVAL, "factor must be in [1, 8] and divide nx and ny");
     const double sf = (1.0 - 0.5 / c->tau) / (1.0 - 1.0 / c->tau);
@@ -1288,8 +1398,8 @@ int lbm_closure_set(lbm_ctx* c, const float* theta, const float* norm)
         return LBM_OK;
     }
     if (!norm) return fail(LBM_EINVAL, "norm is NULL");
-    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal)
-        return fail(LBM_EINVAL, "the closure needs an isothermal RR D2V37 context");
+    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal || c->store == ST_MOM)
+        return fail(LBM_EINVAL, "the closure needs an isothermal RR D2V37 context storing populations");
     if (!c->cl_frags) {
         HIP_TRY(hipMalloc(&c->cl_frags, sizeof(MlpInfer)));
         HIP_TRY(hipMalloc(&c->cl_norm, sizeof(float) * NORM_N));

@@ -1,0 +1,116 @@
+"""The moment representation (LBM_STORE_MOMENTS: six FP64 values per node)
+against the FP64 oracle and against the population form of the library.
+
+For the isothermal recursive regularization the post-collision populations
+are a function of (rho, u, a1^(2)), so lbm_populations rebuilt from the
+moments must equal the oracle's C(f^n) element by element: both sides in
+double, a few ulps of |f| <= 1 per step, bound 1e-12 as for the population
+form.  Grids narrower than the staged tile take the modulo wrap path."""
+import numpy as np
+import pytest
+
+from paper_1704_04413_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def b():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_04413_amd import binding
+
+    binding.lib()
+    return binding
+
+
+def check(got, want, atol, what="f"):
+    err = float(np.abs(np.asarray(got) - np.asarray(want)).max())
+    print(f"[parity] moments {what}: max |gpu - oracle| = {err:.3e} (bound {atol:.0e})", flush=True)
+    assert err <= atol, err
+
+
+def case(orc, name, nx, ny, re=1e4, k=20.0, grad=False):
+    lat = orc.lattice(name)
+    u0, tau = wl.shear_layer_params(lat.cs2, max(nx, ny), re)
+    rho, ux, uy = wl.shear_layer_fields(nx, ny, u0, k=k)
+    g = wl.shear_layer_gradients(nx, ny, u0, k=k) if grad else None
+    noise = wl.uniform_noise(7, lat.Q, ny, nx)
+    f0 = orc.init_populations(lat, rho, ux, uy, None, noise, 1e-8, grad=g, tau=tau)
+    return lat, tau, (rho, ux, uy, g, noise), f0
+
+
+def sim_of(b, name, nx, ny, tau, fields, flags, order=None):
+    rho, ux, uy, g, noise = fields
+    return b.Simulation(name, nx, ny, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, grad=g, flags=flags,
+                        reg_order=order)
+
+
+@pytest.mark.parametrize("name,order", [("D2Q9", 2), ("D2Q9", 3), ("D2Q9", 4), ("D2V17", 2), ("D2V17", 3),
+                                        ("D2V37", 2), ("D2V37", 3), ("D2V37", 4)])
+def test_moments_against_oracle(orc, b, name, order):
+    nx, ny = 70, 45
+    print(f"[case] moments {name} RR{order} {nx}x{ny}", flush=True)
+    lat, tau, fields, f0 = case(orc, name, nx, ny)
+    sim = sim_of(b, name, nx, ny, tau, fields, b.LBM_STORE_MOMENTS, order)
+    done = 0
+    for steps in (0, 1, 7):
+        sim.step(steps - done)
+        done = steps
+        got = sim.populations().cpu().numpy()
+        want = orc.collide(lat, orc.step(lat, f0, tau, steps, order=order), tau, order=order)
+        check(got, want, 1e-12)
+    sim.close()
+
+
+@pytest.mark.parametrize("name,nx,ny", [("D2Q9", 1, 1), ("D2Q9", 2, 3), ("D2V17", 3, 4), ("D2V37", 3, 5),
+                                        ("D2V37", 65, 3), ("D2V37", 5, 70), ("D2V37", 130, 9)])
+def test_moments_small_and_ragged_grids(orc, b, name, nx, ny):
+    print(f"[case] moments {name} {nx}x{ny}", flush=True)
+    lat, tau, fields, f0 = case(orc, name, nx, ny, re=3e3, k=8.0)
+    sim = sim_of(b, name, nx, ny, tau, fields, b.LBM_STORE_MOMENTS)
+    sim.step(5)
+    got = sim.populations().cpu().numpy()
+    sim.close()
+    check(got, orc.collide(lat, orc.step(lat, f0, tau, 5), tau), 1e-12)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2V37"])
+def test_moments_follow_the_population_form(orc, b, name):
+    """200 steps of the shear layer with the f^(0) + f^(1) start: populations
+    and diagnostics of both representations agree."""
+    nx, ny = 128, 96
+    print(f"[case] moments vs populations {name} {nx}x{ny} x 200", flush=True)
+    lat, tau, fields, _ = case(orc, name, nx, ny, re=3e4, k=40.0, grad=True)
+    a = sim_of(b, name, nx, ny, tau, fields, b.LBM_STORE_MOMENTS)
+    p = sim_of(b, name, nx, ny, tau, fields, 0)
+    a.step(200)
+    p.step(200)
+    fa, fp = a.populations().cpu().numpy(), p.populations().cpu().numpy()
+    ma, mp = a.moments(), p.moments()
+    check(fa, fp, 1e-11, "populations vs population form")
+    for key in ("rho", "ux", "uy", "vort"):
+        check(ma[key].cpu().numpy(), mp[key].cpu().numpy(), 1e-11, key)
+    sa, sp = np.asarray(ma["sums"]), np.asarray(mp["sums"])
+    # the net momentum sums are ~0: absolute bound of 1e-12 per node
+    print(f"[parity] moments sums max |diff| {np.abs(sa - sp)[:8].max():.3e}", flush=True)
+    np.testing.assert_allclose(sa[:8], sp[:8], rtol=1e-10, atol=1e-12 * nx * ny)
+    assert sa[8] == sp[8] == 0
+    a.close()
+    p.close()
+
+
+def test_moments_rejected_where_populations_are_needed(orc, b):
+    import torch
+
+    lat, tau, fields, _ = case(orc, "D2V37", 16, 16)
+    sim = sim_of(b, "D2V37", 16, 16, tau, fields, b.LBM_STORE_MOMENTS)
+    with pytest.raises(b.LbmError):
+        b.lbm_batch_create([sim.ctx], 64, 4)
+    theta = torch.zeros(b.LBM_MLP_NPARAM, dtype=torch.float32, device="cuda")
+    norm = torch.ones(b.LBM_MLP_NNORM, dtype=torch.float32, device="cuda")
+    with pytest.raises(b.LbmError):
+        b.lbm_closure_set(sim.ctx, theta, norm)
+    sim.close()
