@@ -104,7 +104,8 @@ def summarize_pmc(args) -> str:
     copy_kib = float(1 << 20)  # 1 GiB read and written by the calibration copy
     fs, ws = copy_kib / cfetch, copy_kib / cwrite
     q = {"D2Q9": 9, "D2V17": 17, "D2V37": 37}[args.lattice]
-    alg = 2 * q * STORAGE_BYTES[args.storage] * args.n * args.n
+    alg = bytes_per_node(q, args.storage) * args.n * args.n
+    alg_formula = ("2*6*8" if args.storage == "moments" else f"2*{q}*{STORAGE_BYTES[args.storage]}") + f"*{args.n}^2"
     rd, wr = fetch * fs * 1024, write * ws * 1024
     name = f"{args.lattice.lower()}_{args.storage}_{args.n}_traffic.txt"
     flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
@@ -122,7 +123,7 @@ def summarize_pmc(args) -> str:
         f"# copy: FETCH_SIZE {cfetch:.1f} KiB, WRITE_SIZE {cwrite:.1f} KiB per dispatch for {copy_kib:.0f} KiB read and written",
         f"#   -> scale factors fetch {fs:.4f}, write {ws:.4f}",
         f"# step kernel ({ndisp} dispatches): FETCH_SIZE {fetch:.1f} KiB, WRITE_SIZE {write:.1f} KiB per dispatch",
-        f"#   -> read {rd / 1e6:.1f} MB, written {wr / 1e6:.1f} MB per launch; algorithmic 2*{q}*{STORAGE_BYTES[args.storage]}*{args.n}^2 = {alg / 1e6:.1f} MB",
+        f"#   -> read {rd / 1e6:.1f} MB, written {wr / 1e6:.1f} MB per launch; algorithmic {alg_formula} = {alg / 1e6:.1f} MB",
         f"#   -> measured / algorithmic = {(rd + wr) / alg:.4f}",
         f"kernel: {kname}",
         f"kernel_source_hash: {kernel_source_hash()}",
@@ -379,7 +380,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.storage == "fp64" else "f32",
+        "dtype": "f32" if args.storage in ("fp32", "bf16") else "f64",
         "data": "synthetic",
         "config": {
             "workload": f"{args.lattice} isothermal recursive-regularized shear layer {args.n}x{args.n}, "
