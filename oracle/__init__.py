@@ -61,6 +61,8 @@ def lib():
         L.orc_noneq_init.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, dp, dp, ctypes.c_double, dp]
         L.orc_collide.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double, i64, dp, dp]
         L.orc_step.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] + [ctypes.c_int] * 3 + [dp, dp]
+        L.orc_collide_mrt.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] * 3 + [i64, dp, dp]
+        L.orc_step_mrt.argtypes = [ctypes.c_int] * 5 + [ctypes.c_double] * 3 + [ctypes.c_int] * 3 + [dp, dp]
         L.orc_moments.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, dp, dp]
         L.orc_threads.argtypes = []
         L.orc_closure_inputs.argtypes = [ctypes.c_int, ctypes.c_double, i64, dp, dp, dp]
@@ -170,13 +172,17 @@ def equilibrium(lat: Lattice, rho, ux, uy, theta=None, order=None) -> np.ndarray
     return out.reshape((lat.Q,) + shape)
 
 
-def collide(lat: Lattice, f, tau, coll=RR, order=None, thermal=False, a13_raw=False) -> np.ndarray:
+def collide(lat: Lattice, f, tau, coll=RR, order=None, thermal=False, a13_raw=False, tau3=None,
+            tau4=None) -> np.ndarray:
+    """Post-collision populations; tau3, tau4 relax ranks 3 and 4 on their own
+    (default tau)."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     n = f.size // lat.Q
     out = np.zeros_like(f)
     order = lat.n_eq if order is None else order
-    _check(lib().orc_collide(lat.id, coll, order, int(thermal), int(a13_raw), tau, n, _p(f), _p(out)),
-           "collide")
+    t3, t4 = (tau if tau3 is None else tau3), (tau if tau4 is None else tau4)
+    _check(lib().orc_collide_mrt(lat.id, coll, order, int(thermal), int(a13_raw), tau, t3, t4, n, _p(f),
+                                 _p(out)), "collide")
     return out
 
 
@@ -206,14 +212,17 @@ def init_populations(lat: Lattice, rho, ux, uy, theta=None, noise=None, noise_am
     return np.ascontiguousarray(f)
 
 
-def step(lat: Lattice, f, tau, nsteps, coll=RR, order=None, thermal=False, a13_raw=False) -> np.ndarray:
-    """nsteps of collide + periodic push stream; f has shape (Q, ny, nx)."""
+def step(lat: Lattice, f, tau, nsteps, coll=RR, order=None, thermal=False, a13_raw=False, tau3=None,
+         tau4=None) -> np.ndarray:
+    """nsteps of collide + periodic push stream; f has shape (Q, ny, nx);
+    tau3, tau4 relax ranks 3 and 4 on their own (default tau)."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     _, ny, nx = f.shape
     tmp = np.empty_like(f)
     order = lat.n_eq if order is None else order
-    _check(lib().orc_step(lat.id, coll, order, int(thermal), int(a13_raw), tau, nx, ny, nsteps,
-                          _p(f), _p(tmp)), "step")
+    t3, t4 = (tau if tau3 is None else tau3), (tau if tau4 is None else tau4)
+    _check(lib().orc_step_mrt(lat.id, coll, order, int(thermal), int(a13_raw), tau, t3, t4, nx, ny, nsteps,
+                              _p(f), _p(tmp)), "step")
     return f
 
 

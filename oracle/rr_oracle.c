@@ -60,6 +60,8 @@ typedef struct {
     int a13_raw;    /* thermal RR: 1 keeps the projected a1^(3) (Sec. II.F), */
                     /* 0 rebuilds it from the averaged gradient (App. C)     */
     double tau;     /* discrete relaxation time (tau-bar of Sec. III.A)      */
+    double tau3;    /* relaxation time of the rank-3 coefficients (= tau     */
+    double tau4;    /* unless per order, Eq. GenRegCollision), and rank 4   */
 } orc_cfg_t;
 
 static int toff(int n, int b) { return (1 << n) - 1 + b; }
@@ -402,13 +404,15 @@ static void node_collide(const orc_lattice_t* L, const orc_cfg_t* c, const doubl
     }
     double a1[ORC_NT];
     noneq_coeffs(L, c, f, feq, rho, u, theta, a0, a1);
-    /* truncation: only ranks 2..N of the basis carry a non-equilibrium part */
+    /* truncation: only ranks 2..N of the basis carry a non-equilibrium part;
+     * rank n relaxes with its own tau_n (Eq. GenRegCollision with one time per
+     * order, the Hermite MRT form), tau_2 = tau */
     double a[ORC_NT];
-    const double k = 1.0 - 1.0 / c->tau;
+    const double kn[5] = { 0.0, 0.0, 1.0 - 1.0 / c->tau, 1.0 - 1.0 / c->tau3, 1.0 - 1.0 / c->tau4 };
     for (int n = 0; n <= 4; ++n)
         for (int b = 0; b < (1 << n); ++b) {
             double v = a0[toff(n, b)];
-            if (n >= 2 && n <= c->order) v += k * a1[toff(n, b)];
+            if (n >= 2 && n <= c->order) v += kn[n] * a1[toff(n, b)];
             a[toff(n, b)] = v;
         }
     hermite_sum(L, a, L->n_eq, out);
@@ -479,7 +483,7 @@ int orc_noneq_coeffs(int id, int coll, int thermal, int a13_raw, const double* f
 {
     orc_lattice_t L;
     if (build_lattice(id, &L)) return -1;
-    orc_cfg_t c = { coll, 4, thermal, a13_raw, 1.0 };
+    orc_cfg_t c = { coll, 4, thermal, a13_raw, 1.0, 1.0, 1.0 };
     double rho, u[2], theta, a0[ORC_NT], feq[ORC_MAXQ];
     node_moments(&L, f, thermal, &rho, &u[0], &u[1], &theta);
     eq_coeffs(&L, rho, u[0], u[1], theta, a0);
@@ -563,37 +567,20 @@ static int check_cfg(const orc_lattice_t* L, int coll, int order, double tau)
     return 0;
 }
 
-/* Post-collision populations of every node (no streaming): out = C(f). */
-int orc_collide(int id, int coll, int order, int thermal, int a13_raw, double tau, int64_t n,
-                const double* f, double* out)
+static void collide_all(const orc_lattice_t* L, const orc_cfg_t* c, int64_t n, const double* f, double* out)
 {
-    orc_lattice_t L;
-    if (build_lattice(id, &L)) return -1;
-    int e = check_cfg(&L, coll, order, tau);
-    if (e) return e;
-    orc_cfg_t c = { coll, order, thermal, a13_raw, tau };
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) {
         double fl[ORC_MAXQ], fo[ORC_MAXQ];
-        for (int i = 0; i < L.Q; ++i) fl[i] = f[(int64_t)i * n + k];
-        node_collide(&L, &c, fl, fo);
-        for (int i = 0; i < L.Q; ++i) out[(int64_t)i * n + k] = fo[i];
+        for (int i = 0; i < L->Q; ++i) fl[i] = f[(int64_t)i * n + k];
+        node_collide(L, c, fl, fo);
+        for (int i = 0; i < L->Q; ++i) out[(int64_t)i * n + k] = fo[i];
     }
-    return 0;
 }
 
-/* nsteps of collide-then-stream on a periodic nx x ny grid (Sec. III.A):
- * f_i(x + c_i, t + 1) = f_i^coll(x, t).  f holds the pre-collision state and
- * is updated in place; tmp is scratch of the same size. */
-int orc_step(int id, int coll, int order, int thermal, int a13_raw, double tau, int nx, int ny,
-             int nsteps, double* f, double* tmp)
+static void step_all(const orc_lattice_t* L, const orc_cfg_t* c, int nx, int ny, int nsteps, double* f,
+                     double* tmp)
 {
-    orc_lattice_t L;
-    if (build_lattice(id, &L)) return -1;
-    int e = check_cfg(&L, coll, order, tau);
-    if (e) return e;
-    if (nx < 1 || ny < 1) return -5;
-    orc_cfg_t c = { coll, order, thermal, a13_raw, tau };
     const int64_t n = (int64_t)nx * ny;
     for (int s = 0; s < nsteps; ++s) {
 #pragma omp parallel for schedule(static)
@@ -601,18 +588,63 @@ int orc_step(int id, int coll, int order, int thermal, int a13_raw, double tau, 
             for (int x = 0; x < nx; ++x) {
                 double fl[ORC_MAXQ], fo[ORC_MAXQ];
                 const int64_t k = (int64_t)y * nx + x;
-                for (int i = 0; i < L.Q; ++i) fl[i] = f[(int64_t)i * n + k];
-                node_collide(&L, &c, fl, fo);
-                for (int i = 0; i < L.Q; ++i) {
-                    int xd = ((x + L.cx[i]) % nx + nx) % nx;
-                    int yd = ((y + L.cy[i]) % ny + ny) % ny;
+                for (int i = 0; i < L->Q; ++i) fl[i] = f[(int64_t)i * n + k];
+                node_collide(L, c, fl, fo);
+                for (int i = 0; i < L->Q; ++i) {
+                    int xd = ((x + L->cx[i]) % nx + nx) % nx;
+                    int yd = ((y + L->cy[i]) % ny + ny) % ny;
                     tmp[(int64_t)i * n + (int64_t)yd * nx + xd] = fo[i];
                 }
             }
         }
-        memcpy(f, tmp, sizeof(double) * (size_t)(n * L.Q));
+        memcpy(f, tmp, sizeof(double) * (size_t)(n * L->Q));
     }
+}
+
+/* Post-collision populations of every node (no streaming): out = C(f).
+ * tau3, tau4: relaxation times of ranks 3 and 4 (pass tau for one time). */
+int orc_collide_mrt(int id, int coll, int order, int thermal, int a13_raw, double tau, double tau3, double tau4,
+                    int64_t n, const double* f, double* out)
+{
+    orc_lattice_t L;
+    if (build_lattice(id, &L)) return -1;
+    int e = check_cfg(&L, coll, order, tau);
+    if (!e) e = check_cfg(&L, coll, order, tau3);
+    if (!e) e = check_cfg(&L, coll, order, tau4);
+    if (e) return e;
+    orc_cfg_t c = { coll, order, thermal, a13_raw, tau, tau3, tau4 };
+    collide_all(&L, &c, n, f, out);
     return 0;
+}
+
+int orc_collide(int id, int coll, int order, int thermal, int a13_raw, double tau, int64_t n,
+                const double* f, double* out)
+{
+    return orc_collide_mrt(id, coll, order, thermal, a13_raw, tau, tau, tau, n, f, out);
+}
+
+/* nsteps of collide-then-stream on a periodic nx x ny grid (Sec. III.A):
+ * f_i(x + c_i, t + 1) = f_i^coll(x, t).  f holds the pre-collision state and
+ * is updated in place; tmp is scratch of the same size. */
+int orc_step_mrt(int id, int coll, int order, int thermal, int a13_raw, double tau, double tau3, double tau4,
+                 int nx, int ny, int nsteps, double* f, double* tmp)
+{
+    orc_lattice_t L;
+    if (build_lattice(id, &L)) return -1;
+    int e = check_cfg(&L, coll, order, tau);
+    if (!e) e = check_cfg(&L, coll, order, tau3);
+    if (!e) e = check_cfg(&L, coll, order, tau4);
+    if (e) return e;
+    if (nx < 1 || ny < 1) return -5;
+    orc_cfg_t c = { coll, order, thermal, a13_raw, tau, tau3, tau4 };
+    step_all(&L, &c, nx, ny, nsteps, f, tmp);
+    return 0;
+}
+
+int orc_step(int id, int coll, int order, int thermal, int a13_raw, double tau, int nx, int ny,
+             int nsteps, double* f, double* tmp)
+{
+    return orc_step_mrt(id, coll, order, thermal, a13_raw, tau, tau, tau, nx, ny, nsteps, f, tmp);
 }
 
 /* ---- Learned-closure support (not part of the paper's method) ----------
@@ -634,7 +666,7 @@ int orc_closure_inputs(int id, double tau, int64_t n, const double* f, double* f
     orc_lattice_t L;
     if (build_lattice(id, &L)) return -1;
     const double s = 1.0 - 0.5 / tau;
-    orc_cfg_t c = { ORC_RR, L.n_eq, 0, 0, tau };
+    orc_cfg_t c = { ORC_RR, L.n_eq, 0, 0, tau, tau, tau };
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) {
         double fl[ORC_MAXQ], a0[ORC_NT], feq[ORC_MAXQ], a1[ORC_NT], rho, u[2], th;
@@ -696,7 +728,7 @@ int orc_collide_closure(int id, int order, double tau, int64_t n, const double* 
     if (build_lattice(id, &L)) return -1;
     int e = check_cfg(&L, ORC_RR, order, tau);
     if (e) return e;
-    orc_cfg_t c = { ORC_RR, order, 0, 0, tau };
+    orc_cfg_t c = { ORC_RR, order, 0, 0, tau, tau, tau };
     const double inv_s = 1.0 / (1.0 - 0.5 / tau);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) {

@@ -115,3 +115,57 @@ def test_uniform_equilibrium_is_steady(orc, name):
     f = orc.init_populations(lat, np.full((n, n), 1.1), np.full((n, n), 0.05), np.full((n, n), -0.03))
     g = orc.step(lat, f, 0.6, 10)
     np.testing.assert_allclose(g, f, rtol=1e-13, atol=0)
+
+
+def entropy_wave_chi(orc, tau, tau3, coll):
+    lat = orc.lattice("D2V37")
+    ny, nx, eps = 64, 4, 1e-4
+    y = (np.arange(ny) + 0.5) / ny
+    th = np.broadcast_to((1.0 + eps * np.sin(2 * np.pi * y))[:, None], (ny, nx)).copy()
+    z = np.zeros((ny, nx))
+    f = orc.init_populations(lat, 1.0 / th, z, z, th)
+    k = 2 * np.pi / ny
+    t1, t2 = 200, 1200
+    f = orc.step(lat, f, tau, t1, coll=coll, thermal=True, tau3=tau3)
+    a1 = amplitude(orc.moments(lat, f, thermal=True)[3][:, 0] - 1.0, ny)
+    f = orc.step(lat, f, tau, t2 - t1, coll=coll, thermal=True, tau3=tau3)
+    a2 = amplitude(orc.moments(lat, f, thermal=True)[3][:, 0] - 1.0, ny)
+    return math.log(a1 / a2) / ((t2 - t1) * k * k), lat.cs2
+
+
+@pytest.mark.parametrize("coll", ["RR", "PR"])
+@pytest.mark.parametrize("tau,tau3", [(0.8, 0.6), (0.6, 0.9)])
+def test_entropy_wave_decays_with_the_rank3_time(orc, coll, tau, tau3):
+    """Per-order relaxation (Eq. GenRegCollision with one time per rank): the
+    heat flux is carried by the rank-3 coefficients, so an isobaric
+    temperature mode decays at chi = c_s^2 theta (tau_3 - 1/2) while the
+    viscosity keeps tau_2 = tau: Pr = (tau - 1/2) / (tau_3 - 1/2)."""
+    chi, cs2 = entropy_wave_chi(orc, tau, tau3, orc.RR if coll == "RR" else orc.PR)
+    assert chi == pytest.approx(cs2 * (tau3 - 0.5), rel=0.05)
+    assert abs(chi - cs2 * (tau - 0.5)) > 0.5 * cs2 * abs(tau3 - tau)
+
+
+@pytest.mark.parametrize("name", ["D2Q9", "D2V37"])
+def test_shear_wave_ignores_rank3_and_rank4_times(orc, name):
+    lat = orc.lattice(name)
+    ny, nx, tau = 64, 4, 0.8
+    U = 1e-4 * math.sqrt(lat.cs2)
+    y = (np.arange(ny) + 0.5) / ny
+    ux = np.broadcast_to((U * np.sin(2 * np.pi * y))[:, None], (ny, nx)).copy()
+    f = orc.init_populations(lat, np.ones((ny, nx)), ux, np.zeros((ny, nx)))
+    k = 2 * np.pi / ny
+    f = orc.step(lat, f, tau, 50, tau3=0.6, tau4=1.1)
+    a1 = amplitude(orc.moments(lat, f)[1][:, 0], ny)
+    f = orc.step(lat, f, tau, 1000, tau3=0.6, tau4=1.1)
+    a2 = amplitude(orc.moments(lat, f)[1][:, 0], ny)
+    assert math.log(a1 / a2) / (1000 * k * k) == pytest.approx(lat.cs2 * (tau - 0.5), rel=0.01)
+
+
+def test_per_order_times_equal_to_tau_are_the_single_time_operator(orc):
+    lat = orc.lattice("D2V37")
+    rng = np.random.default_rng(4)
+    f = orc.equilibrium(lat, rng.uniform(0.9, 1.1, 30), rng.uniform(-0.1, 0.1, 30), rng.uniform(-0.1, 0.1, 30))
+    f = f * (1 + 1e-3 * rng.uniform(-1, 1, f.shape))
+    for coll in (orc.RR, orc.PR):
+        assert np.array_equal(orc.collide(lat, f, 0.7, coll=coll, tau3=0.7, tau4=0.7), orc.collide(lat, f, 0.7, coll=coll))
+        assert not np.array_equal(orc.collide(lat, f, 0.7, coll=coll, tau3=0.9), orc.collide(lat, f, 0.7, coll=coll))
