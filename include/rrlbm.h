@@ -130,6 +130,15 @@ int lbm_step(lbm_ctx* ctx, int nsteps);
 /* Number of steps taken since lbm_init. */
 int64_t lbm_step_count(const lbm_ctx* ctx);
 
+/* Relaxation times of the rank-3 and rank-4 non-equilibrium coefficients
+ * (Eq. GenRegCollision with one time per Hermite order, the MRT form of
+ * Sec. II.C; rank 2 keeps the tau of lbm_init).  Both default to tau.  In
+ * the thermal form tau3 sets the thermal diffusivity c_s^2 theta (tau3 - 1/2),
+ * so Pr = (tau - 1/2) / (tau3 - 1/2).  Applies from the next step; ranks
+ * above the regularization order stay equilibrium.  LBM_EINVAL for a NULL
+ * context or BGK, LBM_ETAU unless both are finite and > 1/2. */
+int lbm_set_relaxation(lbm_ctx* ctx, double tau3, double tau4);
+
 /* Macroscopic fields of the current step (rho, u and theta are collision
  * invariants, so they are the fields before and after the collision).
  * rho, ux, uy, theta, vort: device FP64 fields or NULL.  vort is

@@ -30,7 +30,7 @@ LBM_OK, LBM_EINVAL, LBM_ETAU, LBM_EDEVICE, LBM_ENOMEM = 0, -1, -2, -3, -4
 
 # every symbol declared in include/rrlbm.h
 EXPORTS = ["lbm_lattice_info", "lbm_lattice_velocities", "lbm_buffer_elems", "lbm_init", "lbm_step",
-           "lbm_step_count", "lbm_moments", "lbm_populations", "lbm_destroy", "lbm_last_error",
+           "lbm_step_count", "lbm_set_relaxation", "lbm_moments", "lbm_populations", "lbm_destroy", "lbm_last_error",
            "lbm_batch_create", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_config", "lbm_batch_destroy",
            "lbm_closure_samples", "lbm_mlp_stats", "lbm_mlp_normalize", "lbm_mlp_create", "lbm_mlp_forward",
            "lbm_mlp_step", "lbm_mlp_destroy", "lbm_closure_set", "lbm_closure_fallbacks"]
@@ -62,6 +62,7 @@ def lib():
         L.lbm_init.argtypes = [ctypes.POINTER(vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                ctypes.c_int, ctypes.c_uint32, vp, vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp]
         L.lbm_step.argtypes = [vp, ctypes.c_int]
+        L.lbm_set_relaxation.argtypes = [vp, ctypes.c_double, ctypes.c_double]
         L.lbm_step_count.argtypes = [vp]
         L.lbm_step_count.restype = ctypes.c_int64
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, dp]
@@ -144,6 +145,10 @@ def lbm_init(lattice, nx, ny, tau, reg_order, flags, f_a, f_b, rho, ux, uy, thet
 
 def lbm_step(ctx, nsteps: int):
     _check(lib().lbm_step(ctypes.c_void_p(ctx), nsteps))
+
+
+def lbm_set_relaxation(ctx, tau3: float, tau4: float):
+    _check(lib().lbm_set_relaxation(ctypes.c_void_p(ctx), tau3, tau4))
 
 
 def lbm_step_count(ctx) -> int:
@@ -283,6 +288,9 @@ class Simulation:
 
     def step(self, n: int = 1):
         lbm_step(self.ctx, n)
+
+    def set_relaxation(self, tau3: float, tau4: float):
+        lbm_set_relaxation(self.ctx, tau3, tau4)
 
     def populations(self):
         t = self.torch.empty((self.q, self.ny, self.nx), dtype=self.torch.float64, device=self.device)

@@ -308,7 +308,7 @@ __global__ __launch_bounds__(256) void k_stream_collide_closure(StepArgs a, Clos
         k.a1[1][3] += T(r[7]) * inv_s;
         k.a1[0][4] += T(r[8]) * inv_s;
     }
-    relax_reconstruct<L, T>(k, T(a.keep), a.order, v);
+    relax_reconstruct<L, T>(k, T(a.rx.k2), T(a.rx.k3), T(a.rx.k4), v);
     inv.restore(v);
     if (valid) {
         const int here = lay.row(y) + x;

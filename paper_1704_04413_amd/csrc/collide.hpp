@@ -289,13 +289,18 @@ __device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k
     }
 }
 
+// Relaxation of one step: k_n = 1 - 1/tau_n for the non-equilibrium part of
+// rank n (Eq. GenRegCollision with one time per order, the Hermite MRT form;
+// tau_2 = tau, and 0 above the regularization order), inv_tau = 1/tau (BGK).
+struct Relax {
+    double k2, k3, k4, inv_tau;
+};
+
 // Step 5: relax and rebuild the populations,
-// C = (a0 + k_n a1) / norm over the basis, k_n = keep for 2 <= n <= N.
+// C = (a0 + k_n a1) / norm over the basis, k_n of rank n (0 above N).
 template <class L, class T>
-__device__ __forceinline__ void relax_reconstruct(NodeCoeffs<T>& k, T keep, int order, T (&out)[L::Q])
+__device__ __forceinline__ void relax_reconstruct(NodeCoeffs<T>& k, T keep, T k3, T k4, T (&out)[L::Q])
 {
-    const T k3 = order >= 3 ? keep : T(0);
-    const T k4 = order >= 4 ? keep : T(0);
     static_for<5>([&](auto KX) {
         static_for<5>([&](auto KY) {
             constexpr int n = int(KX) + int(KY);
@@ -378,12 +383,13 @@ struct Invariants<L, float, THERMAL, true> {
     }
 };
 
-// The regularized (or BGK) collision of one node, in place.
-//   keep = 1 - 1/tau, inv_tau = 1/tau, order = N; CONS: restore the conserved
-//   moments summed in double (float storage).
+// The regularized (or BGK) collision of one node, in place, with the
+// relaxation rx; CONS: restore the conserved moments summed in double (float
+// storage).
 template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P, bool CONS>
-__device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, int order)
+__device__ __forceinline__ void collide_node(T (&v)[L::Q], const Relax& rx)
 {
+    const T keep = T(rx.k2), inv_tau = T(rx.inv_tau);
     Invariants<L, T, THERMAL, CONS> inv;
     inv.take(v);
     NodeCoeffs<T> k;
@@ -403,7 +409,7 @@ __device__ __forceinline__ void collide_node(T (&v)[L::Q], T keep, T inv_tau, in
         inv.restore(v);
         return;
     }
-    relax_reconstruct<L, T>(k, keep, order, v);
+    relax_reconstruct<L, T>(k, keep, T(rx.k3), T(rx.k4), v);
     inv.restore(v);
 }
 

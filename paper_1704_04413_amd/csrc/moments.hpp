@@ -38,16 +38,16 @@ constexpr double hc(int cx, int cy, int a, int b)
 }
 
 // Post-collision population I of a node with moments (r, ux, uy, a1^(2)) at
-// regularization order ORDER, keep = 1 - 1/tau:
-//   f_I = w_I [ r E_I(u) + keep (a1_xx A^xx_I(u) + a1_xy A^xy_I(u) + a1_yy A^yy_I(u)) ]
+// regularization order ORDER with the relaxation rx:
+//   f_I = w_I [ r E_I(u) + a1_xx A^xx_I(u) + a1_xy A^xy_I(u) + a1_yy A^yy_I(u) ]
 // with E_I = sum_k h_Ik u_x^kx u_y^ky (the equilibrium, a0_k = r u_x^kx u_y^ky at
 // theta = 1) and A_I the rank-2..ORDER terms of the expansion after the
-// isothermal recursion, which is linear in a1^(2) with coefficients
-// polynomial in u (degree 0, 1, 2 for ranks 2, 3, 4).  Every h is a
-// compile-time constant; zero terms are left out.
+// isothermal recursion, each weighted by its relaxation factor k_n: linear in
+// a1^(2) with coefficients polynomial in u (degree 0, 1, 2 for ranks 2, 3,
+// 4).  Every h is a compile-time constant; zero terms are left out.
 template <class L, int I, int ORDER>
 __device__ __forceinline__ double mom_pop(double r, double ux, double uy, double axx, double axy, double ayy,
-                                          double keep)
+                                          const Relax& rx)
 {
     constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
     constexpr double h10 = hc<L>(cx, cy, 1, 0), h01 = hc<L>(cx, cy, 0, 1);
@@ -73,7 +73,7 @@ __device__ __forceinline__ double mom_pop(double r, double ux, double uy, double
     if constexpr (h22 != 0.0) e += h22 * (x2 * y2);
     if constexpr (h13 != 0.0) e += h13 * (xy * y2);
     if constexpr (h04 != 0.0) e += h04 * (y2 * y2);
-    // non-equilibrium: coefficients of a1_xx, a1_xy, a1_yy
+    // non-equilibrium: coefficients of a1_xx, a1_xy, a1_yy, rank by rank
     // rank 3: a1_30 = 3 ux xx, a1_21 = 2 ux xy + uy xx, a1_12 = 2 uy xy + ux yy, a1_03 = 3 uy yy
     // rank 4: a1_40 = 6 ux^2 xx, a1_31 = 3 (ux^2 xy + ux uy xx),
     //         a1_22 = uy^2 xx + ux^2 yy + 4 ux uy xy, a1_13 = 3 (uy^2 xy + ux uy yy), a1_04 = 6 uy^2 yy
@@ -84,36 +84,46 @@ __device__ __forceinline__ double mom_pop(double r, double ux, double uy, double
     constexpr double cxx_x2 = r4 ? 6.0 * h40 : 0.0, cxx_xy = r4 ? 3.0 * h31 : 0.0, cxx_y2 = r4 ? h22 : 0.0;
     constexpr double cxy_x2 = r4 ? 3.0 * h31 : 0.0, cxy_xy = r4 ? 4.0 * h22 : 0.0, cxy_y2 = r4 ? 3.0 * h13 : 0.0;
     constexpr double cyy_x2 = r4 ? h22 : 0.0, cyy_xy = r4 ? 3.0 * h13 : 0.0, cyy_y2 = r4 ? 6.0 * h04 : 0.0;
+    // per a1 component: k2 c2 + k3 (c_x ux + c_y uy) + k4 (c_x2 x2 + c_xy xy + c_y2 y2)
     double n = 0.0;
     {
-        double c = h20;
-        if constexpr (cxx_x != 0.0) c += cxx_x * ux;
-        if constexpr (cxx_y != 0.0) c += cxx_y * uy;
-        if constexpr (cxx_x2 != 0.0) c += cxx_x2 * x2;
-        if constexpr (cxx_xy != 0.0) c += cxx_xy * xy;
-        if constexpr (cxx_y2 != 0.0) c += cxx_y2 * y2;
+        double c = 0.0, p3 = 0.0, p4 = 0.0;
+        if constexpr (h20 != 0.0) c += rx.k2 * h20;
+        if constexpr (cxx_x != 0.0) p3 += cxx_x * ux;
+        if constexpr (cxx_y != 0.0) p3 += cxx_y * uy;
+        if constexpr (cxx_x2 != 0.0) p4 += cxx_x2 * x2;
+        if constexpr (cxx_xy != 0.0) p4 += cxx_xy * xy;
+        if constexpr (cxx_y2 != 0.0) p4 += cxx_y2 * y2;
+        if constexpr (cxx_x != 0.0 || cxx_y != 0.0) c += rx.k3 * p3;
+        if constexpr (cxx_x2 != 0.0 || cxx_xy != 0.0 || cxx_y2 != 0.0) c += rx.k4 * p4;
         n += c * axx;
     }
     {
-        double c = h11;
-        if constexpr (cxy_x != 0.0) c += cxy_x * ux;
-        if constexpr (cxy_y != 0.0) c += cxy_y * uy;
-        if constexpr (cxy_x2 != 0.0) c += cxy_x2 * x2;
-        if constexpr (cxy_xy != 0.0) c += cxy_xy * xy;
-        if constexpr (cxy_y2 != 0.0) c += cxy_y2 * y2;
+        double c = 0.0, p3 = 0.0, p4 = 0.0;
+        if constexpr (h11 != 0.0) c += rx.k2 * h11;
+        if constexpr (cxy_x != 0.0) p3 += cxy_x * ux;
+        if constexpr (cxy_y != 0.0) p3 += cxy_y * uy;
+        if constexpr (cxy_x2 != 0.0) p4 += cxy_x2 * x2;
+        if constexpr (cxy_xy != 0.0) p4 += cxy_xy * xy;
+        if constexpr (cxy_y2 != 0.0) p4 += cxy_y2 * y2;
+        if constexpr (cxy_x != 0.0 || cxy_y != 0.0) c += rx.k3 * p3;
+        if constexpr (cxy_x2 != 0.0 || cxy_xy != 0.0 || cxy_y2 != 0.0) c += rx.k4 * p4;
         n += c * axy;
     }
     {
-        double c = h02;
-        if constexpr (cyy_x != 0.0) c += cyy_x * ux;
-        if constexpr (cyy_y != 0.0) c += cyy_y * uy;
-        if constexpr (cyy_x2 != 0.0) c += cyy_x2 * x2;
-        if constexpr (cyy_xy != 0.0) c += cyy_xy * xy;
-        if constexpr (cyy_y2 != 0.0) c += cyy_y2 * y2;
+        double c = 0.0, p3 = 0.0, p4 = 0.0;
+        if constexpr (h02 != 0.0) c += rx.k2 * h02;
+        if constexpr (cyy_x != 0.0) p3 += cyy_x * ux;
+        if constexpr (cyy_y != 0.0) p3 += cyy_y * uy;
+        if constexpr (cyy_x2 != 0.0) p4 += cyy_x2 * x2;
+        if constexpr (cyy_xy != 0.0) p4 += cyy_xy * xy;
+        if constexpr (cyy_y2 != 0.0) p4 += cyy_y2 * y2;
+        if constexpr (cyy_x != 0.0 || cyy_y != 0.0) c += rx.k3 * p3;
+        if constexpr (cyy_x2 != 0.0 || cyy_xy != 0.0 || cyy_y2 != 0.0) c += rx.k4 * p4;
         n += c * ayy;
     }
     constexpr double w = L::v.w[I];
-    return w * (r * e + keep * n);
+    return w * (r * e + n);
 }
 
 // Moments (rho, ux, uy, a1^(2)) of the populations v of one node.
@@ -144,7 +154,7 @@ __device__ __forceinline__ void node_state(const double (&v)[L::Q], double (&m)[
 // populations from there and writes its node's new moments.
 template <class L, int ORDER>
 __global__ __launch_bounds__(BX* BY) void k_mom_step(const double* __restrict__ min, double* __restrict__ mout, int nx,
-                                                     int ny, int bx_blocks, double keep)
+                                                     int ny, int bx_blocks, Relax rx)
 {
     constexpr int R = L::R, TW = BX + 2 * R, TH = BY + 2 * R;
     __shared__ double sm[MOM_K][TH][TW];
@@ -179,7 +189,7 @@ __global__ __launch_bounds__(BX* BY) void k_mom_step(const double* __restrict__ 
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
         const int ly = int(threadIdx.y) + R - cy, lx = int(threadIdx.x) + R - cx;
         const double f = mom_pop<L, int(I), ORDER>(sm[0][ly][lx], sm[1][ly][lx], sm[2][ly][lx], sm[3][ly][lx],
-                                                   sm[4][ly][lx], sm[5][ly][lx], keep);
+                                                   sm[4][ly][lx], sm[5][ly][lx], rx);
         r += f;
         if constexpr (cx != 0) jx += double(cx) * f;
         if constexpr (cy != 0) jy += double(cy) * f;
@@ -220,11 +230,11 @@ __global__ __launch_bounds__(256) void k_mom_init(InitArgs a)
 // Post-collision populations of node k (what the population form stores).
 template <class L, int ORDER>
 __device__ __forceinline__ void mom_node_populations(const double* __restrict__ m, int64_t n, int64_t k,
-                                                     double keep, double (&v)[L::Q])
+                                                     const Relax& rx, double (&v)[L::Q])
 {
     const double r = m[k], ux = m[n + k], uy = m[2 * n + k];
     const double axx = m[3 * n + k], axy = m[4 * n + k], ayy = m[5 * n + k];
-    static_for<L::Q>([&](auto I) { v[I] = mom_pop<L, int(I), ORDER>(r, ux, uy, axx, axy, ayy, keep); });
+    static_for<L::Q>([&](auto I) { v[I] = mom_pop<L, int(I), ORDER>(r, ux, uy, axx, axy, ayy, rx); });
 }
 
 } // namespace rr

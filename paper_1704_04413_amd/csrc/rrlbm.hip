@@ -166,9 +166,7 @@ struct StepArgs {
     int bx_blocks;  // blocks along x
     int nblocks;    // total blocks of the 1D grid
     int xcd_remap;  // 1: give each XCD a contiguous band of blocks
-    double keep;    // 1 - 1/tau
-    double inv_tau;
-    int order;
+    Relax rx;       // relaxation factors of ranks 2..4 and 1/tau
     uint32_t seq;   // index of the state written (0: initial state), keys the BF16 dither
 };
 
@@ -188,7 +186,7 @@ __device__ __forceinline__ int block_index(const StepArgs& a)
 template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
 __device__ __forceinline__ void node_update(const typename S::elem* __restrict__ fin,
                                             typename S::elem* __restrict__ fout, const Layout& lay, int x,
-                                            int y, double keep, double inv_tau, int order, uint32_t seq)
+                                            int y, const Relax& rx, uint32_t seq)
 {
     using T = typename S::math;
     constexpr int R = L::R;
@@ -218,7 +216,7 @@ __device__ __forceinline__ void node_update(const typename S::elem* __restrict__
         v[I] = S::load(fin + idx);
     });
 
-    collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, T(keep), T(inv_tau), order);
+    collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, rx);
 
     store_node<L, S>(fout, here, lay.te, v, uint32_t(y) * uint32_t(nx) + uint32_t(x), seq);
 }
@@ -232,8 +230,7 @@ void k_stream_collide(StepArgs a)
     const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
     if (x >= a.lay.nx || y >= a.lay.ny) return;
     node_update<L, S, COLL, THERMAL, A13P, PULL>(static_cast<const typename S::elem*>(a.fin),
-                                                 static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.keep,
-                                                 a.inv_tau, a.order, a.seq);
+                                                 static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx, a.seq);
 }
 
 // ---------------------------------------------------------- batch kernel
@@ -245,8 +242,7 @@ struct InstDesc {
     int lattice;
     int bx_blocks; // work items along x
     int flip;      // index of the buffer holding the member's current state
-    int order;
-    double keep, inv_tau;
+    Relax rx;
     uint32_t seq;  // index of the state the parity-0 launch writes (BF16 dither key)
 };
 
@@ -280,9 +276,9 @@ __global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ d
             const int x = x0 + sub + int(threadIdx.x);
             if (x < d.lay.nx && y < d.lay.ny) {
                 switch (d.lattice) {
-                case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order, d.seq + uint32_t(parity)); break;
-                case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order, d.seq + uint32_t(parity)); break;
-                default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.keep, d.inv_tau, d.order, d.seq + uint32_t(parity)); break;
+                case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
+                case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
+                default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
                 }
             }
         }
@@ -372,12 +368,12 @@ __device__ __forceinline__ void block_sums(double (&val)[NS], double* partial)
 }
 
 template <class L, int ORDER>
-__global__ __launch_bounds__(256) void k_mom_populations(const double* m, int64_t n, double keep, double* out)
+__global__ __launch_bounds__(256) void k_mom_populations(const double* m, int64_t n, Relax rx, double* out)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     double v[L::Q];
-    mom_node_populations<L, ORDER>(m, n, k, keep, v);
+    mom_node_populations<L, ORDER>(m, n, k, rx, v);
     static_for<L::Q>([&](auto I) { out[int64_t(I) * n + k] = v[I]; });
 }
 
@@ -439,14 +435,14 @@ __global__ __launch_bounds__(256) void k_moments(const void* fsrc, Layout lay, i
 
 // The same from the moment representation.
 template <class L, int ORDER>
-__global__ __launch_bounds__(256) void k_mom_moments(const double* m, int64_t n, double keep, double* rho_o,
+__global__ __launch_bounds__(256) void k_mom_moments(const double* m, int64_t n, Relax rx, double* rho_o,
                                                      double* ux_o, double* uy_o, double* th_o, double* partial)
 {
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double val[MOM_NS] = { 0, 0, 0, 0, 0, 0, 0, 0 };
     if (k < n) {
         double v[L::Q];
-        mom_node_populations<L, ORDER>(m, n, k, keep, v);
+        mom_node_populations<L, ORDER>(m, n, k, rx, v);
         node_diag<L>(v, 0, k, rho_o, ux_o, uy_o, th_o, val);
     }
     block_sums<MOM_NS>(val, partial);
@@ -528,7 +524,7 @@ bool lattice_info(int lattice, LatInfo* out)
 
 struct lbm_ctx {
     int lattice = 0, nx = 0, ny = 0, order = 2;
-    double tau = 1.0;
+    double tau = 1.0, tau3 = 1.0, tau4 = 1.0; // tau_2 = tau; ranks 3, 4 (lbm_set_relaxation)
     uint32_t flags = 0;
     int store = ST_F64, coll = COLL_RR;
     bool thermal = false, a13p = false;
@@ -553,26 +549,32 @@ struct lbm_ctx {
 
 namespace {
 
+Relax relax_of(const lbm_ctx* c)
+{
+    return Relax{ 1.0 - 1.0 / c->tau, c->order >= 3 ? 1.0 - 1.0 / c->tau3 : 0.0,
+                  c->order >= 4 ? 1.0 - 1.0 / c->tau4 : 0.0, 1.0 / c->tau };
+}
+
 // ---- moment representation: per-lattice launches (order as a template argument)
 template <class L, int ORDER>
 hipError_t mom_launch(const lbm_ctx* c, int what, const void* fin, void* fout, InitArgs* ia, double* out, double* r,
                       double* ux, double* uy, double* th)
 {
     const int64_t n = int64_t(c->nx) * c->ny;
-    const double keep = 1.0 - 1.0 / c->tau;
+    const Relax rx = relax_of(c);
     const double* m = static_cast<const double*>(c->buf[c->cur]);
     const dim3 grid(unsigned((n + 255) / 256)), block(256);
     switch (what) {
     case 0: k_mom_init<L><<<grid, block, 0, c->stream>>>(*ia); break;
-    case 1: k_mom_populations<L, ORDER><<<grid, block, 0, c->stream>>>(m, n, keep, out); break;
+    case 1: k_mom_populations<L, ORDER><<<grid, block, 0, c->stream>>>(m, n, rx, out); break;
     case 2:
-        k_mom_moments<L, ORDER><<<dim3(unsigned(c->nblk)), block, 0, c->stream>>>(m, n, keep, r, ux, uy, th,
+        k_mom_moments<L, ORDER><<<dim3(unsigned(c->nblk)), block, 0, c->stream>>>(m, n, rx, r, ux, uy, th,
                                                                                  c->partial);
         break;
     default: {
         const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
         k_mom_step<L, ORDER><<<dim3(unsigned(bxn * byn)), dim3(BX, BY), 0, c->stream>>>(
-            static_cast<const double*>(fin), static_cast<double*>(fout), c->nx, c->ny, bxn, keep);
+            static_cast<const double*>(fin), static_cast<double*>(fout), c->nx, c->ny, bxn, rx);
     }
     }
     return hipGetLastError();
@@ -605,8 +607,7 @@ template <class L, class S, int COLL, bool TH, bool A13P>
 hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
     const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
-    StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, 1.0 - 1.0 / c->tau, 1.0 / c->tau, c->order,
-                pull ? uint32_t(c->steps + 1) : 0u };
+    StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, relax_of(c), pull ? uint32_t(c->steps + 1) : 0u };
     dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if constexpr (L::id == LBM_D2V37 && COLL == COLL_RR && !TH) {
         if (pull && c->closure) {
@@ -818,6 +819,8 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     c->nx = nx;
     c->ny = ny;
     c->tau = tau;
+    c->tau3 = tau;
+    c->tau4 = tau;
     c->order = (flags & LBM_COLL_BGK) ? 2 : reg_order;
     c->flags = flags;
     c->store = (flags & LBM_STORE_FP32)      ? ST_F32
@@ -868,6 +871,17 @@ int lbm_step(lbm_ctx* c, int nsteps)
 }
 
 int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->steps : -1; }
+
+int lbm_set_relaxation(lbm_ctx* c, double tau3, double tau4)
+{
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->coll == COLL_BGK) return fail(LBM_EINVAL, "BGK has a single relaxation time");
+    if (!std::isfinite(tau3) || !(tau3 > 0.5) || !std::isfinite(tau4) || !(tau4 > 0.5))
+        return fail(LBM_ETAU, "tau3 and tau4 must be finite and > 1/2");
+    c->tau3 = tau3;
+    c->tau4 = tau4;
+    return LBM_OK;
+}
 
 int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* theta, double* vort, double* sums)
 {
@@ -1004,9 +1018,7 @@ int batch_prepare(lbm_batch* b)
         d.lattice = c->lattice;
         d.bx_blocks = (c->nx + b->tile_x - 1) / b->tile_x;
         d.flip = c->cur;
-        d.order = c->order;
-        d.keep = 1.0 - 1.0 / c->tau;
-        d.inv_tau = 1.0 / c->tau;
+        d.rx = relax_of(c);
         d.seq = uint32_t(c->steps + 1);
         b->begin[i] = int(total);
         total += int64_t(d.bx_blocks) * ((c->ny + BY - 1) / BY);
@@ -1036,7 +1048,8 @@ int batch_prepare(lbm_batch* b)
 }
 
 // If a member was stepped on its own (or an odd step count left the device's
-// dither keys behind), refresh the parities and keys on the device.
+// dither keys behind, or its relaxation times changed), refresh the
+// parities, keys and relaxation factors on the device.
 int batch_sync_parity(lbm_batch* b)
 {
     const bool dither = b->store == ST_BF16;
@@ -1050,6 +1063,11 @@ int batch_sync_parity(lbm_batch* b)
         }
         if (dither && d.seq != uint32_t(c->steps + 1)) {
             d.seq = uint32_t(c->steps + 1);
+            stale = true;
+        }
+        const Relax rx = relax_of(c);
+        if (d.rx.k2 != rx.k2 || d.rx.k3 != rx.k3 || d.rx.k4 != rx.k4 || d.rx.inv_tau != rx.inv_tau) {
+            d.rx = rx;
             stale = true;
         }
     }

@@ -98,7 +98,8 @@ def test_init_rejects_invalid_arguments(args, code):
 
 
 def test_null_context_is_rejected():
-    for fn in (lambda: b.lbm_step(None, 1), lambda: b.lbm_moments(None), lambda: b.lbm_populations(None, None)):
+    for fn in (lambda: b.lbm_step(None, 1), lambda: b.lbm_moments(None), lambda: b.lbm_populations(None, None),
+               lambda: b.lbm_set_relaxation(None, 0.7, 0.7)):
         with pytest.raises(b.LbmError):
             fn()
     b.lbm_destroy(None)

@@ -259,3 +259,51 @@ def test_fp64_d2v37_full_size_sampled(orc, b):
     assert sums[8] == 0
     mass0 = float(rho.sum()) + 1e-8 * float(lat.w @ noise.reshape(lat.Q, -1).sum(1))
     assert sums[0] == pytest.approx(mass0, rel=1e-13)
+
+
+@pytest.mark.parametrize("name,coll,flags", [("D2Q9", "rr", 0), ("D2V17", "rr", 0), ("D2V37", "rr", 0),
+                                             ("D2V37", "pr", 0), ("D2V37", "rr", "moments"),
+                                             ("D2V17", "rr", "moments")])
+def test_fp64_per_order_relaxation(orc, b, name, coll, flags):
+    """Ranks 3 and 4 relaxed with their own times (lbm_set_relaxation)."""
+    nx, ny, tau3, tau4 = 40, 36, 0.62, 0.9
+    say(f"per-order relaxation {name} {coll} {flags or 'populations'}")
+    lat, u0, tau, fields, f0 = shear_case(orc, name, nx, ny, re=3e3)
+    rho, ux, uy, th, noise = fields
+    fl = (b.LBM_COLL_PR if coll == "pr" else 0) | (b.LBM_STORE_MOMENTS if flags == "moments" else 0)
+    sim = b.Simulation(name, nx, ny, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, flags=fl)
+    sim.set_relaxation(tau3, tau4)
+    sim.step(10)
+    got = sim.populations().cpu().numpy()
+    sim.close()
+    c = orc.PR if coll == "pr" else orc.RR
+    if flags == "moments":
+        # the state is the pre-collision moments: every rebuild, the first one
+        # included, uses the times in force
+        g = orc.step(lat, f0, tau, 10, coll=c, tau3=tau3, tau4=tau4)
+    else:
+        # the stored initial state is C(f0) with the single time (set_relaxation
+        # comes after lbm_init)
+        g = orc.stream(lat, orc.collide(lat, f0, tau, coll=c))
+        g = orc.step(lat, g, tau, 9, coll=c, tau3=tau3, tau4=tau4)
+    want = orc.collide(lat, g, tau, coll=c, tau3=tau3, tau4=tau4)
+    check(got, want, 1e-12)
+    assert np.abs(want - orc.collide(lat, orc.step(lat, f0, tau, 10, coll=c), tau, coll=c)).max() > 1e-10
+
+
+def test_fp64_thermal_per_order_relaxation(orc, b):
+    """Thermal D2V37 Sod with Pr = (tau - 1/2)/(tau3 - 1/2) = 0.5."""
+    say("thermal per-order relaxation")
+    lat = orc.lattice("D2V37")
+    nx, ny, tau, tau3 = 400, 4, 0.6, 0.7
+    rho, ux, uy, th = wl.sod_fields(nx, ny)
+    sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_THERMAL)
+    sim.set_relaxation(tau3, tau)
+    sim.step(30)
+    got = sim.populations().cpu().numpy()
+    sim.close()
+    f0 = orc.init_populations(lat, rho, ux, uy, th)
+    g = orc.stream(lat, orc.collide(lat, f0, tau, thermal=True))
+    g = orc.step(lat, g, tau, 29, thermal=True, tau3=tau3, tau4=tau)
+    want = orc.collide(lat, g, tau, thermal=True, tau3=tau3, tau4=tau)
+    check(got, want, 1e-11)
