@@ -44,8 +44,10 @@ constexpr double hc(int cx, int cy, int a, int b)
 // theta = 1) and A_I the rank-2..ORDER terms of the expansion after the
 // isothermal recursion, each weighted by its relaxation factor k_n: linear in
 // a1^(2) with coefficients polynomial in u (degree 0, 1, 2 for ranks 2, 3,
-// 4).  Every h is a compile-time constant; zero terms are left out.
-template <class L, int I, int ORDER>
+// 4).  Every h is a compile-time constant; zero terms are left out.  PO:
+// per-order factors; otherwise k3 = k4 = k2 on the kept ranks and the common
+// factor is applied once.
+template <class L, int I, int ORDER, bool PO>
 __device__ __forceinline__ double mom_pop(double r, double ux, double uy, double axx, double axy, double ayy,
                                           const Relax& rx)
 {
@@ -88,42 +90,42 @@ __device__ __forceinline__ double mom_pop(double r, double ux, double uy, double
     double n = 0.0;
     {
         double c = 0.0, p3 = 0.0, p4 = 0.0;
-        if constexpr (h20 != 0.0) c += rx.k2 * h20;
+        if constexpr (h20 != 0.0) c += (PO ? rx.k2 : 1.0) * h20;
         if constexpr (cxx_x != 0.0) p3 += cxx_x * ux;
         if constexpr (cxx_y != 0.0) p3 += cxx_y * uy;
         if constexpr (cxx_x2 != 0.0) p4 += cxx_x2 * x2;
         if constexpr (cxx_xy != 0.0) p4 += cxx_xy * xy;
         if constexpr (cxx_y2 != 0.0) p4 += cxx_y2 * y2;
-        if constexpr (cxx_x != 0.0 || cxx_y != 0.0) c += rx.k3 * p3;
-        if constexpr (cxx_x2 != 0.0 || cxx_xy != 0.0 || cxx_y2 != 0.0) c += rx.k4 * p4;
+        if constexpr (cxx_x != 0.0 || cxx_y != 0.0) c += PO ? rx.k3 * p3 : p3;
+        if constexpr (cxx_x2 != 0.0 || cxx_xy != 0.0 || cxx_y2 != 0.0) c += PO ? rx.k4 * p4 : p4;
         n += c * axx;
     }
     {
         double c = 0.0, p3 = 0.0, p4 = 0.0;
-        if constexpr (h11 != 0.0) c += rx.k2 * h11;
+        if constexpr (h11 != 0.0) c += (PO ? rx.k2 : 1.0) * h11;
         if constexpr (cxy_x != 0.0) p3 += cxy_x * ux;
         if constexpr (cxy_y != 0.0) p3 += cxy_y * uy;
         if constexpr (cxy_x2 != 0.0) p4 += cxy_x2 * x2;
         if constexpr (cxy_xy != 0.0) p4 += cxy_xy * xy;
         if constexpr (cxy_y2 != 0.0) p4 += cxy_y2 * y2;
-        if constexpr (cxy_x != 0.0 || cxy_y != 0.0) c += rx.k3 * p3;
-        if constexpr (cxy_x2 != 0.0 || cxy_xy != 0.0 || cxy_y2 != 0.0) c += rx.k4 * p4;
+        if constexpr (cxy_x != 0.0 || cxy_y != 0.0) c += PO ? rx.k3 * p3 : p3;
+        if constexpr (cxy_x2 != 0.0 || cxy_xy != 0.0 || cxy_y2 != 0.0) c += PO ? rx.k4 * p4 : p4;
         n += c * axy;
     }
     {
         double c = 0.0, p3 = 0.0, p4 = 0.0;
-        if constexpr (h02 != 0.0) c += rx.k2 * h02;
+        if constexpr (h02 != 0.0) c += (PO ? rx.k2 : 1.0) * h02;
         if constexpr (cyy_x != 0.0) p3 += cyy_x * ux;
         if constexpr (cyy_y != 0.0) p3 += cyy_y * uy;
         if constexpr (cyy_x2 != 0.0) p4 += cyy_x2 * x2;
         if constexpr (cyy_xy != 0.0) p4 += cyy_xy * xy;
         if constexpr (cyy_y2 != 0.0) p4 += cyy_y2 * y2;
-        if constexpr (cyy_x != 0.0 || cyy_y != 0.0) c += rx.k3 * p3;
-        if constexpr (cyy_x2 != 0.0 || cyy_xy != 0.0 || cyy_y2 != 0.0) c += rx.k4 * p4;
+        if constexpr (cyy_x != 0.0 || cyy_y != 0.0) c += PO ? rx.k3 * p3 : p3;
+        if constexpr (cyy_x2 != 0.0 || cyy_xy != 0.0 || cyy_y2 != 0.0) c += PO ? rx.k4 * p4 : p4;
         n += c * ayy;
     }
     constexpr double w = L::v.w[I];
-    return w * (r * e + n);
+    return PO ? w * (r * e + n) : w * (r * e + rx.k2 * n);
 }
 
 // Moments (rho, ux, uy, a1^(2)) of the populations v of one node.
@@ -152,7 +154,7 @@ __device__ __forceinline__ void node_state(const double (&v)[L::Q], double (&m)[
 // One step on a BX x BY tile: the tile's moments and a halo of the lattice
 // reach are staged in LDS (periodic wrap), each thread pulls its Q
 // populations from there and writes its node's new moments.
-template <class L, int ORDER>
+template <class L, int ORDER, bool PO>
 __global__ __launch_bounds__(BX* BY) void k_mom_step(const double* __restrict__ min, double* __restrict__ mout, int nx,
                                                      int ny, int bx_blocks, Relax rx)
 {
@@ -188,7 +190,7 @@ __global__ __launch_bounds__(BX* BY) void k_mom_step(const double* __restrict__ 
     static_for<L::Q>([&](auto I) {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
         const int ly = int(threadIdx.y) + R - cy, lx = int(threadIdx.x) + R - cx;
-        const double f = mom_pop<L, int(I), ORDER>(sm[0][ly][lx], sm[1][ly][lx], sm[2][ly][lx], sm[3][ly][lx],
+        const double f = mom_pop<L, int(I), ORDER, PO>(sm[0][ly][lx], sm[1][ly][lx], sm[2][ly][lx], sm[3][ly][lx],
                                                    sm[4][ly][lx], sm[5][ly][lx], rx);
         r += f;
         if constexpr (cx != 0) jx += double(cx) * f;
@@ -234,7 +236,7 @@ __device__ __forceinline__ void mom_node_populations(const double* __restrict__ 
 {
     const double r = m[k], ux = m[n + k], uy = m[2 * n + k];
     const double axx = m[3 * n + k], axy = m[4 * n + k], ayy = m[5 * n + k];
-    static_for<L::Q>([&](auto I) { v[I] = mom_pop<L, int(I), ORDER>(r, ux, uy, axx, axy, ayy, rx); });
+    static_for<L::Q>([&](auto I) { v[I] = mom_pop<L, int(I), ORDER, true>(r, ux, uy, axx, axy, ayy, rx); });
 }
 
 } // namespace rr

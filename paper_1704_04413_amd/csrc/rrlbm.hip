@@ -573,8 +573,13 @@ hipError_t mom_launch(const lbm_ctx* c, int what, const void* fin, void* fout, I
         break;
     default: {
         const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
-        k_mom_step<L, ORDER><<<dim3(unsigned(bxn * byn)), dim3(BX, BY), 0, c->stream>>>(
-            static_cast<const double*>(fin), static_cast<double*>(fout), c->nx, c->ny, bxn, rx);
+        const dim3 g(unsigned(bxn * byn)), blk(BX, BY);
+        const double* a = static_cast<const double*>(fin);
+        double* o = static_cast<double*>(fout);
+        if (c->tau3 == c->tau && c->tau4 == c->tau)
+            k_mom_step<L, ORDER, false><<<g, blk, 0, c->stream>>>(a, o, c->nx, c->ny, bxn, rx);
+        else
+            k_mom_step<L, ORDER, true><<<g, blk, 0, c->stream>>>(a, o, c->nx, c->ny, bxn, rx);
     }
     }
     return hipGetLastError();
