@@ -56,6 +56,10 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_D2Q9 0  /* E^9_{2,5},  c_s^2 = 1/3, basis 1,x,y,xx,xy,yy,xxy,xyy,xxyy */
 #define LBM_D2V17 1 /* E^17_{2,7}, all Hermite tensors of rank <= 3           */
 #define LBM_D2V37 2 /* E^37_{2,9}, all Hermite tensors of rank <= 4           */
+/* 3D lattices (Table II); isothermal, FP64 populations, lbm_*_3d entry points. */
+#define LBM_D3Q19 3 /* E^19_{3,5}, c_s^2 = 1/3, ranks <= 2 and the six xxy-type rank-3 tensors */
+#define LBM_D3Q27 4 /* E^27_{3,5}, c_s^2 = 1/3, the 27 products with each exponent <= 2 */
+#define LBM_D3V39 5 /* E^39_{3,7}, c_s^2 = 2/3, all Hermite tensors of rank <= 3 */
 
 /* Flags for lbm_init (bitwise OR). */
 #define LBM_THERMAL 0x1u        /* thermal/compressible form; D2V37 only          */
@@ -74,8 +78,8 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_EDEVICE (-3)  /* a HIP call failed                                    */
 #define LBM_ENOMEM (-4)   /* the context could not allocate its scratch           */
 
-/* Lattice constants (Table I).  Any output pointer may be NULL.
- * q: number of velocities; reach: largest |c_x| or |c_y|; n_eq: highest
+/* Lattice constants (Tables I and II).  Any output pointer may be NULL.
+ * q: number of velocities; reach: largest velocity component; n_eq: highest
  * Hermite rank of the basis (the order the equilibrium is expanded to);
  * cs2: c_s^2 in lattice units.  Returns LBM_EINVAL for an unknown lattice. */
 int lbm_lattice_info(int lattice, int* q, int* reach, int* n_eq, double* cs2);
@@ -162,6 +166,51 @@ void lbm_destroy(lbm_ctx* ctx);
 
 /* Message describing the last error on the calling thread ("" if none). */
 const char* lbm_last_error(void);
+
+/* ---- 3D lattices (Table II) ---------------------------------------------
+ * Isothermal recursive regularization (the 3D forms of the recursion in
+ * App. C, Eq. MalaspinasRecursiveRelation at theta = 1), projection-based
+ * regularization or BGK on D3Q19, D3Q27 and D3V39, FP64 populations.  Grids
+ * are periodic nx by ny by nz; fields are [z][y][x] (nx*ny*nz doubles) and
+ * populations exchanged with the caller are [i][z][y][x].  The layout is the
+ * 2D one over the ny*nz rows r = z*ny + y.  A 3D context works with
+ * lbm_step, lbm_step_count, lbm_populations and lbm_destroy; lbm_moments,
+ * lbm_set_relaxation, batches and the closure reject it. */
+
+/* Velocities (ascending c_z, then c_y, then c_x) and weights of a 3D lattice;
+ * host arrays of q entries (any may be NULL).  LBM_EINVAL for a 2D id. */
+int lbm_lattice_velocities_3d(int lattice, int* cx, int* cy, int* cz, double* w);
+
+/* Doubles one state buffer holds: q * nx * (ny*nz rounded up to a multiple of
+ * 4).  flags must carry no LBM_STORE_* bit.  Negative on error. */
+int64_t lbm_buffer_elems_3d(int lattice, int nx, int ny, int nz, uint32_t flags);
+
+/* Creates a 3D context and writes the initial state, the equilibrium of
+ * (rho, u) over the lattice's basis (LBM_EQ_INIT_ORDER2: ranks <= 2) plus
+ * noise_amp * w_i * noise[i][z][y][x], collided once (the kept state is
+ * post-collision, as in 2D).
+ *   lattice    LBM_D3Q19, LBM_D3Q27 or LBM_D3V39.
+ *   nx, ny, nz each >= the lattice reach; lbm_buffer_elems_3d() < 2^31.
+ *   tau        discrete relaxation time (> 1/2), nu = c_s^2 (tau - 1/2).
+ *   reg_order  2 <= N <= n_eq (3, 6, 3); ignored with LBM_COLL_BGK.
+ *   flags      LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2 only.
+ *   f_a, f_b   two distinct device buffers of lbm_buffer_elems_3d() doubles,
+ *              owned by the caller for the context's lifetime.
+ *   rho, ux, uy, uz  device fields; noise device [q][z][y][x] or NULL.
+ * Same errors as lbm_init. */
+int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, int reg_order, uint32_t flags,
+                void* f_a, void* f_b, const double* rho, const double* ux, const double* uy, const double* uz,
+                const double* noise, double noise_amp, void* stream);
+
+/* Fields of the current step of a 3D context: rho, ux, uy, uz device FP64
+ * arrays or NULL.  sums: host array of LBM_NSUMS_3D doubles or NULL; when
+ * given the call synchronizes the stream and fills, over all nodes,
+ *   [0] sum rho  [1] sum rho ux  [2] sum rho uy  [3] sum rho uz
+ *   [4] sum_i f_i |c_i|^2 / 2    [5] sum |u|^2   [6] sum |u|^4
+ *   [7] non-finite nodes
+ * LBM_EINVAL for a 2D context. */
+#define LBM_NSUMS_3D 8
+int lbm_moments_3d(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* uz, double* sums);
 
 /* ---- Batched stepping ----------------------------------------------------
  * Many independent contexts (any lattice and grid size) advanced together:

@@ -15,7 +15,9 @@ import numpy as np
 LIB_PATH = os.environ.get("RRLBM_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "librrlbm.so")
 
 LBM_D2Q9, LBM_D2V17, LBM_D2V37 = 0, 1, 2
-LATTICES = {"D2Q9": LBM_D2Q9, "D2V17": LBM_D2V17, "D2V37": LBM_D2V37}
+LBM_D3Q19, LBM_D3Q27, LBM_D3V39 = 3, 4, 5
+LATTICES = {"D2Q9": LBM_D2Q9, "D2V17": LBM_D2V17, "D2V37": LBM_D2V37,
+            "D3Q19": LBM_D3Q19, "D3Q27": LBM_D3Q27, "D3V39": LBM_D3V39}
 LBM_THERMAL = 0x1
 LBM_STORE_FP32 = 0x2
 LBM_STORE_BF16 = 0x4
@@ -25,6 +27,7 @@ LBM_COLL_BGK = 0x20
 LBM_EQ_INIT_ORDER2 = 0x100
 LBM_A13_PROJECTED = 0x200
 LBM_NSUMS = 10
+LBM_NSUMS_3D = 8
 
 LBM_OK, LBM_EINVAL, LBM_ETAU, LBM_EDEVICE, LBM_ENOMEM = 0, -1, -2, -3, -4
 
@@ -33,7 +36,8 @@ EXPORTS = ["lbm_lattice_info", "lbm_lattice_velocities", "lbm_buffer_elems", "lb
            "lbm_step_count", "lbm_set_relaxation", "lbm_moments", "lbm_populations", "lbm_destroy", "lbm_last_error",
            "lbm_batch_create", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_config", "lbm_batch_destroy",
            "lbm_closure_samples", "lbm_mlp_stats", "lbm_mlp_normalize", "lbm_mlp_create", "lbm_mlp_forward",
-           "lbm_mlp_step", "lbm_mlp_destroy", "lbm_closure_set", "lbm_closure_fallbacks"]
+           "lbm_mlp_step", "lbm_mlp_destroy", "lbm_closure_set", "lbm_closure_fallbacks",
+           "lbm_lattice_velocities_3d", "lbm_buffer_elems_3d", "lbm_init_3d", "lbm_moments_3d"]
 LBM_MLP_NPARAM = 5776
 LBM_MLP_NNORM = 96
 
@@ -89,6 +93,13 @@ def lib():
         L.lbm_mlp_destroy.restype = None
         L.lbm_closure_set.argtypes = [vp, vp, vp]
         L.lbm_closure_fallbacks.argtypes = [vp, ctypes.POINTER(ctypes.c_int64)]
+        ci = ctypes.c_int
+        L.lbm_lattice_velocities_3d.argtypes = [ci, ip, ip, ip, dp]
+        L.lbm_buffer_elems_3d.argtypes = [ci, ci, ci, ci, ctypes.c_uint32]
+        L.lbm_buffer_elems_3d.restype = ctypes.c_int64
+        L.lbm_init_3d.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ci, ctypes.c_double, ci, ctypes.c_uint32,
+                                  vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp]
+        L.lbm_moments_3d.argtypes = [vp, vp, vp, vp, vp, dp]
         _lib = L
     return _lib
 
@@ -168,6 +179,36 @@ def lbm_populations(ctx, f_out):
 
 def lbm_destroy(ctx):
     lib().lbm_destroy(ctypes.c_void_p(ctx))
+
+
+def lbm_lattice_velocities_3d(lattice):
+    q = lbm_lattice_info(lattice)[0]
+    cx, cy, cz, w = (ctypes.c_int * q)(), (ctypes.c_int * q)(), (ctypes.c_int * q)(), (ctypes.c_double * q)()
+    _check(lib().lbm_lattice_velocities_3d(lattice_id(lattice), cx, cy, cz, w))
+    return np.array(list(cx)), np.array(list(cy)), np.array(list(cz)), np.array(list(w))
+
+
+def lbm_buffer_elems_3d(lattice, nx, ny, nz, flags=0) -> int:
+    n = lib().lbm_buffer_elems_3d(lattice_id(lattice), nx, ny, nz, flags)
+    if n < 0:
+        raise LbmError(int(n), lbm_last_error())
+    return int(n)
+
+
+def lbm_init_3d(lattice, nx, ny, nz, tau, reg_order, flags, f_a, f_b, rho, ux, uy, uz, noise=None,
+                noise_amp=0.0, stream=None):
+    """Returns the context handle (an integer)."""
+    ctx = ctypes.c_void_p()
+    s = ctypes.c_void_p(stream.cuda_stream if stream is not None else 0)
+    _check(lib().lbm_init_3d(ctypes.byref(ctx), lattice_id(lattice), nx, ny, nz, tau, reg_order, flags, _ptr(f_a),
+                             _ptr(f_b), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(uz), _ptr(noise), noise_amp, s))
+    return ctx.value
+
+
+def lbm_moments_3d(ctx, rho=None, ux=None, uy=None, uz=None, sums=False):
+    out = (ctypes.c_double * LBM_NSUMS_3D)() if sums else None
+    _check(lib().lbm_moments_3d(ctypes.c_void_p(ctx), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(uz), out))
+    return np.array(list(out)) if sums else None
 
 
 def lbm_batch_create(ctxs, tile_x=64, blocks_per_cu=4):
@@ -316,3 +357,45 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+class Simulation3D(Simulation):
+    """A 3D context (Table II lattices, FP64 populations) and its buffers;
+    fields are [z][y][x] arrays."""
+
+    def __init__(self, lattice, nx, ny, nz, tau, rho, ux, uy, uz, noise=None, noise_amp=0.0, reg_order=None,
+                 flags=0, device="cuda:0", stream=None):
+        import torch
+
+        self.torch = torch
+        self.lattice = lattice_id(lattice)
+        self.q, self.reach, self.n_eq, self.cs2 = lbm_lattice_info(self.lattice)
+        self.nx, self.ny, self.nz, self.tau, self.flags = nx, ny, nz, tau, flags
+        self.reg_order = self.n_eq if reg_order is None else reg_order
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        n = lbm_buffer_elems_3d(self.lattice, nx, ny, nz, flags)
+        self.bufs = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(2)]
+
+        def dev(a):
+            if a is None:
+                return None
+            t = torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64)) if isinstance(a, np.ndarray) else a
+            return t.to(self.device, torch.float64).contiguous()
+
+        fields = [dev(a) for a in (rho, ux, uy, uz, noise)]
+        self.ctx = lbm_init_3d(self.lattice, nx, ny, nz, tau, self.reg_order, flags, self.bufs[0], self.bufs[1],
+                               *fields, noise_amp=noise_amp, stream=self.stream)
+        self._keep = fields
+
+    def populations(self):
+        t = self.torch.empty((self.q, self.nz, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
+        lbm_populations(self.ctx, t)
+        return t
+
+    def moments(self, sums=True):
+        torch = self.torch
+        mk = lambda: torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        rho, ux, uy, uz = mk(), mk(), mk(), mk()
+        s = lbm_moments_3d(self.ctx, rho, ux, uy, uz, sums=sums)
+        return dict(rho=rho, ux=ux, uy=uy, uz=uz, sums=s)

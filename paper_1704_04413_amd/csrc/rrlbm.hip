@@ -476,6 +476,8 @@ __global__ __launch_bounds__(256) void k_vorticity(const double* ux, const doubl
 
 } // namespace rr
 
+#include "collide3d.hpp"
+
 // ================================================================== C-ABI
 
 using namespace rr;
@@ -509,12 +511,17 @@ LatInfo info_of()
     return { L::Q, L::R, L::NEQ, L::cs2 };
 }
 
+bool is_3d(int lattice) { return lattice == LBM_D3Q19 || lattice == LBM_D3Q27 || lattice == LBM_D3V39; }
+
 bool lattice_info(int lattice, LatInfo* out)
 {
     switch (lattice) {
     case LBM_D2Q9: *out = info_of<D2Q9>(); return true;
     case LBM_D2V17: *out = info_of<D2V17>(); return true;
     case LBM_D2V37: *out = info_of<D2V37>(); return true;
+    case LBM_D3Q19: *out = info_of<D3Q19>(); return true;
+    case LBM_D3Q27: *out = info_of<D3Q27>(); return true;
+    case LBM_D3V39: *out = info_of<D3V39>(); return true;
     }
     return false;
 }
@@ -524,6 +531,7 @@ bool lattice_info(int lattice, LatInfo* out)
 
 struct lbm_ctx {
     int lattice = 0, nx = 0, ny = 0, order = 2;
+    int nz = 1, dim = 2; // 3D lattices: rows r = z * ny + y of the layout
     double tau = 1.0, tau3 = 1.0, tau4 = 1.0; // tau_2 = tau; ranks 3, 4 (lbm_set_relaxation)
     uint32_t flags = 0;
     int store = ST_F64, coll = COLL_RR;
@@ -659,8 +667,45 @@ hipError_t launch_step_l(const lbm_ctx* c, const void* fin, void* fout, bool pul
     }
 }
 
+// ---- 3D lattices (FP64 populations)
+template <class L, int MODE>
+hipError_t launch_step3_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
+{
+    const int rows = c->ny * c->nz;
+    const int bxn = (c->nx + BX - 1) / BX, byn = (rows + BY - 1) / BY;
+    Step3Args a{ fin, fout, c->lay, c->ny, c->nz, bxn, relax_of(c), c->order };
+    const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
+    if (pull)
+        k_stream_collide3<L, MODE, true><<<grid, block, 0, c->stream>>>(a);
+    else
+        k_stream_collide3<L, MODE, false><<<grid, block, 0, c->stream>>>(a);
+    return hipGetLastError();
+}
+
+template <class L>
+hipError_t launch_step3_l(const lbm_ctx* c, const void* fin, void* fout, bool pull)
+{
+    switch (c->coll) {
+    case COLL_PR: return launch_step3_t<L, C3_PR>(c, fin, fout, pull);
+    case COLL_BGK: return launch_step3_t<L, C3_BGK>(c, fin, fout, pull);
+    default: return launch_step3_t<L, C3_RR>(c, fin, fout, pull);
+    }
+}
+
+template <class F>
+hipError_t on_lattice3(int lattice, F&& f)
+{
+    switch (lattice) {
+    case LBM_D3Q19: return f(D3Q19{});
+    case LBM_D3Q27: return f(D3Q27{});
+    default: return f(D3V39{});
+    }
+}
+
 hipError_t launch_step(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
+    if (c->dim == 3)
+        return on_lattice3(c->lattice, [&](auto l) { return launch_step3_l<decltype(l)>(c, fin, fout, pull); });
     if (c->store == ST_MOM) return mom_launch_any(c, 3, fin, fout);
     switch (c->lattice) {
     case LBM_D2Q9: return launch_step_l<D2Q9>(c, fin, fout, pull);
@@ -729,6 +774,7 @@ struct MomOp {
 int validate(int lattice, int nx, int ny, double tau, int reg_order, uint32_t flags, LatInfo* li)
 {
     if (!lattice_info(lattice, li)) return fail(LBM_EINVAL, "unknown lattice " + std::to_string(lattice));
+    if (is_3d(lattice)) return fail(LBM_EINVAL, "3D lattice: use lbm_init_3d");
     if (nx < li->reach || ny < li->reach || nx < 1 || ny < 1)
         return fail(LBM_EINVAL, "grid " + std::to_string(nx) + "x" + std::to_string(ny) +
                                     " smaller than the lattice reach " + std::to_string(li->reach));
@@ -783,7 +829,7 @@ int lbm_lattice_velocities(int lattice, int* cx, int* cy, double* w)
     case LBM_D2Q9: t = &D2Q9::v; break;
     case LBM_D2V17: t = &D2V17::v; break;
     case LBM_D2V37: t = &D2V37::v; break;
-    default: return fail(LBM_EINVAL, "unknown lattice");
+    default: return fail(LBM_EINVAL, is_3d(lattice) ? "3D lattice: use lbm_lattice_velocities_3d" : "unknown lattice");
     }
     for (int i = 0; i < t->q; ++i) {
         if (cx) cx[i] = t->cx[i];
@@ -797,6 +843,7 @@ int64_t lbm_buffer_elems(int lattice, int nx, int ny, uint32_t flags)
 {
     LatInfo li;
     if (!lattice_info(lattice, &li)) return fail(LBM_EINVAL, "unknown lattice");
+    if (is_3d(lattice)) return fail(LBM_EINVAL, "3D lattice: use lbm_buffer_elems_3d");
     if (nx < 1 || ny < 1) return fail(LBM_EINVAL, "empty grid");
     if (flags & LBM_STORE_MOMENTS) return int64_t(MOM_K) * nx * ny;
     return layout_elems(li.q, nx, ny);
@@ -881,6 +928,7 @@ int lbm_set_relaxation(lbm_ctx* c, double tau3, double tau4)
 {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (c->coll == COLL_BGK) return fail(LBM_EINVAL, "BGK has a single relaxation time");
+    if (c->dim == 3) return fail(LBM_EINVAL, "3D contexts have a single relaxation time");
     if (!std::isfinite(tau3) || !(tau3 > 0.5) || !std::isfinite(tau4) || !(tau4 > 0.5))
         return fail(LBM_ETAU, "tau3 and tau4 must be finite and > 1/2");
     c->tau3 = tau3;
@@ -891,6 +939,7 @@ int lbm_set_relaxation(lbm_ctx* c, double tau3, double tau4)
 int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* theta, double* vort, double* sums)
 {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->dim == 3) return fail(LBM_EINVAL, "3D context: use lbm_moments_3d");
     const int64_t n = int64_t(c->nx) * c->ny;
     if (!c->fields) {
         HIP_TRY(hipMalloc(&c->fields, sizeof(double) * 5 * n));
@@ -930,10 +979,18 @@ int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* theta, 
 int lbm_populations(lbm_ctx* c, double* f_out)
 {
     if (!c || !f_out) return fail(LBM_EINVAL, "ctx or f_out is NULL");
-    if (c->store == ST_MOM)
+    if (c->dim == 3) {
+        const int64_t n = int64_t(c->nx) * c->ny * c->nz;
+        HIP_TRY(on_lattice3(c->lattice, [&](auto l) {
+            k_populations<decltype(l), StoreF64><<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream>>>(
+                c->buf[c->cur], c->lay, f_out);
+            return hipGetLastError();
+        }));
+    } else if (c->store == ST_MOM) {
         HIP_TRY(mom_launch_any(c, 1, nullptr, nullptr, nullptr, f_out));
-    else
+    } else {
         HIP_TRY(dispatch_ls<PopOp>(c, f_out));
+    }
     return LBM_OK;
 }
 
@@ -950,6 +1007,122 @@ void lbm_destroy(lbm_ctx* c)
 }
 
 const char* lbm_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------- 3D
+
+int lbm_lattice_velocities_3d(int lattice, int* cx, int* cy, int* cz, double* w)
+{
+    const VelTable3* t = nullptr;
+    switch (lattice) {
+    case LBM_D3Q19: t = &D3Q19::v; break;
+    case LBM_D3Q27: t = &D3Q27::v; break;
+    case LBM_D3V39: t = &D3V39::v; break;
+    default: return fail(LBM_EINVAL, "not a 3D lattice");
+    }
+    for (int i = 0; i < t->q; ++i) {
+        if (cx) cx[i] = t->cx[i];
+        if (cy) cy[i] = t->cy[i];
+        if (cz) cz[i] = t->cz[i];
+        if (w) w[i] = t->w[i];
+    }
+    return LBM_OK;
+}
+
+int64_t lbm_buffer_elems_3d(int lattice, int nx, int ny, int nz, uint32_t flags)
+{
+    LatInfo li;
+    if (!is_3d(lattice) || !lattice_info(lattice, &li)) return fail(LBM_EINVAL, "not a 3D lattice");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_EINVAL, "empty grid");
+    if (flags & (LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS))
+        return fail(LBM_EINVAL, "3D lattices store FP64 populations");
+    if (int64_t(ny) * nz >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "grid too large");
+    return layout_elems(li.q, nx, ny * nz);
+}
+
+int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, int reg_order, uint32_t flags,
+                void* f_a, void* f_b, const double* rho, const double* ux, const double* uy, const double* uz,
+                const double* noise, double noise_amp, void* stream)
+{
+    if (!out) return fail(LBM_EINVAL, "out is NULL");
+    LatInfo li;
+    if (!is_3d(lattice) || !lattice_info(lattice, &li)) return fail(LBM_EINVAL, "not a 3D lattice");
+    if (nx < li.reach || ny < li.reach || nz < li.reach || nx < 1 || ny < 1 || nz < 1)
+        return fail(LBM_EINVAL, "grid smaller than the lattice reach " + std::to_string(li.reach));
+    if (int64_t(ny) * nz >= (int64_t(1) << 31) || layout_elems(li.q, nx, ny * nz) >= (int64_t(1) << 31))
+        return fail(LBM_EINVAL, "grid too large");
+    if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_ETAU, "tau must be finite and > 1/2");
+    const uint32_t known = LBM_COLL_PR | LBM_COLL_BGK | LBM_EQ_INIT_ORDER2;
+    if (flags & ~known) return fail(LBM_EINVAL, "3D lattices take LBM_COLL_PR, LBM_COLL_BGK and LBM_EQ_INIT_ORDER2 only");
+    if ((flags & LBM_COLL_PR) && (flags & LBM_COLL_BGK)) return fail(LBM_EINVAL, "two collision flags");
+    if (!(flags & LBM_COLL_BGK) && (reg_order < 2 || reg_order > li.n_eq))
+        return fail(LBM_EINVAL, "regularization order must be in [2, " + std::to_string(li.n_eq) + "]");
+    if (!f_a || !f_b || f_a == f_b) return fail(LBM_EINVAL, "two distinct population buffers are needed");
+    if (!rho || !ux || !uy || !uz) return fail(LBM_EINVAL, "rho, ux, uy and uz are required");
+    if (!std::isfinite(noise_amp)) return fail(LBM_EINVAL, "noise_amp not finite");
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx;
+    if (!c) return fail(LBM_ENOMEM, "context allocation failed");
+    c->lattice = lattice;
+    c->dim = 3;
+    c->nx = nx;
+    c->ny = ny;
+    c->nz = nz;
+    c->tau = tau;
+    c->tau3 = tau;
+    c->tau4 = tau;
+    c->order = (flags & LBM_COLL_BGK) ? 2 : reg_order;
+    c->flags = flags;
+    c->store = ST_F64;
+    c->coll = (flags & LBM_COLL_PR) ? COLL_PR : (flags & LBM_COLL_BGK) ? COLL_BGK : COLL_RR;
+    c->q = li.q;
+    c->lay = make_layout(li.q, nx, ny * nz);
+    c->buf[0] = f_a;
+    c->buf[1] = f_b;
+    c->stream = static_cast<hipStream_t>(stream);
+    const int64_t n = int64_t(nx) * ny * nz;
+    c->nblk = (n + 255) / 256;
+    Init3Args ia{ f_a, c->lay, ny, nz, rho, ux, uy, uz, noise, noise_amp,
+                  (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq };
+    hipError_t he = on_lattice3(lattice, [&](auto l) {
+        k_init3<decltype(l)><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
+        return hipGetLastError();
+    });
+    if (he == hipSuccess) he = launch_step(c, f_a, f_a, false); // collide in place: post-collision state
+    if (he != hipSuccess) {
+        delete c;
+        return fail(LBM_EDEVICE, std::string("init launch: ") + hipGetErrorString(he));
+    }
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_moments_3d(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz, double* sums)
+{
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->dim != 3) return fail(LBM_EINVAL, "2D context: use lbm_moments");
+    const int64_t n = int64_t(c->nx) * c->ny * c->nz;
+    if (!c->fields) {
+        HIP_TRY(hipMalloc(&c->fields, sizeof(double) * 4 * n));
+        HIP_TRY(hipMalloc(&c->partial, sizeof(double) * MOM3_NS * c->nblk));
+        HIP_TRY(hipHostMalloc(&c->partial_host, sizeof(double) * MOM3_NS * c->nblk));
+    }
+    double* r = rho ? rho : c->fields;
+    double* vx = ux ? ux : c->fields + n;
+    double* vy = uy ? uy : c->fields + 2 * n;
+    double* vz = uz ? uz : c->fields + 3 * n;
+    HIP_TRY(on_lattice3(c->lattice, [&](auto l) {
+        k_moments3<decltype(l)><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(
+            static_cast<const double*>(c->buf[c->cur]), c->lay, c->ny, c->nz, r, vx, vy, vz, c->partial);
+        return hipGetLastError();
+    }));
+    if (sums) {
+        HIP_TRY(hipMemcpyAsync(c->partial_host, c->partial, sizeof(double) * MOM3_NS * c->nblk,
+                               hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
+        for (int s = 0; s < MOM3_NS; ++s) sums[s] = neumaier(c->partial_host + s, c->nblk, MOM3_NS);
+    }
+    return LBM_OK;
+}
 
 } // extern "C"
 
@@ -1097,6 +1270,7 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, i
     for (int i = 0; i < n; ++i) {
         const lbm_ctx* c = ctxs[i];
         if (!c) return fail(LBM_EINVAL, "NULL member");
+        if (c->dim == 3) return fail(LBM_EINVAL, "batch members must be 2D");
         if (c->coll != COLL_RR || c->thermal)
             return fail(LBM_EINVAL, "batch members must use the isothermal recursive regularization");
         if (c->store == ST_MOM) return fail(LBM_EINVAL, "batch members must store populations");

@@ -74,3 +74,23 @@ def uniform_noise(seed: int, q: int, ny: int, nx: int) -> np.ndarray:
     """U(-1, 1) samples of shape (q, ny, nx) from NumPy's PCG64 with `seed`."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-1.0, 1.0, size=(q, ny, nx))
+
+
+def shear_layer_fields_3d(nx: int, ny: int, nz: int, u0: float, k: float = 80.0, delta: float = 0.05):
+    """The doubly periodic shear layer extruded along z, with a second
+    perturbation u_z = u0 delta sin(2 pi (z + x)) so that the flow is
+    three-dimensional.  Returns rho, ux, uy, uz as float64 arrays [z, y, x]."""
+    rho2, ux2, uy2 = shear_layer_fields(nx, ny, u0, k, delta)
+    x = cell_centres(nx)[None, None, :]
+    z = cell_centres(nz)[:, None, None]
+    shape = (nz, ny, nx)
+    ux = np.broadcast_to(ux2[None], shape).copy()
+    uy = np.broadcast_to(uy2[None], shape).copy()
+    uz = np.broadcast_to(u0 * delta * np.sin(2.0 * np.pi * (z + x)), shape).copy()
+    return np.ones(shape), ux, uy, uz
+
+
+def uniform_noise_3d(seed: int, q: int, nz: int, ny: int, nx: int) -> np.ndarray:
+    """U(-1, 1) samples of shape (q, nz, ny, nx) from NumPy's PCG64 with `seed`."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return rng.uniform(-1.0, 1.0, size=(q, nz, ny, nx))

@@ -64,7 +64,8 @@ class FakePtr:
 
 
 @pytest.mark.parametrize("args,code", [
-    (dict(lattice=5), b.LBM_EINVAL),
+    (dict(lattice=9), b.LBM_EINVAL),
+    (dict(lattice=b.LBM_D3Q19), b.LBM_EINVAL),      # 3D lattices go through lbm_init_3d
     (dict(nx=2), b.LBM_EINVAL),                     # below the D2V37 reach
     (dict(ny=0), b.LBM_EINVAL),
     (dict(tau=0.5), b.LBM_ETAU),
@@ -116,3 +117,74 @@ def test_batch_rejects_invalid_arguments():
         with pytest.raises(b.LbmError):
             fn()
     b.lbm_batch_destroy(None)
+
+
+# ---------------------------------------------------------------- 3D
+
+@pytest.mark.parametrize("name", ["D3Q19", "D3Q27", "D3V39"])
+def test_3d_lattice_tables_agree_with_oracle(name):
+    from oracle import o3d
+
+    lat = o3d.lattice(name)
+    q, reach, n_eq, cs2 = b.lbm_lattice_info(name)
+    assert (q, n_eq) == (lat.Q, lat.nmax)
+    assert reach == int(np.abs(lat.c).max())
+    assert cs2 == pytest.approx(lat.cs2, rel=2e-16)
+    cx, cy, cz, w = b.lbm_lattice_velocities_3d(name)
+    np.testing.assert_array_equal(np.stack([cx, cy, cz], 1), lat.c)
+    np.testing.assert_allclose(w, lat.w, rtol=1e-15, atol=0)
+    with pytest.raises(b.LbmError):
+        b.lbm_lattice_velocities(name)
+    with pytest.raises(b.LbmError):
+        b.lbm_lattice_velocities_3d("D2Q9")
+
+
+def test_3d_buffer_elems():
+    for name in ("D3Q19", "D3Q27", "D3V39"):
+        q = b.lbm_lattice_info(name)[0]
+        for nx, ny, nz in ((1, 1, 1), (3, 5, 7), (64, 64, 64), (128, 128, 128)):
+            n = b.lbm_buffer_elems_3d(name, nx, ny, nz)
+            assert n >= q * nx * ny * nz
+            assert n == q * nx * (-(-(ny * nz) // 4) * 4)
+        with pytest.raises(b.LbmError):
+            b.lbm_buffer_elems_3d(name, 4, 4, 4, b.LBM_STORE_FP32)
+        with pytest.raises(b.LbmError):
+            b.lbm_buffer_elems(name, 4, 4)
+    with pytest.raises(b.LbmError):
+        b.lbm_buffer_elems_3d("D2V37", 4, 4, 4)
+    with pytest.raises(b.LbmError):
+        b.lbm_buffer_elems_3d("D3Q19", 4, 0, 4)
+
+
+@pytest.mark.parametrize("args,code", [
+    (dict(lattice=b.LBM_D2V37), b.LBM_EINVAL),
+    (dict(lattice=9), b.LBM_EINVAL),
+    (dict(nz=2), b.LBM_EINVAL),                       # below the D3V39 reach
+    (dict(nx=0), b.LBM_EINVAL),
+    (dict(nx=1 << 14, ny=1 << 14, nz=4), b.LBM_EINVAL),  # layout beyond 2^31 elements
+    (dict(tau=0.5), b.LBM_ETAU),
+    (dict(reg_order=4), b.LBM_EINVAL),                # D3V39 stops at rank 3
+    (dict(reg_order=1), b.LBM_EINVAL),
+    (dict(flags=b.LBM_STORE_FP32), b.LBM_EINVAL),
+    (dict(flags=b.LBM_THERMAL), b.LBM_EINVAL),
+    (dict(flags=b.LBM_COLL_PR | b.LBM_COLL_BGK), b.LBM_EINVAL),
+    (dict(same_buffers=True), b.LBM_EINVAL),
+    (dict(no_uz=True), b.LBM_EINVAL),
+])
+def test_init_3d_rejects_invalid_arguments(args, code):
+    p = dict(lattice=b.LBM_D3V39, nx=8, ny=8, nz=8, tau=0.6, reg_order=3, flags=0)
+    p.update({k: v for k, v in args.items() if k in p})
+    fa, fb = FakePtr(0x1000), FakePtr(0x2000)
+    if args.get("same_buffers"):
+        fb = fa
+    uz = None if args.get("no_uz") else FakePtr(0x6000)
+    with pytest.raises(b.LbmError) as e:
+        b.lbm_init_3d(p["lattice"], p["nx"], p["ny"], p["nz"], p["tau"], p["reg_order"], p["flags"], fa, fb,
+                      FakePtr(0x3000), FakePtr(0x4000), FakePtr(0x5000), uz)
+    assert e.value.code == code
+    assert b.lbm_last_error()
+
+
+def test_3d_calls_reject_null_context():
+    with pytest.raises(b.LbmError):
+        b.lbm_moments_3d(None)
