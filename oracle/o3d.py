@@ -1,5 +1,5 @@
 """3D part of the CPU reference (Table II lattices D3Q19, D3Q27, D3V39,
-isothermal): ctypes access to ``rr_oracle3d.c``.
+D3Q103, isothermal): ctypes access to ``rr_oracle3d.c``.
 
 TEST INFRASTRUCTURE ONLY, like the rest of this package.
 """
@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rr_oracle3d.c")
 _LIB = os.path.join(_HERE, "liboracle3d.so")
 
-LATTICES = {"D3Q19": 0, "D3Q27": 1, "D3V39": 2}
+LATTICES = {"D3Q19": 0, "D3Q27": 1, "D3V39": 2, "D3Q103": 3}
 RR, PR, BGK = 0, 1, 2
 
 
@@ -78,8 +78,8 @@ def lattice(name: str) -> Lattice3:
     lid = LATTICES[name]
     Q, nmax = ctypes.c_int(), ctypes.c_int()
     cs2 = ctypes.c_double()
-    cx, cy, cz = (np.zeros(39, dtype=np.int32) for _ in range(3))
-    w = np.zeros(39)
+    cx, cy, cz = (np.zeros(103, dtype=np.int32) for _ in range(3))
+    w = np.zeros(103)
     ip = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
     _check(lib().o3_lattice(lid, ctypes.byref(Q), ctypes.byref(nmax), ctypes.byref(cs2), ip(cx), ip(cy), ip(cz),
                             _p(w)), "lattice")

@@ -1,7 +1,7 @@
 /*
  * Plain FP64 reference of the recursive-regularized LBM step on the 3D
  * lattices of Table II (E^19_{3,5} "D3Q19", E^27_{3,5} "D3Q27",
- * E^39_{3,7} "D3V39"), isothermal.
+ * E^39_{3,7} "D3V39", E^103_{3,9} "D3Q103"), isothermal.
  *
  * TEST INFRASTRUCTURE ONLY: the tests may load it; the product library never
  * does.  It shares no code, header, table or constant with the HIP library.
@@ -28,7 +28,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define O3_MAXQ 39
+#define O3_MAXQ 103
 #define O3_MAXN 6
 #define O3_NT 1093 /* sum_{n <= 6} 3^n */
 
@@ -100,6 +100,8 @@ static int in_basis3(int id, const int e[3])
         return e[0] <= 2 && e[1] <= 2 && e[2] <= 2;
     case 2: /* D3V39: every tensor of rank <= 3 */
         return n <= 3;
+    case 3: /* D3Q103: every tensor of rank <= 4 */
+        return n <= 4;
     }
     return 0;
 }
@@ -120,12 +122,22 @@ static int build3(int id, o3_lattice_t* L)
                                       { 1, 1, 1, 1.0 / 216.0 } };
     static const o3_group_t g39[] = { { 0, 0, 0, 1.0 / 12.0 }, { 1, 0, 0, 1.0 / 12.0 }, { 1, 1, 1, 1.0 / 27.0 },
                                       { 2, 0, 0, 2.0 / 135.0 }, { 2, 2, 0, 1.0 / 432.0 }, { 3, 0, 0, 1.0 / 1620.0 } };
+    /* D3Q103: weights as printed in Table II (21 digits), c_s = 1 / 1.19697977039307435897239 */
+    static const o3_group_t g103[] = {
+        { 0, 0, 0, 0.032633351764471159466 }, { 1, 0, 0, 0.097656833590334574221 },
+        { 1, 1, 1, 0.028097750290257335627 }, { 2, 0, 0, 0.001045259560430061466 },
+        { 2, 1, 0, 0.005705329016894815990 }, { 2, 2, 0, 0.000611939269829747839 },
+        { 2, 2, 2, 0.000155964159374283722 }, { 3, 0, 0, 0.000284443251800055207 },
+        { 3, 1, 1, 0.000130698375985191585 }, { 3, 3, 3, 0.000001223194501323058 }
+    };
+    const double inv_cs103 = 1.19697977039307435897239;
     const o3_group_t* g;
     int ng;
     switch (id) {
     case 0: g = g19; ng = 3; L->cs2 = 1.0 / 3.0; L->nmax = 3; break;
     case 1: g = g27; ng = 4; L->cs2 = 1.0 / 3.0; L->nmax = 6; break;
     case 2: g = g39; ng = 6; L->cs2 = 2.0 / 3.0; L->nmax = 3; break;
+    case 3: g = g103; ng = 10; L->cs2 = 1.0 / (inv_cs103 * inv_cs103); L->nmax = 4; break;
     default: return -1;
     }
     L->id = id;
