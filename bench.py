@@ -70,7 +70,8 @@ def read_traffic(name: str):
 # Turning rocprofv3 output into the summaries under profiles/ (runs on any
 # host, after the profiled runs on the GPU).
 
-PROFILE_RUN = "python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline --no-sweep --no-batch --no-studies --closure none"
+PROFILE_RUN = ("python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline --no-sweep --no-batch --no-3d --no-studies "
+               "--closure none")
 
 
 def _pmc_per_kernel(csv_dir: str, counter: str):
@@ -156,7 +157,7 @@ def summarize_trace(args) -> str:
     out = [f"# rocprofv3 kernel trace: {args.lattice} {args.storage.upper()} {args.n}x{args.n} shear layer (pull stream-collide)",
            "", "Command (repo root on an MI355X):", "",
            f"    rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o run -- python3 bench.py --steps 50 --warmup 5 "
-           f"--no-cpu-baseline --no-sweep --no-batch --no-studies --closure none --lattice {args.lattice} --n {args.n}{flag}",
+           f"--no-cpu-baseline --no-sweep --no-batch --no-3d --no-studies --closure none --lattice {args.lattice} --n {args.n}{flag}",
            "", f"Summary: `python3 bench.py --lattice {args.lattice} --n {args.n}{flag} --summarize-trace <run_results.db> <bench output>`",
            "", "From the `top_kernels` view of the run's database (durations in microseconds):", "",
            "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
@@ -183,6 +184,37 @@ def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0):
     sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, theta=theta, noise=noise, noise_amp=1e-8,
                        flags=flags)
     return sim, dict(q=q, tau=tau, u0=u0, rho=rho, ux=ux, uy=uy, noise=noise)
+
+
+def make_sim3(b, wl, lattice, n, re=1e5, flags=0, seed=0):
+    """The shear layer extruded along z (with a z perturbation) on an n^3
+    periodic box, FP64 populations."""
+    q, reach, n_eq, cs2 = b.lbm_lattice_info(lattice)
+    u0, tau = wl.shear_layer_params(cs2, n, re)
+    rho, ux, uy, uz = wl.shear_layer_fields_3d(n, n, n, u0)
+    sim = b.Simulation3D(lattice, n, n, n, tau, rho, ux, uy, uz, flags=flags)
+    return sim, dict(q=q, tau=tau, u0=u0)
+
+
+LATTICES_3D = [("D3Q19", "RR"), ("D3Q19", "BGK"), ("D3Q27", "RR"), ("D3V39", "RR"), ("D3Q103", "RR")]
+
+
+def suite_3d(torch, b, wl, n=128, steps=30, warmup=3, only=None):
+    rows = []
+    for lat, coll in LATTICES_3D:
+        if only is not None and (lat, coll) != only:
+            continue
+        flags = b.LBM_COLL_BGK if coll == "BGK" else 0
+        sim, meta = make_sim3(b, wl, lat, n, flags=flags)
+        wall, kms = time_steps(torch, sim, steps, warmup)
+        bad = int(sim.moments()["sums"][7])
+        sim.close()
+        nodes = n ** 3
+        gbs = bytes_per_node(meta["q"], "fp64") * nodes / (kms * 1e-3) / 1e9
+        rows.append({"lattice": lat, "collision": coll, "n": n, "order": b.lbm_lattice_info(lat)[2] if coll == "RR"
+                     else None, "MLUPS": round(nodes * steps / wall / 1e6, 1), "kernel_ms_avg": round(kms, 4),
+                     "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": bad})
+    return rows
 
 
 def time_steps(torch, sim, steps, warmup):
@@ -320,6 +352,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D lattice lines (128^3)")
+    ap.add_argument("--only-3d", metavar="LATTICE:COLL",
+                    help="time one 3D case (e.g. D3Q19:RR) for --steps and print its line alone")
     ap.add_argument("--no-studies", action="store_true", help="skip the precision, Sod and stability studies")
     ap.add_argument("--closure", choices=["full", "small", "none"], default="full",
                     help="learned-closure study: D2V37 256^2 coarse / 1024^2 fine (full) or 64^2 / 256^2")
@@ -357,6 +392,12 @@ def main():
 
     if args.copy_only:
         print(json.dumps({"copy_GBs": round(copy_bandwidth(torch), 1)}), flush=True)
+        return
+
+    if args.only_3d:
+        lat, coll = args.only_3d.split(":")
+        print(json.dumps({"lattices_3d": suite_3d(torch, b, wl, steps=args.steps, warmup=args.warmup,
+                                                  only=(lat, coll))}), flush=True)
         return
 
     sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage)
@@ -417,6 +458,8 @@ def main():
                           "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
         out["per_lattice"] = sweep
         out["copy_GBs"] = round(copy_bandwidth(torch), 1)
+    if not args.no_3d:
+        out["lattices_3d"] = suite_3d(torch, b, wl)
     if not args.no_batch:
         out["batched"] = batched_suite(torch, b, wl)
     if not args.no_studies:

@@ -60,6 +60,7 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_D3Q19 3 /* E^19_{3,5}, c_s^2 = 1/3, ranks <= 2 and the six xxy-type rank-3 tensors */
 #define LBM_D3Q27 4 /* E^27_{3,5}, c_s^2 = 1/3, the 27 products with each exponent <= 2 */
 #define LBM_D3V39 5 /* E^39_{3,7}, c_s^2 = 2/3, all Hermite tensors of rank <= 3 */
+#define LBM_D3Q103 6 /* E^103_{3,9}, c_s = 1/1.19697977..., all Hermite tensors of rank <= 4 */
 
 /* Flags for lbm_init (bitwise OR). */
 #define LBM_THERMAL 0x1u        /* thermal/compressible form; D2V37 only          */
@@ -170,7 +171,7 @@ const char* lbm_last_error(void);
 /* ---- 3D lattices (Table II) ---------------------------------------------
  * Isothermal recursive regularization (the 3D forms of the recursion in
  * App. C, Eq. MalaspinasRecursiveRelation at theta = 1), projection-based
- * regularization or BGK on D3Q19, D3Q27 and D3V39, FP64 populations.  Grids
+ * regularization or BGK on D3Q19, D3Q27, D3V39 and D3Q103, FP64 populations.  Grids
  * are periodic nx by ny by nz; fields are [z][y][x] (nx*ny*nz doubles) and
  * populations exchanged with the caller are [i][z][y][x].  The layout is the
  * 2D one over the ny*nz rows r = z*ny + y.  A 3D context works with
@@ -189,10 +190,10 @@ int64_t lbm_buffer_elems_3d(int lattice, int nx, int ny, int nz, uint32_t flags)
  * (rho, u) over the lattice's basis (LBM_EQ_INIT_ORDER2: ranks <= 2) plus
  * noise_amp * w_i * noise[i][z][y][x], collided once (the kept state is
  * post-collision, as in 2D).
- *   lattice    LBM_D3Q19, LBM_D3Q27 or LBM_D3V39.
+ *   lattice    LBM_D3Q19, LBM_D3Q27, LBM_D3V39 or LBM_D3Q103.
  *   nx, ny, nz each >= the lattice reach; lbm_buffer_elems_3d() < 2^31.
  *   tau        discrete relaxation time (> 1/2), nu = c_s^2 (tau - 1/2).
- *   reg_order  2 <= N <= n_eq (3, 6, 3); ignored with LBM_COLL_BGK.
+ *   reg_order  2 <= N <= n_eq (3, 6, 3, 4); ignored with LBM_COLL_BGK.
  *   flags      LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2 only.
  *   f_a, f_b   two distinct device buffers of lbm_buffer_elems_3d() doubles,
  *              owned by the caller for the context's lifetime.

@@ -15,9 +15,9 @@ import numpy as np
 LIB_PATH = os.environ.get("RRLBM_LIB") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "librrlbm.so")
 
 LBM_D2Q9, LBM_D2V17, LBM_D2V37 = 0, 1, 2
-LBM_D3Q19, LBM_D3Q27, LBM_D3V39 = 3, 4, 5
+LBM_D3Q19, LBM_D3Q27, LBM_D3V39, LBM_D3Q103 = 3, 4, 5, 6
 LATTICES = {"D2Q9": LBM_D2Q9, "D2V17": LBM_D2V17, "D2V37": LBM_D2V37,
-            "D3Q19": LBM_D3Q19, "D3Q27": LBM_D3Q27, "D3V39": LBM_D3V39}
+            "D3Q19": LBM_D3Q19, "D3Q27": LBM_D3Q27, "D3V39": LBM_D3V39, "D3Q103": LBM_D3Q103}
 LBM_THERMAL = 0x1
 LBM_STORE_FP32 = 0x2
 LBM_STORE_BF16 = 0x4

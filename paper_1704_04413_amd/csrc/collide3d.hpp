@@ -1,5 +1,6 @@
 // Isothermal regularized collision and step kernels on the 3D lattices of
-// Table II (FP64 populations).
+// Table II (FP64 populations).  Basis exponents reach 4 (D3Q103), so the
+// coefficient tables are 5 x 5 x 5 with compile-time holes.
 //
 // Per node: rho, j and Pi from the populations; a0 of every basis term is
 // rho u_x^a u_y^b u_z^c (Eq. HermiteCoeffEq at theta = 1); a1^(2) = Pi -
@@ -40,14 +41,14 @@ enum { C3_RR = 0, C3_PR = 1, C3_BGK = 2, C3_EQ = 3 };
 // sum over the basis of He_a(c_x) He_b(c_y) He_c(c_z) C[a][b][c] for
 // velocity I (the products are compile-time constants; zeros are skipped)
 template <class L, int I>
-__device__ __forceinline__ double hsum3(const double (&C)[4][4][4])
+__device__ __forceinline__ double hsum3(const double (&C)[5][5][5])
 {
     constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
     constexpr double cs2 = L::cs2;
     double s = 0.0;
-    static_for<4>([&](auto A) {
-        static_for<4>([&](auto B) {
-            static_for<4>([&](auto Cc) {
+    static_for<5>([&](auto A) {
+        static_for<5>([&](auto B) {
+            static_for<5>([&](auto Cc) {
                 constexpr int a = int(A), b = int(B), c = int(Cc);
                 if constexpr (L::basis(a, b, c)) {
                     constexpr double h = he(a, double(cx), cs2) * he(b, double(cy), cs2) * he(c, double(cz), cs2);
@@ -102,14 +103,14 @@ __device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int
             ayz = pyz - r * uy * uz;
         }
     }
-    const double px[4] = { 1.0, ux, ux * ux, ux * ux * ux };
-    const double py[4] = { 1.0, uy, uy * uy, uy * uy * uy };
-    const double pz[4] = { 1.0, uz, uz * uz, uz * uz * uz };
+    const double px[5] = { 1.0, ux, ux * ux, ux * ux * ux, (ux * ux) * (ux * ux) };
+    const double py[5] = { 1.0, uy, uy * uy, uy * uy * uy, (uy * uy) * (uy * uy) };
+    const double pz[5] = { 1.0, uz, uz * uz, uz * uz * uz, (uz * uz) * (uz * uz) };
     // C[a][b][c] = (a0 + k_n a1) / (a! b! c! c_s^2n) on the basis
-    double C[4][4][4];
-    static_for<4>([&](auto A) {
-        static_for<4>([&](auto B) {
-            static_for<4>([&](auto Cc) {
+    double C[5][5][5];
+    static_for<5>([&](auto A) {
+        static_for<5>([&](auto B) {
+            static_for<5>([&](auto Cc) {
                 constexpr int a = int(A), b = int(B), c = int(Cc), n = a + b + c;
                 if constexpr (L::basis(a, b, c)) {
                     double val = r * px[a] * py[b] * pz[c];
@@ -136,9 +137,9 @@ __device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int
         // f^neq = f - f^eq, then a1 of every kept tensor of rank 2..order by
         // projection onto it
         static_for<L::Q>([&](auto I) { v[I] -= L::v.w[I] * hsum3<L, int(I)>(C); });
-        static_for<4>([&](auto A) {
-            static_for<4>([&](auto B) {
-                static_for<4>([&](auto Cc) {
+        static_for<5>([&](auto A) {
+            static_for<5>([&](auto B) {
+                static_for<5>([&](auto Cc) {
                     constexpr int a = int(A), b = int(B), c = int(Cc), n = a + b + c;
                     if constexpr (L::basis(a, b, c) && n >= 2) {
                         double p = 0.0;

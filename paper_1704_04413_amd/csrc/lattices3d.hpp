@@ -1,5 +1,5 @@
 // Compile-time 3D lattices of Table II: E^19_{3,5} "D3Q19", E^27_{3,5}
-// "D3Q27", E^39_{3,7} "D3V39".  Velocities in canonical order: ascending
+// "D3Q27", E^39_{3,7} "D3V39", E^103_{3,9} "D3Q103".  Velocities in canonical order: ascending
 // c_z, then c_y, then c_x; the population planes follow it.
 #pragma once
 
@@ -14,10 +14,10 @@ struct Group3 {
 
 struct VelTable3 {
     int q = 0;
-    int cx[39] = {};
-    int cy[39] = {};
-    int cz[39] = {};
-    double w[39] = {};
+    int cx[103] = {};
+    int cy[103] = {};
+    int cz[103] = {};
+    double w[103] = {};
 };
 
 template <int NG>
@@ -84,7 +84,25 @@ struct D3V39 {
     static constexpr bool basis(int a, int b, int c) { return a + b + c <= 3; }
 };
 
-static_assert(D3Q19::v.q == 19 && D3Q27::v.q == 27 && D3V39::v.q == 39, "velocity count");
+// D3Q103: the 21-digit weights of Table II on (0,0,0), (1,0,0), (1,1,1),
+// (2,0,0), (2,1,0), (2,2,0), (2,2,2), (3,0,0), (3,1,1), (3,3,3); c_s =
+// 1 / 1.19697977039307435897239.  Basis: every tensor of rank <= 4.
+struct D3Q103 {
+    static constexpr int id = 6, Q = 103, R = 3, NEQ = 4;
+    static constexpr double inv_cs = 1.19697977039307435897239;
+    static constexpr double cs2 = 1.0 / (inv_cs * inv_cs);
+    static constexpr Group3 groups[10] = {
+        { 0, 0, 0, 0.032633351764471159466 }, { 1, 0, 0, 0.097656833590334574221 },
+        { 1, 1, 1, 0.028097750290257335627 }, { 2, 0, 0, 0.001045259560430061466 },
+        { 2, 1, 0, 0.005705329016894815990 }, { 2, 2, 0, 0.000611939269829747839 },
+        { 2, 2, 2, 0.000155964159374283722 }, { 3, 0, 0, 0.000284443251800055207 },
+        { 3, 1, 1, 0.000130698375985191585 }, { 3, 3, 3, 0.000001223194501323058 }
+    };
+    static constexpr VelTable3 v = expand3(groups);
+    static constexpr bool basis(int a, int b, int c) { return a + b + c <= 4; }
+};
+
+static_assert(D3Q19::v.q == 19 && D3Q27::v.q == 27 && D3V39::v.q == 39 && D3Q103::v.q == 103, "velocity count");
 
 // 1 / (a! b! c! c_s^(2(a+b+c))): the normalisation of each 3D basis term.
 template <class L>

@@ -511,7 +511,10 @@ LatInfo info_of()
     return { L::Q, L::R, L::NEQ, L::cs2 };
 }
 
-bool is_3d(int lattice) { return lattice == LBM_D3Q19 || lattice == LBM_D3Q27 || lattice == LBM_D3V39; }
+bool is_3d(int lattice)
+{
+    return lattice == LBM_D3Q19 || lattice == LBM_D3Q27 || lattice == LBM_D3V39 || lattice == LBM_D3Q103;
+}
 
 bool lattice_info(int lattice, LatInfo* out)
 {
@@ -522,6 +525,7 @@ bool lattice_info(int lattice, LatInfo* out)
     case LBM_D3Q19: *out = info_of<D3Q19>(); return true;
     case LBM_D3Q27: *out = info_of<D3Q27>(); return true;
     case LBM_D3V39: *out = info_of<D3V39>(); return true;
+    case LBM_D3Q103: *out = info_of<D3Q103>(); return true;
     }
     return false;
 }
@@ -698,7 +702,8 @@ hipError_t on_lattice3(int lattice, F&& f)
     switch (lattice) {
     case LBM_D3Q19: return f(D3Q19{});
     case LBM_D3Q27: return f(D3Q27{});
-    default: return f(D3V39{});
+    case LBM_D3V39: return f(D3V39{});
+    default: return f(D3Q103{});
     }
 }
 
@@ -1017,6 +1022,7 @@ int lbm_lattice_velocities_3d(int lattice, int* cx, int* cy, int* cz, double* w)
     case LBM_D3Q19: t = &D3Q19::v; break;
     case LBM_D3Q27: t = &D3Q27::v; break;
     case LBM_D3V39: t = &D3V39::v; break;
+    case LBM_D3Q103: t = &D3Q103::v; break;
     default: return fail(LBM_EINVAL, "not a 3D lattice");
     }
     for (int i = 0; i < t->q; ++i) {

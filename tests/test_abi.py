@@ -121,7 +121,7 @@ def test_batch_rejects_invalid_arguments():
 
 # ---------------------------------------------------------------- 3D
 
-@pytest.mark.parametrize("name", ["D3Q19", "D3Q27", "D3V39"])
+@pytest.mark.parametrize("name", ["D3Q19", "D3Q27", "D3V39", "D3Q103"])
 def test_3d_lattice_tables_agree_with_oracle(name):
     from oracle import o3d
 
@@ -140,7 +140,7 @@ def test_3d_lattice_tables_agree_with_oracle(name):
 
 
 def test_3d_buffer_elems():
-    for name in ("D3Q19", "D3Q27", "D3V39"):
+    for name in ("D3Q19", "D3Q27", "D3V39", "D3Q103"):
         q = b.lbm_lattice_info(name)[0]
         for nx, ny, nz in ((1, 1, 1), (3, 5, 7), (64, 64, 64), (128, 128, 128)):
             n = b.lbm_buffer_elems_3d(name, nx, ny, nz)

@@ -1,4 +1,4 @@
-"""GPU parity of the 3D lattices (Table II: D3Q19, D3Q27, D3V39) against the
+"""GPU parity of the 3D lattices (Table II: D3Q19, D3Q27, D3V39, D3Q103) against the
 FP64 3D oracle, through the C-ABI.
 
 As in 2D the library keeps the post-collision state, so after n steps its
@@ -17,7 +17,7 @@ from paper_1704_04413_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-NAMES = ["D3Q19", "D3Q27", "D3V39"]
+NAMES = ["D3Q19", "D3Q27", "D3V39", "D3Q103"]
 
 
 @pytest.fixture(scope="module")
@@ -90,7 +90,7 @@ def test_3d_populations(o3d, b, name, coll):
 
 
 @pytest.mark.parametrize("name,order", [("D3Q19", 2), ("D3Q27", 2), ("D3Q27", 3), ("D3Q27", 4), ("D3Q27", 5),
-                                        ("D3V39", 2)])
+                                        ("D3V39", 2), ("D3Q103", 2), ("D3Q103", 3)])
 def test_3d_lower_orders(o3d, b, name, order):
     dims, steps, tau = (66, 4, 4), 6, 0.6
     say(f"3D RR order {order} {name} {dims}")
