@@ -28,9 +28,18 @@ struct Step3Args {
     Layout lay; // row-tiled over the ny * nz rows, row r = z ny + y
     int ny, nz;
     int bx_blocks;
+    int nblocks;   // blocks in the grid
+    int xcd_remap; // 1: XCD k takes the k-th contiguous eighth of the tiles
     Relax rx;
     int order;
 };
+
+// Register budget of the 3D step kernel, as the minimum number of waves per
+// SIMD the compiler must leave room for.
+#ifndef RRLBM_WAVES_PER_EU_3D
+#define RRLBM_WAVES_PER_EU_3D 1
+#endif
+
 
 // Modes of collide3: C3_RR regularized with the recursion at order `order`,
 // C3_PR regularized by projection (Eq. a1Proj on every kept rank up to
@@ -60,9 +69,121 @@ __device__ __forceinline__ double hsum3(const double (&C)[5][5][5])
     return s;
 }
 
-template <class L, int MODE>
-__device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int order, double eq_rho = 0.0,
-                                         double eq_ux = 0.0, double eq_uy = 0.0, double eq_uz = 0.0)
+// Bit 4p + 2q + r set when parity class (p, q, r) of orbit (ax, ay, az)
+// holds a basis term with a non-zero product.
+template <class L>
+constexpr int classes_used(int ax, int ay, int az)
+{
+    int m = 0;
+    for (int a = 0; a < 5; ++a)
+        for (int b = 0; b < 5; ++b)
+            for (int c = 0; c < 5; ++c)
+                if (L::basis(a, b, c) &&
+                    he(a, double(ax), L::cs2) * he(b, double(ay), L::cs2) * he(c, double(az), L::cs2) != 0.0)
+                    m |= 1 << (4 * (a & 1) + 2 * (b & 1) + (c & 1));
+    return m;
+}
+
+// emit(I, s) with s = sum over the basis of He_a(c_x) He_b(c_y) He_c(c_z)
+// C[a][b][c] for every velocity I, orbit by orbit: the eight parity sums
+// P_pqr = sum over (a, b, c) = (p, q, r) mod 2 of the products at
+// (|c_x|, |c_y|, |c_z|) are formed once per orbit, and each member adds them
+// with the signs of its negative components.
+template <class L, class Emit>
+__device__ __forceinline__ void reconstruct3(const double (&C)[5][5][5], Emit&& emit)
+{
+    constexpr double cs2 = L::cs2;
+    static_for<OrbitsOf<L>::o.n>([&](auto K) {
+        constexpr int ax = OrbitsOf<L>::o.ax[K], ay = OrbitsOf<L>::o.ay[K], az = OrbitsOf<L>::o.az[K];
+        constexpr int used = classes_used<L>(ax, ay, az);
+        double P[2][2][2];
+        static_for<8>([&](auto PC) { P[PC >> 2][(PC >> 1) & 1][PC & 1] = 0.0; });
+        static_for<5>([&](auto A) {
+            static_for<5>([&](auto B) {
+                static_for<5>([&](auto Cc) {
+                    constexpr int a = int(A), b = int(B), c = int(Cc);
+                    if constexpr (L::basis(a, b, c)) {
+                        constexpr double h = he(a, double(ax), cs2) * he(b, double(ay), cs2) * he(c, double(az), cs2);
+                        if constexpr (h != 0.0) P[a & 1][b & 1][c & 1] += h * C[a][b][c];
+                    }
+                });
+            });
+        });
+        static_for<L::Q>([&](auto I) {
+            constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
+            if constexpr ((cx < 0 ? -cx : cx) == ax && (cy < 0 ? -cy : cy) == ay && (cz < 0 ? -cz : cz) == az) {
+                double s = 0.0;
+                static_for<8>([&](auto PC) {
+                    constexpr int p = int(PC) >> 2, q = (int(PC) >> 1) & 1, r = int(PC) & 1;
+                    if constexpr ((used >> int(PC)) & 1) {
+                        constexpr bool neg = ((p && cx < 0) + (q && cy < 0) + (r && cz < 0)) & 1;
+                        if constexpr (neg)
+                            s -= P[p][q][r];
+                        else
+                            s += P[p][q][r];
+                    }
+                });
+                emit(I, s);
+            }
+        });
+    });
+}
+
+// The post-collision value of velocity I goes to out(I, value) as soon as
+// it is formed (v is read, never written, except by the PR pass).
+// A[a][b][c] = sum_i He_a(c_x) He_b(c_y) He_c(c_z) g_i on every basis term
+// of rank >= 2 (the projection of Eq. a1Proj), orbit by orbit: the signed
+// sums G_pqr = sum over the orbit of s_x^p s_y^q s_z^r g_i are formed once
+// and each term takes the one of its parity class.
+template <class L>
+__device__ __forceinline__ void project3(const double (&g)[L::Q], double (&A)[5][5][5])
+{
+    constexpr double cs2 = L::cs2;
+    static_for<5>([&](auto Aa) {
+        static_for<5>([&](auto B) {
+            static_for<5>([&](auto Cc) {
+                if constexpr (L::basis(int(Aa), int(B), int(Cc))) A[Aa][B][Cc] = 0.0;
+            });
+        });
+    });
+    static_for<OrbitsOf<L>::o.n>([&](auto K) {
+        constexpr int ax = OrbitsOf<L>::o.ax[K], ay = OrbitsOf<L>::o.ay[K], az = OrbitsOf<L>::o.az[K];
+        constexpr int used = classes_used<L>(ax, ay, az);
+        double G[2][2][2];
+        static_for<8>([&](auto PC) { G[PC >> 2][(PC >> 1) & 1][PC & 1] = 0.0; });
+        static_for<L::Q>([&](auto I) {
+            constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
+            if constexpr ((cx < 0 ? -cx : cx) == ax && (cy < 0 ? -cy : cy) == ay && (cz < 0 ? -cz : cz) == az) {
+                static_for<8>([&](auto PC) {
+                    constexpr int p = int(PC) >> 2, q = (int(PC) >> 1) & 1, r = int(PC) & 1;
+                    if constexpr ((used >> int(PC)) & 1) {
+                        constexpr bool neg = ((p && cx < 0) + (q && cy < 0) + (r && cz < 0)) & 1;
+                        if constexpr (neg)
+                            G[p][q][r] -= g[I];
+                        else
+                            G[p][q][r] += g[I];
+                    }
+                });
+            }
+        });
+        static_for<5>([&](auto Aa) {
+            static_for<5>([&](auto B) {
+                static_for<5>([&](auto Cc) {
+                    constexpr int a = int(Aa), b = int(B), c = int(Cc);
+                    if constexpr (L::basis(a, b, c) && a + b + c >= 2) {
+                        constexpr double h = he(a, double(ax), cs2) * he(b, double(ay), cs2) * he(c, double(az), cs2);
+                        if constexpr (h != 0.0) A[a][b][c] += h * G[a & 1][b & 1][c & 1];
+                    }
+                });
+            });
+        });
+    });
+}
+
+template <class L, int MODE, class Out>
+__device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int order, Out&& out,
+                                         double eq_rho = 0.0, double eq_ux = 0.0, double eq_uy = 0.0,
+                                         double eq_uz = 0.0)
 {
     constexpr double cs2 = L::cs2;
     double r, ux, uy, uz, axx = 0, ayy = 0, azz = 0, axy = 0, axz = 0, ayz = 0;
@@ -128,7 +249,8 @@ __device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int
                         const double k = n == 2 ? rx.k2 : n == 3 ? rx.k3 : (n <= order ? rx.k4 : 0.0);
                         val += k * t;
                     }
-                    C[a][b][c] = val * inv_norm3<L>(a, b, c);
+                    constexpr double nrm = inv_norm3<L>(a, b, c);
+                    C[a][b][c] = val * nrm;
                 }
             });
         });
@@ -136,45 +258,56 @@ __device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int
     if constexpr (MODE == C3_PR) {
         // f^neq = f - f^eq, then a1 of every kept tensor of rank 2..order by
         // projection onto it
-        static_for<L::Q>([&](auto I) { v[I] -= L::v.w[I] * hsum3<L, int(I)>(C); });
+        reconstruct3<L>(C, [&](auto I, double s) { v[I] -= L::v.w[I] * s; });
+        double A1[5][5][5];
+        project3<L>(v, A1);
         static_for<5>([&](auto A) {
             static_for<5>([&](auto B) {
                 static_for<5>([&](auto Cc) {
                     constexpr int a = int(A), b = int(B), c = int(Cc), n = a + b + c;
                     if constexpr (L::basis(a, b, c) && n >= 2) {
-                        double p = 0.0;
-                        static_for<L::Q>([&](auto I) {
-                            constexpr double h = he(a, double(L::v.cx[I]), cs2) * he(b, double(L::v.cy[I]), cs2) *
-                                                 he(c, double(L::v.cz[I]), cs2);
-                            if constexpr (h != 0.0) p += h * v[I];
-                        });
                         const double k = n == 2 ? rx.k2 : n == 3 ? rx.k3 : (n <= order ? rx.k4 : 0.0);
-                        C[a][b][c] += k * p * inv_norm3<L>(a, b, c);
+                        constexpr double nrm = inv_norm3<L>(a, b, c);
+                        C[a][b][c] += k * A1[a][b][c] * nrm;
                     }
                 });
             });
         });
     }
-    static_for<L::Q>([&](auto I) {
-        const double s = hsum3<L, int(I)>(C);
+    reconstruct3<L>(C, [&](auto I, double s) {
         constexpr double w = L::v.w[I];
         if constexpr (MODE == C3_BGK)
-            v[I] = rx.k2 * v[I] + rx.inv_tau * (w * s);
+            out(I, rx.k2 * v[I] + rx.inv_tau * (w * s));
         else
-            v[I] = w * s;
+            out(I, w * s);
     });
 }
 
-template <class L, int MODE, bool PULL>
-__global__ __launch_bounds__(BX* BY) void k_stream_collide3(Step3Args a)
+// One thread per node.  A block is 64 x 4 nodes and a wave is one 64-wide
+// row segment (BX equals the wave size), so the row, its y and z, and every
+// source row of the pull are wave-uniform: the base address of each
+// (population, source row) pair is scalar and a lane adds only the byte
+// offset of its wrapped x, a 32-bit value.
+template <class L, int MODE>
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU_3D)))
+void k_stream_collide3(Step3Args a)
 {
+    static_assert(BX == 64, "one wave per row segment");
     constexpr int R = L::R;
     const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
-    const int x = int(blockIdx.x % unsigned(a.bx_blocks)) * BX + int(threadIdx.x);
-    const int row = int(blockIdx.x / unsigned(a.bx_blocks)) * BY + int(threadIdx.y);
-    if (x >= nx || row >= ny * nz) return;
+    int bid = int(blockIdx.x);
+    if (a.xcd_remap) {
+        // the hardware deals blocks to the 8 XCDs round-robin
+        const int q = a.nblocks / 8, r = a.nblocks % 8, xcd = bid % 8, local = bid / 8;
+        bid = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    }
+    const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y)); // uniform within a wave
+    const int row = (bid / a.bx_blocks) * BY + ty;
+    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
+    if (row >= ny * nz || x >= nx) return;
     const int y = row % ny, z = row / ny;
-    int xs[2 * R + 1], ys[2 * R + 1], zs[2 * R + 1];
+    uint32_t xb[2 * R + 1]; // byte offset of the source column, per shift
+    int ys[2 * R + 1], zs[2 * R + 1];
     static_for<2 * R + 1>([&](auto D) {
         constexpr int d = int(D) - R;
         int xx = x - d, yy = y - d, zz = z - d;
@@ -187,21 +320,25 @@ __global__ __launch_bounds__(BX* BY) void k_stream_collide3(Step3Args a)
             yy -= (yy >= ny) ? ny : 0;
             zz -= (zz >= nz) ? nz : 0;
         }
-        xs[D] = xx;
+        xb[D] = uint32_t(xx) * uint32_t(sizeof(double));
         ys[D] = yy;
         zs[D] = zz;
     });
-    const double* fin = static_cast<const double*>(a.fin);
-    double* fout = static_cast<double*>(a.fout);
-    const int here = a.lay.row(row) + x;
+    const char* __restrict__ fin = static_cast<const char*>(a.fin);
+    char* __restrict__ fout = static_cast<char*>(a.fout);
+    const int64_t plane = int64_t(a.lay.te) * int64_t(sizeof(double));
+    const int64_t here_row = int64_t(a.lay.row(row)) * int64_t(sizeof(double));
+    const uint32_t xh = uint32_t(x) * uint32_t(sizeof(double));
     double v[L::Q];
     static_for<L::Q>([&](auto I) {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
-        const int idx = PULL ? a.lay.row(zs[cz + R] * ny + ys[cy + R]) + xs[cx + R] : here;
-        v[I] = fin[idx + int(I) * a.lay.te];
+        const int64_t src_row = int64_t(a.lay.row(zs[cz + R] * ny + ys[cy + R])) * int64_t(sizeof(double));
+        const char* base = fin + src_row + int64_t(I) * plane;
+        v[I] = *reinterpret_cast<const double*>(base + xb[cx + R]);
     });
-    collide3<L, MODE>(v, a.rx, a.order);
-    static_for<L::Q>([&](auto I) { __builtin_nontemporal_store(v[I], fout + here + int(I) * a.lay.te); });
+    collide3<L, MODE>(v, a.rx, a.order, [&](auto I, double val) {
+        __builtin_nontemporal_store(val, reinterpret_cast<double*>(fout + here_row + int64_t(I) * plane + xh));
+    });
 }
 
 struct Init3Args {
@@ -213,23 +350,33 @@ struct Init3Args {
     int eq_order;
 };
 
-// f^(0) over the basis up to rank eq_order plus noise_amp w_i noise_i.
+// f^(0) over the basis up to rank eq_order plus noise_amp w_i noise_i,
+// written for the first pull: value i of node x goes to node x - c_i, so
+// that one step kernel launch gathers f^(0) back at every node and collides
+// it (the kept state is post-collision).
 template <class L>
 __global__ __launch_bounds__(256) void k_init3(Init3Args a)
 {
-    const int64_t n = int64_t(a.lay.nx) * a.ny * a.nz;
+    const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
+    const int64_t n = int64_t(nx) * ny * nz;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const int here = a.lay.row(int(k / a.lay.nx)) + int(k % a.lay.nx);
+    const int x = int(k % nx), row = int(k / nx), y = row % ny, z = row / ny;
     double f[L::Q];
     const Relax none{ 0.0, 0.0, 0.0, 0.0 };
-    collide3<L, C3_EQ>(f, none, a.eq_order, a.rho[k], a.ux[k], a.uy[k], a.uz[k]);
     double* out = static_cast<double*>(a.f);
-    static_for<L::Q>([&](auto I) {
-        double val = f[I];
-        if (a.noise) val += a.noise_amp * L::v.w[I] * a.noise[int64_t(I) * n + k];
-        out[here + int(I) * a.lay.te] = val;
-    });
+    collide3<L, C3_EQ>(
+        f, none, a.eq_order,
+        [&](auto I, double val) {
+            constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
+            if (a.noise) val += a.noise_amp * L::v.w[I] * a.noise[int64_t(I) * n + k];
+            int xd = x - cx, yd = y - cy, zd = z - cz; // |c| <= reach <= each dimension
+            xd += xd < 0 ? nx : (xd >= nx ? -nx : 0);
+            yd += yd < 0 ? ny : (yd >= ny ? -ny : 0);
+            zd += zd < 0 ? nz : (zd >= nz ? -nz : 0);
+            out[a.lay.row(zd * ny + yd) + xd + int(I) * a.lay.te] = val;
+        },
+        a.rho[k], a.ux[k], a.uy[k], a.uz[k]);
 }
 
 // rho, u per node and block sums of [rho, rho ux, rho uy, rho uz,

@@ -104,6 +104,40 @@ struct D3Q103 {
 
 static_assert(D3Q19::v.q == 19 && D3Q27::v.q == 27 && D3V39::v.q == 39 && D3Q103::v.q == 103, "velocity count");
 
+// Sign orbits: the distinct (|c_x|, |c_y|, |c_z|) of a lattice.  Since
+// He_n(-x) = (-1)^n He_n(x), every velocity of one orbit sees the same basis
+// products up to the sign (-1)^(a sx + b sy + c sz) of its negative axes.
+struct Orbits3 {
+    int n = 0;
+    int ax[103] = {};
+    int ay[103] = {};
+    int az[103] = {};
+};
+
+constexpr Orbits3 orbits3(const VelTable3& v)
+{
+    Orbits3 o{};
+    for (int i = 0; i < v.q; ++i) {
+        const int a = v.cx[i] < 0 ? -v.cx[i] : v.cx[i];
+        const int b = v.cy[i] < 0 ? -v.cy[i] : v.cy[i];
+        const int c = v.cz[i] < 0 ? -v.cz[i] : v.cz[i];
+        bool seen = false;
+        for (int k = 0; k < o.n; ++k) seen = seen || (o.ax[k] == a && o.ay[k] == b && o.az[k] == c);
+        if (!seen) {
+            o.ax[o.n] = a;
+            o.ay[o.n] = b;
+            o.az[o.n] = c;
+            ++o.n;
+        }
+    }
+    return o;
+}
+
+template <class L>
+struct OrbitsOf {
+    static constexpr Orbits3 o = orbits3(L::v);
+};
+
 // 1 / (a! b! c! c_s^(2(a+b+c))): the normalisation of each 3D basis term.
 template <class L>
 constexpr double inv_norm3(int a, int b, int c)

@@ -671,28 +671,25 @@ hipError_t launch_step_l(const lbm_ctx* c, const void* fin, void* fout, bool pul
     }
 }
 
-// ---- 3D lattices (FP64 populations)
+// ---- 3D lattices (FP64 populations; the step always pulls)
 template <class L, int MODE>
-hipError_t launch_step3_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
+hipError_t launch_step3_t(const lbm_ctx* c, const void* fin, void* fout)
 {
     const int rows = c->ny * c->nz;
     const int bxn = (c->nx + BX - 1) / BX, byn = (rows + BY - 1) / BY;
-    Step3Args a{ fin, fout, c->lay, c->ny, c->nz, bxn, relax_of(c), c->order };
+    Step3Args a{ fin, fout, c->lay, c->ny, c->nz, bxn, bxn * byn, c->xcd_remap, relax_of(c), c->order };
     const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
-    if (pull)
-        k_stream_collide3<L, MODE, true><<<grid, block, 0, c->stream>>>(a);
-    else
-        k_stream_collide3<L, MODE, false><<<grid, block, 0, c->stream>>>(a);
+    k_stream_collide3<L, MODE><<<grid, block, 0, c->stream>>>(a);
     return hipGetLastError();
 }
 
 template <class L>
-hipError_t launch_step3_l(const lbm_ctx* c, const void* fin, void* fout, bool pull)
+hipError_t launch_step3_l(const lbm_ctx* c, const void* fin, void* fout)
 {
     switch (c->coll) {
-    case COLL_PR: return launch_step3_t<L, C3_PR>(c, fin, fout, pull);
-    case COLL_BGK: return launch_step3_t<L, C3_BGK>(c, fin, fout, pull);
-    default: return launch_step3_t<L, C3_RR>(c, fin, fout, pull);
+    case COLL_PR: return launch_step3_t<L, C3_PR>(c, fin, fout);
+    case COLL_BGK: return launch_step3_t<L, C3_BGK>(c, fin, fout);
+    default: return launch_step3_t<L, C3_RR>(c, fin, fout);
     }
 }
 
@@ -709,8 +706,10 @@ hipError_t on_lattice3(int lattice, F&& f)
 
 hipError_t launch_step(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
-    if (c->dim == 3)
-        return on_lattice3(c->lattice, [&](auto l) { return launch_step3_l<decltype(l)>(c, fin, fout, pull); });
+    if (c->dim == 3) {
+        if (!pull) return hipErrorInvalidValue; // 3D contexts are only ever stepped with a pull
+        return on_lattice3(c->lattice, [&](auto l) { return launch_step3_l<decltype(l)>(c, fin, fout); });
+    }
     if (c->store == ST_MOM) return mom_launch_any(c, 3, fin, fout);
     switch (c->lattice) {
     case LBM_D2Q9: return launch_step_l<D2Q9>(c, fin, fout, pull);
@@ -1082,18 +1081,20 @@ int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, 
     c->coll = (flags & LBM_COLL_PR) ? COLL_PR : (flags & LBM_COLL_BGK) ? COLL_BGK : COLL_RR;
     c->q = li.q;
     c->lay = make_layout(li.q, nx, ny * nz);
+    if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     c->buf[0] = f_a;
     c->buf[1] = f_b;
     c->stream = static_cast<hipStream_t>(stream);
     const int64_t n = int64_t(nx) * ny * nz;
     c->nblk = (n + 255) / 256;
-    Init3Args ia{ f_a, c->lay, ny, nz, rho, ux, uy, uz, noise, noise_amp,
+    // f^(0) goes to f_b shifted by -c_i; one pull launch then collides it into f_a
+    Init3Args ia{ f_b, c->lay, ny, nz, rho, ux, uy, uz, noise, noise_amp,
                   (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq };
     hipError_t he = on_lattice3(lattice, [&](auto l) {
         k_init3<decltype(l)><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
         return hipGetLastError();
     });
-    if (he == hipSuccess) he = launch_step(c, f_a, f_a, false); // collide in place: post-collision state
+    if (he == hipSuccess) he = launch_step(c, f_b, f_a, true); // post-collision state in f_a, cur = 0
     if (he != hipSuccess) {
         delete c;
         return fail(LBM_EDEVICE, std::string("init launch: ") + hipGetErrorString(he));
