@@ -174,6 +174,41 @@ def summarize_trace(args) -> str:
     return path
 
 
+def summarize_trace3d(args) -> str:
+    """Writes profiles/lattices3d_<n>_kernel_trace.md from the rocpd database of
+    a --kernel-trace --stats run of `bench.py --only-3d all` and that run's
+    JSON line (live HIP-event timing of each case)."""
+    import sqlite3
+
+    db, bench_json = args.summarize_trace3d
+    rows = sqlite3.connect(db).execute(
+        "select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    line = [ln for ln in open(bench_json) if ln.startswith("{")][-1]
+    cases = json.loads(line)["lattices_3d"]
+    n = cases[0]["n"]
+    cmd = (f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof3d -o run -- python3 bench.py --only-3d all "
+           f"--steps {args.steps} --warmup {args.warmup} --n3 {n}")
+    out = [f"# rocprofv3 kernel trace: 3D lattices (Table II), {n}^3 extruded shear layer, FP64", "",
+           "Command (repo root on an MI355X):", "", f"    {cmd}", "",
+           f"Summary: `python3 bench.py --summarize-trace3d <run_results.db> <bench output>`", "",
+           "From the `top_kernels` view (durations in microseconds; the step kernel of each lattice and "
+           "collision is one template instance, `k_stream_collide3<L, MODE>` with MODE 0 RR, 2 BGK):", "",
+           "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for name, c, tot, avg, pct in rows:
+        out.append(f"| `{name[:110]}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
+    out += ["", "Live HIP-event timing inside the same run (average step-kernel duration, algorithmic "
+                "bytes 2 Q 8 per node, fraction of the 8 TB/s HBM3E peak):", "",
+            "| lattice | collision | us per step | GB/s | % of peak |", "|---|---|---|---|---|"]
+    for r in cases:
+        out.append(f"| {r['lattice']} | {r['collision']} | {r['kernel_ms_avg'] * 1e3:.1f} | {r['kernel_GBs']:.0f} | "
+                   f"{r['frac_hbm'] * 100:.1f} |")
+    out += ["", f"kernel_source_hash: {kernel_source_hash()}"]
+    path = os.path.join(ROOT, "profiles", f"lattices3d_{n}_kernel_trace.md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    return path
+
+
 def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0):
     q, reach, n_eq, cs2 = b.lbm_lattice_info(lattice)
     u0, tau = wl.shear_layer_params(cs2, n, re)
@@ -354,7 +389,10 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D lattice lines (128^3)")
     ap.add_argument("--only-3d", metavar="LATTICE:COLL",
-                    help="time one 3D case (e.g. D3Q19:RR) for --steps and print its line alone")
+                    help="time one 3D case (e.g. D3Q19:RR, or 'all') for --steps and print its line alone")
+    ap.add_argument("--n3", type=int, default=128, help="edge of the 3D box")
+    ap.add_argument("--summarize-trace3d", nargs=2, metavar=("DB", "BENCH_OUT"),
+                    help="write the 3D kernel-trace summary under profiles/ and exit")
     ap.add_argument("--no-studies", action="store_true", help="skip the precision, Sod and stability studies")
     ap.add_argument("--closure", choices=["full", "small", "none"], default="full",
                     help="learned-closure study: D2V37 256^2 coarse / 1024^2 fine (full) or 64^2 / 256^2")
@@ -371,6 +409,9 @@ def main():
         return
     if args.summarize_trace:
         print(summarize_trace(args))
+        return
+    if args.summarize_trace3d:
+        print(summarize_trace3d(args))
         return
 
     if args.gpus != 1:
@@ -395,9 +436,9 @@ def main():
         return
 
     if args.only_3d:
-        lat, coll = args.only_3d.split(":")
-        print(json.dumps({"lattices_3d": suite_3d(torch, b, wl, steps=args.steps, warmup=args.warmup,
-                                                  only=(lat, coll))}), flush=True)
+        only = None if args.only_3d == "all" else tuple(args.only_3d.split(":"))
+        print(json.dumps({"lattices_3d": suite_3d(torch, b, wl, n=args.n3, steps=args.steps, warmup=args.warmup,
+                                                  only=only)}), flush=True)
         return
 
     sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage)
@@ -459,7 +500,7 @@ def main():
         out["per_lattice"] = sweep
         out["copy_GBs"] = round(copy_bandwidth(torch), 1)
     if not args.no_3d:
-        out["lattices_3d"] = suite_3d(torch, b, wl)
+        out["lattices_3d"] = suite_3d(torch, b, wl, n=args.n3)
     if not args.no_batch:
         out["batched"] = batched_suite(torch, b, wl)
     if not args.no_studies:

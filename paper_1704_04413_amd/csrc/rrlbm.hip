@@ -89,6 +89,7 @@ struct StoreBF16 {
     {
         __builtin_nontemporal_store(round_sr(v, r), p);
     }
+    static __device__ __forceinline__ void store_sr(uint16_t* p, float v, uint32_t r) { *p = round_sr(v, r); }
 };
 
 // Counter-based random bits for stochastic rounding: a function of the node
@@ -117,15 +118,23 @@ struct Dither {
 
 // Writes the Q post-collision values of one node (stochastic rounding where
 // the storage asks for it).
-template <class L, class S, class T>
+template <class L, class S, class T, bool NT = true>
 __device__ __forceinline__ void store_node(typename S::elem* __restrict__ fout, int here, int te, const T (&v)[L::Q],
                                            uint32_t node, uint32_t seq)
 {
+    // NT: non-temporal stores, for state buffers larger than the memory-side
+    // cache; ordinary stores leave the written state there for the next step
     if constexpr (S::dithered) {
         Dither dz(node, seq);
-        static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + here + int(I) * te, v[I], dz.next16()); });
+        if constexpr (NT)
+            static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + here + int(I) * te, v[I], dz.next16()); });
+        else
+            static_for<L::Q>([&](auto I) { S::store_sr(fout + here + int(I) * te, v[I], dz.next16()); });
     } else {
-        static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * te, v[I]); });
+        if constexpr (NT)
+            static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * te, v[I]); });
+        else
+            static_for<L::Q>([&](auto I) { S::store(fout + here + int(I) * te, v[I]); });
     }
 }
 
@@ -168,22 +177,28 @@ struct StepArgs {
     int xcd_remap;  // 1: give each XCD a contiguous band of blocks
     Relax rx;       // relaxation factors of ranks 2..4 and 1/tau
     uint32_t seq;   // index of the state written (0: initial state), keys the BF16 dither
+    int reverse;    // 1: walk the tiles last to first (every other step with ordinary stores)
 };
 
 // The hardware hands consecutive workgroup ids to the 8 XCDs in turn; with
 // the remap, XCD k works on the k-th contiguous eighth of the tiles, so
 // neighbouring tiles share that XCD's L2.
+// With `reverse` the tiles are walked last to first: a step then starts on
+// the tiles the previous step wrote last, which are the ones still in the
+// memory-side cache.
 __device__ __forceinline__ int block_index(const StepArgs& a)
 {
-    const int id = int(blockIdx.x);
-    if (!a.xcd_remap) return id;
-    const int q = a.nblocks / 8, r = a.nblocks % 8;
-    const int xcd = id % 8, local = id / 8;
-    return xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    int id = int(blockIdx.x);
+    if (a.xcd_remap) {
+        const int q = a.nblocks / 8, r = a.nblocks % 8;
+        const int xcd = id % 8, local = id / 8;
+        id = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    }
+    return a.reverse ? a.nblocks - 1 - id : id;
 }
 
 // One node: gather (pull, periodic, or local when !PULL), collide, store.
-template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, bool NT = true>
 __device__ __forceinline__ void node_update(const typename S::elem* __restrict__ fin,
                                             typename S::elem* __restrict__ fout, const Layout& lay, int x,
                                             int y, const Relax& rx, uint32_t seq)
@@ -218,10 +233,10 @@ __device__ __forceinline__ void node_update(const typename S::elem* __restrict__
 
     collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, rx);
 
-    store_node<L, S>(fout, here, lay.te, v, uint32_t(y) * uint32_t(nx) + uint32_t(x), seq);
+    store_node<L, S, T, NT>(fout, here, lay.te, v, uint32_t(y) * uint32_t(nx) + uint32_t(x), seq);
 }
 
-template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL>
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, bool NT>
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU)))
 void k_stream_collide(StepArgs a)
 {
@@ -229,8 +244,9 @@ void k_stream_collide(StepArgs a)
     const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
     const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
     if (x >= a.lay.nx || y >= a.lay.ny) return;
-    node_update<L, S, COLL, THERMAL, A13P, PULL>(static_cast<const typename S::elem*>(a.fin),
-                                                 static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx, a.seq);
+    node_update<L, S, COLL, THERMAL, A13P, PULL, NT>(static_cast<const typename S::elem*>(a.fin),
+                                                     static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx,
+                                                     a.seq);
 }
 
 // ---------------------------------------------------------- batch kernel
@@ -543,6 +559,7 @@ struct lbm_ctx {
     int q = 0;
     Layout lay{};
     int xcd_remap = 1;
+    int nt = 1; // non-temporal stores in the 2D step (set from the buffer size at init; 3D always)
     void* buf[2] = { nullptr, nullptr };
     int cur = 0;
     int64_t steps = 0;
@@ -560,6 +577,17 @@ struct lbm_ctx {
 };
 
 namespace {
+
+// Ordinary stores while one state buffer is at most half the 256 MiB
+// memory-side cache (the next step then reads much of it from there),
+// non-temporal stores above (measured: D2Q9 FP64 and D2V37 BF16 at 1024^2,
+// 75-78 MB per buffer, gain 12-15 points of HBM peak; D2V17 FP64 and D2V37
+// FP32 at 142-155 MB are level or lose).  RRLBM_NT_STORES=0/1 forces either.
+int choose_nt(int64_t buffer_bytes)
+{
+    if (const char* e = std::getenv("RRLBM_NT_STORES")) return std::atoi(e) != 0;
+    return buffer_bytes > (int64_t(128) << 20) ? 1 : 0;
+}
 
 Relax relax_of(const lbm_ctx* c)
 {
@@ -624,7 +652,8 @@ template <class L, class S, int COLL, bool TH, bool A13P>
 hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
     const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
-    StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, relax_of(c), pull ? uint32_t(c->steps + 1) : 0u };
+    StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, relax_of(c), pull ? uint32_t(c->steps + 1) : 0u,
+                (!c->nt && pull && (c->steps & 1)) ? 1 : 0 };
     dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if constexpr (L::id == LBM_D2V37 && COLL == COLL_RR && !TH) {
         if (pull && c->closure) {
@@ -633,10 +662,12 @@ hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pul
             return hipGetLastError();
         }
     }
-    if (pull)
-        k_stream_collide<L, S, COLL, TH, A13P, true><<<grid, block, 0, c->stream>>>(a);
+    if (!pull)
+        k_stream_collide<L, S, COLL, TH, A13P, false, true><<<grid, block, 0, c->stream>>>(a);
+    else if (c->nt)
+        k_stream_collide<L, S, COLL, TH, A13P, true, true><<<grid, block, 0, c->stream>>>(a);
     else
-        k_stream_collide<L, S, COLL, TH, A13P, false><<<grid, block, 0, c->stream>>>(a);
+        k_stream_collide<L, S, COLL, TH, A13P, true, false><<<grid, block, 0, c->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -888,6 +919,10 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     c->a13p = (flags & LBM_A13_PROJECTED) != 0;
     c->q = li.q;
     c->lay = make_layout(li.q, nx, ny);
+    {
+        const int64_t esz = c->store == ST_F32 ? 4 : c->store == ST_BF16 ? 2 : 8;
+        c->nt = choose_nt(esz * (c->store == ST_MOM ? int64_t(MOM_K) * nx * ny : layout_elems(li.q, nx, ny)));
+    }
     // tuning knob: RRLBM_XCD_REMAP=0 keeps the hardware's round-robin block order
     if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     c->buf[0] = f_a;
