@@ -39,6 +39,7 @@ struct StoreF64 {
     static constexpr bool conserve_in_double = false;
     static constexpr bool dithered = false;
     static __device__ __forceinline__ double load(const double* p) { return *p; }
+    static __device__ __forceinline__ double load_nt(const double* p) { return __builtin_nontemporal_load(p); }
     static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
     static __device__ __forceinline__ void store_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
 };
@@ -50,6 +51,7 @@ struct StoreF32 {
     static constexpr bool conserve_in_double = true;
     static constexpr bool dithered = false;
     static __device__ __forceinline__ float load(const float* p) { return *p; }
+    static __device__ __forceinline__ float load_nt(const float* p) { return __builtin_nontemporal_load(p); }
     static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
     static __device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
@@ -68,6 +70,10 @@ struct StoreBF16 {
     static __device__ __forceinline__ float load(const uint16_t* p)
     {
         return __uint_as_float(uint32_t(*p) << 16);
+    }
+    static __device__ __forceinline__ float load_nt(const uint16_t* p)
+    {
+        return __uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16);
     }
     static __device__ __forceinline__ uint16_t round(float v)
     {
@@ -198,7 +204,16 @@ __device__ __forceinline__ int block_index(const StepArgs& a)
 }
 
 // One node: gather (pull, periodic, or local when !PULL), collide, store.
-template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, bool NT = true>
+// Cache policy of the 2D step, from the size of one state buffer against the
+// 256 MiB memory-side cache: POL_STREAM ordinary loads, non-temporal stores
+// (large buffers); POL_CACHE ordinary loads and stores, tile order reversed
+// every other step (small buffers: the state stays in the cache);
+// POL_KEEP non-temporal loads and ordinary stores (buffers about the cache's
+// size: the reads no longer evict what the step writes, which the next step
+// reads).
+enum Policy { POL_STREAM = 0, POL_CACHE = 1, POL_KEEP = 2 };
+
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, bool NT = true, bool NTLOAD = false>
 __device__ __forceinline__ void node_update(const typename S::elem* __restrict__ fin,
                                             typename S::elem* __restrict__ fout, const Layout& lay, int x,
                                             int y, const Relax& rx, uint32_t seq)
@@ -228,7 +243,10 @@ __device__ __forceinline__ void node_update(const typename S::elem* __restrict__
     static_for<L::Q>([&](auto I) {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
         const int idx = (PULL ? ys[cy + R] + xs[cx + R] : here) + int(I) * lay.te;
-        v[I] = S::load(fin + idx);
+        if constexpr (NTLOAD)
+            v[I] = S::load_nt(fin + idx);
+        else
+            v[I] = S::load(fin + idx);
     });
 
     collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, rx);
@@ -236,7 +254,7 @@ __device__ __forceinline__ void node_update(const typename S::elem* __restrict__
     store_node<L, S, T, NT>(fout, here, lay.te, v, uint32_t(y) * uint32_t(nx) + uint32_t(x), seq);
 }
 
-template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, bool NT>
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, int POL>
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU)))
 void k_stream_collide(StepArgs a)
 {
@@ -244,9 +262,9 @@ void k_stream_collide(StepArgs a)
     const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
     const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
     if (x >= a.lay.nx || y >= a.lay.ny) return;
-    node_update<L, S, COLL, THERMAL, A13P, PULL, NT>(static_cast<const typename S::elem*>(a.fin),
-                                                     static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx,
-                                                     a.seq);
+    node_update<L, S, COLL, THERMAL, A13P, PULL, POL == POL_STREAM, POL == POL_KEEP>(
+        static_cast<const typename S::elem*>(a.fin), static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx,
+        a.seq);
 }
 
 // ---------------------------------------------------------- batch kernel
@@ -559,7 +577,7 @@ struct lbm_ctx {
     int q = 0;
     Layout lay{};
     int xcd_remap = 1;
-    int nt = 1; // non-temporal stores in the 2D step (set from the buffer size at init; 3D always)
+    int pol = POL_STREAM; // cache policy of the 2D step (from the buffer size at init)
     void* buf[2] = { nullptr, nullptr };
     int cur = 0;
     int64_t steps = 0;
@@ -578,15 +596,21 @@ struct lbm_ctx {
 
 namespace {
 
-// Ordinary stores while one state buffer is at most half the 256 MiB
-// memory-side cache (the next step then reads much of it from there),
-// non-temporal stores above (measured: D2Q9 FP64 and D2V37 BF16 at 1024^2,
-// 75-78 MB per buffer, gain 12-15 points of HBM peak; D2V17 FP64 and D2V37
-// FP32 at 142-155 MB are level or lose).  RRLBM_NT_STORES=0/1 forces either.
-int choose_nt(int64_t buffer_bytes)
+// Cache policy from the bytes of one state buffer (see Policy), measured on
+// the step at 768^2, 1024^2 and 1536^2 for every lattice and storage:
+// POL_CACHE wins up to 128 MiB (by up to 20 points of HBM peak), POL_KEEP from
+// 256 to 320 MiB (D2V37 FP64 1024^2, 310 MB: 75.7% against 71.5%), POL_STREAM
+// elsewhere.  RRLBM_CACHE_POLICY=0/1/2 forces one.
+int choose_policy(int64_t buffer_bytes)
 {
-    if (const char* e = std::getenv("RRLBM_NT_STORES")) return std::atoi(e) != 0;
-    return buffer_bytes > (int64_t(128) << 20) ? 1 : 0;
+    if (const char* e = std::getenv("RRLBM_CACHE_POLICY")) {
+        const int p = std::atoi(e);
+        if (p >= POL_STREAM && p <= POL_KEEP) return p;
+    }
+    const int64_t MiB = int64_t(1) << 20;
+    if (buffer_bytes <= 128 * MiB) return POL_CACHE;
+    if (buffer_bytes > 256 * MiB && buffer_bytes <= 320 * MiB) return POL_KEEP;
+    return POL_STREAM;
 }
 
 Relax relax_of(const lbm_ctx* c)
@@ -653,7 +677,7 @@ hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pul
 {
     const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
     StepArgs a{ fin, fout, c->lay, bxn, bxn * byn, c->xcd_remap, relax_of(c), pull ? uint32_t(c->steps + 1) : 0u,
-                (!c->nt && pull && (c->steps & 1)) ? 1 : 0 };
+                (c->pol == POL_CACHE && pull && (c->steps & 1)) ? 1 : 0 };
     dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if constexpr (L::id == LBM_D2V37 && COLL == COLL_RR && !TH) {
         if (pull && c->closure) {
@@ -663,11 +687,13 @@ hipError_t launch_step_t(const lbm_ctx* c, const void* fin, void* fout, bool pul
         }
     }
     if (!pull)
-        k_stream_collide<L, S, COLL, TH, A13P, false, true><<<grid, block, 0, c->stream>>>(a);
-    else if (c->nt)
-        k_stream_collide<L, S, COLL, TH, A13P, true, true><<<grid, block, 0, c->stream>>>(a);
+        k_stream_collide<L, S, COLL, TH, A13P, false, POL_STREAM><<<grid, block, 0, c->stream>>>(a);
+    else if (c->pol == POL_CACHE)
+        k_stream_collide<L, S, COLL, TH, A13P, true, POL_CACHE><<<grid, block, 0, c->stream>>>(a);
+    else if (c->pol == POL_KEEP)
+        k_stream_collide<L, S, COLL, TH, A13P, true, POL_KEEP><<<grid, block, 0, c->stream>>>(a);
     else
-        k_stream_collide<L, S, COLL, TH, A13P, true, false><<<grid, block, 0, c->stream>>>(a);
+        k_stream_collide<L, S, COLL, TH, A13P, true, POL_STREAM><<<grid, block, 0, c->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -921,7 +947,7 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     c->lay = make_layout(li.q, nx, ny);
     {
         const int64_t esz = c->store == ST_F32 ? 4 : c->store == ST_BF16 ? 2 : 8;
-        c->nt = choose_nt(esz * (c->store == ST_MOM ? int64_t(MOM_K) * nx * ny : layout_elems(li.q, nx, ny)));
+        c->pol = choose_policy(esz * (c->store == ST_MOM ? int64_t(MOM_K) * nx * ny : layout_elems(li.q, nx, ny)));
     }
     // tuning knob: RRLBM_XCD_REMAP=0 keeps the hardware's round-robin block order
     if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;

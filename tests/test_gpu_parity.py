@@ -311,23 +311,24 @@ def test_fp64_thermal_per_order_relaxation(orc, b):
 
 @pytest.mark.parametrize("name,flags", [("D2V37", 0), ("D2Q9", 0), ("D2V37", 0x2), ("D2V37", 0x4),
                                         ("D2V37", 0x1)])
-def test_store_kind_and_tile_order_do_not_change_results(orc, b, name, flags, monkeypatch):
-    """Ordinary stores with the tile order reversed every other step and
-    non-temporal stores in the fixed order give bitwise the same states: each
-    node's update is independent of launch order, and the BF16 dither is keyed
-    by node and step only."""
-    say(f"store kind / tile order {name} flags={flags:#x}")
+def test_cache_policy_and_tile_order_do_not_change_results(orc, b, name, flags, monkeypatch):
+    """The three cache policies of the 2D step (ordinary loads with
+    non-temporal stores; ordinary loads and stores with the tile order
+    reversed every other step; non-temporal loads with ordinary stores) give
+    bitwise the same states: each node's update is independent of launch
+    order, and the BF16 dither is keyed by node and step only."""
+    say(f"cache policy / tile order {name} flags={flags:#x}")
     lat = orc.lattice(name)
     u0, tau = wl.shear_layer_params(lat.cs2, 96, 1e4)
     rho, ux, uy = wl.shear_layer_fields(96, 70, u0)
     noise = wl.uniform_noise(5, lat.Q, 70, 96)
     th = np.ones_like(rho) if flags & b.LBM_THERMAL else None
     out = []
-    for nt in ("1", "0"):
-        monkeypatch.setenv("RRLBM_NT_STORES", nt)
+    for pol in ("0", "1", "2"):
+        monkeypatch.setenv("RRLBM_CACHE_POLICY", pol)
         sim = b.Simulation(name, 96, 70, tau, rho, ux, uy, theta=th, noise=noise, noise_amp=1e-8, flags=flags)
         sim.step(7)
         out.append(sim.populations().cpu().numpy())
         sim.close()
     np.testing.assert_array_equal(out[0], out[1])
-
+    np.testing.assert_array_equal(out[0], out[2])
