@@ -32,6 +32,7 @@ struct Step3Args {
     int xcd_remap; // 1: XCD k takes the k-th contiguous eighth of the tiles
     Relax rx;
     int order;
+    int reverse;   // 1: walk the tiles last to first (POL_CACHE, every other step)
 };
 
 // Register budget of the 3D step kernel, as the minimum number of waves per
@@ -40,34 +41,11 @@ struct Step3Args {
 #define RRLBM_WAVES_PER_EU_3D 1
 #endif
 
-
 // Modes of collide3: C3_RR regularized with the recursion at order `order`,
 // C3_PR regularized by projection (Eq. a1Proj on every kept rank up to
 // `order`), C3_BGK single relaxation to the full-basis equilibrium, C3_EQ the
 // equilibrium of (eq_rho, eq_u) truncated to ranks <= `order`.
 enum { C3_RR = 0, C3_PR = 1, C3_BGK = 2, C3_EQ = 3 };
-
-// sum over the basis of He_a(c_x) He_b(c_y) He_c(c_z) C[a][b][c] for
-// velocity I (the products are compile-time constants; zeros are skipped)
-template <class L, int I>
-__device__ __forceinline__ double hsum3(const double (&C)[5][5][5])
-{
-    constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
-    constexpr double cs2 = L::cs2;
-    double s = 0.0;
-    static_for<5>([&](auto A) {
-        static_for<5>([&](auto B) {
-            static_for<5>([&](auto Cc) {
-                constexpr int a = int(A), b = int(B), c = int(Cc);
-                if constexpr (L::basis(a, b, c)) {
-                    constexpr double h = he(a, double(cx), cs2) * he(b, double(cy), cs2) * he(c, double(cz), cs2);
-                    if constexpr (h != 0.0) s += h * C[a][b][c];
-                }
-            });
-        });
-    });
-    return s;
-}
 
 // Bit 4p + 2q + r set when parity class (p, q, r) of orbit (ax, ay, az)
 // holds a basis term with a non-zero product.
@@ -129,8 +107,6 @@ __device__ __forceinline__ void reconstruct3(const double (&C)[5][5][5], Emit&& 
     });
 }
 
-// The post-collision value of velocity I goes to out(I, value) as soon as
-// it is formed (v is read, never written, except by the PR pass).
 // A[a][b][c] = sum_i He_a(c_x) He_b(c_y) He_c(c_z) g_i on every basis term
 // of rank >= 2 (the projection of Eq. a1Proj), orbit by orbit: the signed
 // sums G_pqr = sum over the orbit of s_x^p s_y^q s_z^r g_i are formed once
@@ -180,6 +156,8 @@ __device__ __forceinline__ void project3(const double (&g)[L::Q], double (&A)[5]
     });
 }
 
+// The post-collision value of velocity I goes to out(I, value) as soon as
+// it is formed (v is read, never written, except by the PR pass).
 template <class L, int MODE, class Out>
 __device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int order, Out&& out,
                                          double eq_rho = 0.0, double eq_ux = 0.0, double eq_uy = 0.0,
@@ -288,7 +266,10 @@ __device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int
 // source row of the pull are wave-uniform: the base address of each
 // (population, source row) pair is scalar and a lane adds only the byte
 // offset of its wrapped x, a 32-bit value.
-template <class L, int MODE>
+// POL: cache policy as in the 2D step (POL_STREAM ordinary loads and
+// non-temporal stores, POL_CACHE ordinary loads and stores, POL_KEEP
+// non-temporal loads and ordinary stores).
+template <class L, int MODE, int POL>
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU_3D)))
 void k_stream_collide3(Step3Args a)
 {
@@ -301,6 +282,7 @@ void k_stream_collide3(Step3Args a)
         const int q = a.nblocks / 8, r = a.nblocks % 8, xcd = bid % 8, local = bid / 8;
         bid = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
     }
+    if (a.reverse) bid = a.nblocks - 1 - bid;
     const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y)); // uniform within a wave
     const int row = (bid / a.bx_blocks) * BY + ty;
     const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
@@ -334,10 +316,18 @@ void k_stream_collide3(Step3Args a)
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
         const int64_t src_row = int64_t(a.lay.row(zs[cz + R] * ny + ys[cy + R])) * int64_t(sizeof(double));
         const char* base = fin + src_row + int64_t(I) * plane;
-        v[I] = *reinterpret_cast<const double*>(base + xb[cx + R]);
+        const double* p = reinterpret_cast<const double*>(base + xb[cx + R]);
+        if constexpr (POL == POL_KEEP)
+            v[I] = __builtin_nontemporal_load(p);
+        else
+            v[I] = *p;
     });
     collide3<L, MODE>(v, a.rx, a.order, [&](auto I, double val) {
-        __builtin_nontemporal_store(val, reinterpret_cast<double*>(fout + here_row + int64_t(I) * plane + xh));
+        double* p = reinterpret_cast<double*>(fout + here_row + int64_t(I) * plane + xh);
+        if constexpr (POL == POL_STREAM)
+            __builtin_nontemporal_store(val, p);
+        else
+            *p = val;
     });
 }
 

@@ -577,7 +577,7 @@ struct lbm_ctx {
     int q = 0;
     Layout lay{};
     int xcd_remap = 1;
-    int pol = POL_STREAM; // cache policy of the 2D step (from the buffer size at init)
+    int pol = POL_STREAM; // cache policy of the step (from the buffer size at init; 3D: RR only)
     void* buf[2] = { nullptr, nullptr };
     int cur = 0;
     int64_t steps = 0;
@@ -734,9 +734,22 @@ hipError_t launch_step3_t(const lbm_ctx* c, const void* fin, void* fout)
 {
     const int rows = c->ny * c->nz;
     const int bxn = (c->nx + BX - 1) / BX, byn = (rows + BY - 1) / BY;
-    Step3Args a{ fin, fout, c->lay, c->ny, c->nz, bxn, bxn * byn, c->xcd_remap, relax_of(c), c->order };
+    // the cache policies are instantiated for the RR step only; PR and BGK stream
+    const int pol = MODE == C3_RR ? c->pol : POL_STREAM;
+    Step3Args a{ fin, fout, c->lay, c->ny, c->nz, bxn, bxn * byn, c->xcd_remap, relax_of(c), c->order,
+                 (pol == POL_CACHE && (c->steps & 1)) ? 1 : 0 };
     const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
-    k_stream_collide3<L, MODE><<<grid, block, 0, c->stream>>>(a);
+    if constexpr (MODE == C3_RR) {
+        if (pol == POL_CACHE) {
+            k_stream_collide3<L, MODE, POL_CACHE><<<grid, block, 0, c->stream>>>(a);
+            return hipGetLastError();
+        }
+        if (pol == POL_KEEP) {
+            k_stream_collide3<L, MODE, POL_KEEP><<<grid, block, 0, c->stream>>>(a);
+            return hipGetLastError();
+        }
+    }
+    k_stream_collide3<L, MODE, POL_STREAM><<<grid, block, 0, c->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -1142,6 +1155,7 @@ int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, 
     c->coll = (flags & LBM_COLL_PR) ? COLL_PR : (flags & LBM_COLL_BGK) ? COLL_BGK : COLL_RR;
     c->q = li.q;
     c->lay = make_layout(li.q, nx, ny * nz);
+    c->pol = choose_policy(int64_t(sizeof(double)) * layout_elems(li.q, nx, ny * nz));
     if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     c->buf[0] = f_a;
     c->buf[1] = f_b;
