@@ -40,6 +40,15 @@
  *   of these alone (Eq. GenRegCollision, Eq. MalaspinasRecursiveRelation), so
  *   a step rebuilds each pulled population from its source node's moments.
  *   The sequence of states equals that of LBM_STORE_FP64 up to rounding.
+ *
+ * Environment (read when a context is created; none changes any result)
+ *   RRLBM_CACHE_POLICY=0/1/2  forces the cache policy of the step: 0 ordinary
+ *     loads and non-temporal stores, 1 ordinary loads and stores with the tile
+ *     order reversed every other step, 2 non-temporal loads and ordinary
+ *     stores.  By default the policy follows the size of one state buffer
+ *     (1 up to 128 MiB, 2 from 256 to 320 MiB, 0 otherwise; 3D: RR only).
+ *   RRLBM_XCD_REMAP=0  keeps the hardware's round-robin order of blocks over
+ *     the 8 XCDs instead of giving each XCD a contiguous band of tiles.
  */
 #ifndef RRLBM_H
 #define RRLBM_H
