@@ -12,8 +12,9 @@
 // kernel: the thread of node x gathers f_i(x - c_i) from the source buffer (one
 // fixed offset per plane, so every stored value is read exactly once),
 // collides in registers and writes its Q post-collision values to the
-// destination buffer with non-temporal stores.  The two buffers alternate; the
-// state kept between steps is post-collision.
+// destination buffer, with the load and store kinds of the cache policy that
+// the buffer size selects (Policy).  The two buffers alternate; the state
+// kept between steps is post-collision.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
