@@ -416,7 +416,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU layout is described in DESIGN.md)", file=sys.stderr)
+              "(this benchmark times one GPU's share of the work)", file=sys.stderr)
         sys.exit(2)
 
     import torch
