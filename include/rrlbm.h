@@ -46,7 +46,7 @@
  *     loads and non-temporal stores, 1 ordinary loads and stores with the tile
  *     order reversed every other step, 2 non-temporal loads and ordinary
  *     stores.  By default the policy follows the size of one state buffer
- *     (1 up to 128 MiB, 2 from 256 to 320 MiB, 0 otherwise; 3D: RR only).
+ *     (1 up to 128 MiB, 2 from 256 to 320 MiB, 0 otherwise; 3D: RR and BGK).
  *   RRLBM_XCD_REMAP=0  keeps the hardware's round-robin order of blocks over
  *     the 8 XCDs instead of giving each XCD a contiguous band of tiles.
  */

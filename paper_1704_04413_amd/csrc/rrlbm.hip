@@ -578,7 +578,7 @@ struct lbm_ctx {
     int q = 0;
     Layout lay{};
     int xcd_remap = 1;
-    int pol = POL_STREAM; // cache policy of the step (from the buffer size at init; 3D: RR only)
+    int pol = POL_STREAM; // cache policy of the step (from the buffer size at init; 3D: RR and BGK)
     void* buf[2] = { nullptr, nullptr };
     int cur = 0;
     int64_t steps = 0;
@@ -735,12 +735,12 @@ hipError_t launch_step3_t(const lbm_ctx* c, const void* fin, void* fout)
 {
     const int rows = c->ny * c->nz;
     const int bxn = (c->nx + BX - 1) / BX, byn = (rows + BY - 1) / BY;
-    // the cache policies are instantiated for the RR step only; PR and BGK stream
-    const int pol = MODE == C3_RR ? c->pol : POL_STREAM;
+    // the cache policies are instantiated for the RR and BGK steps; PR streams
+    const int pol = MODE != C3_PR ? c->pol : POL_STREAM;
     Step3Args a{ fin, fout, c->lay, c->ny, c->nz, bxn, bxn * byn, c->xcd_remap, relax_of(c), c->order,
                  (pol == POL_CACHE && (c->steps & 1)) ? 1 : 0 };
     const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
-    if constexpr (MODE == C3_RR) {
+    if constexpr (MODE != C3_PR) {
         if (pol == POL_CACHE) {
             k_stream_collide3<L, MODE, POL_CACHE><<<grid, block, 0, c->stream>>>(a);
             return hipGetLastError();

@@ -206,17 +206,18 @@ def test_3d_shear_wave_decay_full_size(b, name):
     assert nu == pytest.approx(cs2 * (tau - 0.5), rel=0.01)
 
 
-@pytest.mark.parametrize("name", ["D3Q19", "D3V39"])
-def test_3d_cache_policies_give_the_same_states(o3d, b, name, monkeypatch):
-    """The three cache policies of the RR step (streaming; ordinary loads and
-    stores with the tile order reversed every other step; non-temporal loads
-    with ordinary stores) give bitwise the same populations."""
+@pytest.mark.parametrize("name,flags", [("D3Q19", 0), ("D3V39", 0), ("D3Q19", 0x20), ("D3Q27", 0x20)])
+def test_3d_cache_policies_give_the_same_states(o3d, b, name, flags, monkeypatch):
+    """The three cache policies of the RR and BGK steps (streaming; ordinary
+    loads and stores with the tile order reversed every other step;
+    non-temporal loads with ordinary stores) give bitwise the same
+    populations."""
     dims = (66, 6, 5)
-    say(f"3D cache policies {name} {dims}")
+    say(f"3D cache policies {name} flags={flags:#x} {dims}")
     lat, fields, _ = case(o3d, name, *dims, seed=7)
     out = []
     for pol in ("0", "1", "2"):
         monkeypatch.setenv("RRLBM_CACHE_POLICY", pol)
-        out.append(run_gpu(b, name, dims, 0.6, fields, 5)["f"])
+        out.append(run_gpu(b, name, dims, 0.6, fields, 5, flags=flags)["f"])
     np.testing.assert_array_equal(out[0], out[1])
     np.testing.assert_array_equal(out[0], out[2])
