@@ -49,6 +49,9 @@ def lib():
         L.o3_noneq.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp]
         L.o3_collide.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, i64, dp, dp]
         L.o3_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double] + [ctypes.c_int] * 4 + [dp, dp]
+        d = ctypes.c_double
+        L.o3_collide_mrt.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d, d, i64, dp, dp]
+        L.o3_step_mrt.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, d, d, d] + [ctypes.c_int] * 4 + [dp, dp]
         L.o3_moments.argtypes = [ctypes.c_int, i64, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
@@ -120,21 +123,26 @@ def noneq(lat: Lattice3, f_node, coll=RR) -> np.ndarray:
     return a1
 
 
-def collide(lat: Lattice3, f, tau, coll=RR, order=None) -> np.ndarray:
+def collide(lat: Lattice3, f, tau, coll=RR, order=None, tau3=None, tau4=None) -> np.ndarray:
+    """One collision; tau3 (rank 3) and tau4 (ranks >= 4) default to tau."""
     f = np.ascontiguousarray(f, dtype=np.float64)
     out = np.zeros_like(f)
     order = lat.nmax if order is None else order
-    _check(lib().o3_collide(lat.id, coll, order, tau, f.size // lat.Q, _p(f), _p(out)), "collide")
+    t3 = tau if tau3 is None else tau3
+    t4 = tau if tau4 is None else tau4
+    _check(lib().o3_collide_mrt(lat.id, coll, order, tau, t3, t4, f.size // lat.Q, _p(f), _p(out)), "collide")
     return out
 
 
-def step(lat: Lattice3, f, tau, nsteps, coll=RR, order=None) -> np.ndarray:
+def step(lat: Lattice3, f, tau, nsteps, coll=RR, order=None, tau3=None, tau4=None) -> np.ndarray:
     """nsteps of collide + periodic push stream; f has shape (Q, nz, ny, nx)."""
     f = np.array(f, dtype=np.float64, order="C", copy=True)
     _, nz, ny, nx = f.shape
     tmp = np.empty_like(f)
     order = lat.nmax if order is None else order
-    _check(lib().o3_step(lat.id, coll, order, tau, nx, ny, nz, nsteps, _p(f), _p(tmp)), "step")
+    t3 = tau if tau3 is None else tau3
+    t4 = tau if tau4 is None else tau4
+    _check(lib().o3_step_mrt(lat.id, coll, order, tau, t3, t4, nx, ny, nz, nsteps, _p(f), _p(tmp)), "step")
     return f
 
 

@@ -270,7 +270,14 @@ static void noneq3(const o3_lattice_t* L, int coll, const double* f, double rho,
     }
 }
 
-static void collide3(const o3_lattice_t* L, int coll, int order, double tau, const double* f, double* out)
+/* Relaxation times: tau for rank 2 (and BGK), tau3 for rank 3, tau4 for every
+ * rank >= 4 (the Hermite MRT form of Eq. GenRegCollision with one time per
+ * order; tau3 = tau4 = tau is the single-time operator). */
+typedef struct {
+    double tau, tau3, tau4;
+} o3_times_t;
+
+static void collide3(const o3_lattice_t* L, int coll, int order, o3_times_t tt, const double* f, double* out)
 {
     double rho, u[3];
     moments3(L, f, &rho, u);
@@ -278,16 +285,16 @@ static void collide3(const o3_lattice_t* L, int coll, int order, double tau, con
     eq3(L, rho, u, 1.0, a0);
     hsum3(L, a0, L->nmax, feq);
     if (coll == O3_BGK) {
-        for (int i = 0; i < L->Q; ++i) out[i] = f[i] - (f[i] - feq[i]) / tau;
+        for (int i = 0; i < L->Q; ++i) out[i] = f[i] - (f[i] - feq[i]) / tt.tau;
         return;
     }
     double a1[O3_NT], a[O3_NT];
     noneq3(L, coll, f, rho, u, a0, feq, a1);
-    const double k = 1.0 - 1.0 / tau;
+    const double k2 = 1.0 - 1.0 / tt.tau, k3 = 1.0 - 1.0 / tt.tau3, k4 = 1.0 - 1.0 / tt.tau4;
     for (int n = 0; n <= O3_MAXN; ++n)
         for (int b = 0; b < pow3(n); ++b) {
             double v = a0[t3off(n) + b];
-            if (n >= 2 && n <= order) v += k * a1[t3off(n) + b];
+            if (n >= 2 && n <= order) v += (n == 2 ? k2 : n == 3 ? k3 : k4) * a1[t3off(n) + b];
             a[t3off(n) + b] = v;
         }
     hsum3(L, a, L->nmax, out);
@@ -370,29 +377,35 @@ int o3_noneq(int id, int coll, const double* f, double* a1)
     return 0;
 }
 
-int o3_collide(int id, int coll, int order, double tau, int64_t n, const double* f, double* out)
+int o3_collide_mrt(int id, int coll, int order, double tau, double tau3, double tau4, int64_t n, const double* f,
+                    double* out)
 {
     static o3_lattice_t L;
     if (build3(id, &L)) return -1;
     int e = check3(&L, coll, order, tau);
     if (e) return e;
+    if (!(tau3 > 0.5) || !isfinite(tau3) || !(tau4 > 0.5) || !isfinite(tau4)) return -4;
+    const o3_times_t tt = { tau, tau3, tau4 };
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < n; ++k) {
         double fl[O3_MAXQ], fo[O3_MAXQ];
         for (int i = 0; i < L.Q; ++i) fl[i] = f[(int64_t)i * n + k];
-        collide3(&L, coll, order, tau, fl, fo);
+        collide3(&L, coll, order, tt, fl, fo);
         for (int i = 0; i < L.Q; ++i) out[(int64_t)i * n + k] = fo[i];
     }
     return 0;
 }
 
 /* nsteps of collide-then-stream (push) on a periodic nx x ny x nz box. */
-int o3_step(int id, int coll, int order, double tau, int nx, int ny, int nz, int nsteps, double* f, double* tmp)
+int o3_step_mrt(int id, int coll, int order, double tau, double tau3, double tau4, int nx, int ny, int nz, int nsteps,
+                 double* f, double* tmp)
 {
     static o3_lattice_t L;
     if (build3(id, &L)) return -1;
     int e = check3(&L, coll, order, tau);
     if (e) return e;
+    if (!(tau3 > 0.5) || !isfinite(tau3) || !(tau4 > 0.5) || !isfinite(tau4)) return -4;
+    const o3_times_t tt = { tau, tau3, tau4 };
     if (nx < 1 || ny < 1 || nz < 1) return -5;
     const int64_t n = (int64_t)nx * ny * nz;
     for (int s = 0; s < nsteps; ++s) {
@@ -403,7 +416,7 @@ int o3_step(int id, int coll, int order, double tau, int nx, int ny, int nz, int
                     double fl[O3_MAXQ], fo[O3_MAXQ];
                     const int64_t k = ((int64_t)z * ny + y) * nx + x;
                     for (int i = 0; i < L.Q; ++i) fl[i] = f[(int64_t)i * n + k];
-                    collide3(&L, coll, order, tau, fl, fo);
+                    collide3(&L, coll, order, tt, fl, fo);
                     for (int i = 0; i < L.Q; ++i) {
                         const int xd = ((x + L.cx[i]) % nx + nx) % nx;
                         const int yd = ((y + L.cy[i]) % ny + ny) % ny;
@@ -414,6 +427,16 @@ int o3_step(int id, int coll, int order, double tau, int nx, int ny, int nz, int
         memcpy(f, tmp, sizeof(double) * (size_t)(n * L.Q));
     }
     return 0;
+}
+
+int o3_collide(int id, int coll, int order, double tau, int64_t n, const double* f, double* out)
+{
+    return o3_collide_mrt(id, coll, order, tau, tau, tau, n, f, out);
+}
+
+int o3_step(int id, int coll, int order, double tau, int nx, int ny, int nz, int nsteps, double* f, double* tmp)
+{
+    return o3_step_mrt(id, coll, order, tau, tau, tau, nx, ny, nz, nsteps, f, tmp);
 }
 
 int o3_moments(int id, int64_t n, const double* f, double* rho, double* ux, double* uy, double* uz)

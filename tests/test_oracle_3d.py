@@ -232,3 +232,64 @@ def test_shear_wave_decay_3d(lats, name):
     f = o3d.step(lat, f, tau, 300)
     a2 = amp(f)
     assert math.log(a1 / a2) / (300 * k * k) == pytest.approx(nu, rel=0.01)
+
+
+# ---------------------------------------------------------- per-order relaxation
+
+@pytest.mark.parametrize("name", NAMES)
+def test_mrt_with_equal_times_is_the_single_time_operator(lats, name):
+    lat = lats[name]
+    rng = np.random.default_rng(8)
+    f = np.stack([noneq_node(lat, rng) for _ in range(6)], axis=1)
+    for coll in (o3d.RR, o3d.PR):
+        np.testing.assert_array_equal(o3d.collide(lat, f, 0.7, coll, tau3=0.7, tau4=0.7), o3d.collide(lat, f, 0.7, coll))
+
+
+@pytest.mark.parametrize("name", ["D3Q27", "D3V39", "D3Q103"])
+@pytest.mark.parametrize("coll", ["RR", "PR"])
+def test_mrt_relaxes_each_rank_with_its_own_time(lats, name, coll):
+    """On a lattice whose Gram matrix is diagonal on its basis, the projection
+    of f' - f^eq onto a basis tensor of rank n is k_n a1 of that tensor, with
+    k_2 = 1 - 1/tau, k_3 = 1 - 1/tau3 and k_n = 1 - 1/tau4 for n >= 4."""
+    lat = lats[name]
+    cc = {"RR": o3d.RR, "PR": o3d.PR}[coll]
+    tau, tau3, tau4 = 0.8, 0.62, 1.3
+    rng = np.random.default_rng(9)
+    f = noneq_node(lat, rng)
+    fp = o3d.collide(lat, f[:, None], tau, cc, tau3=tau3, tau4=tau4)[:, 0]
+    r, ux, uy, uz = o3d.moments(lat, f[:, None])
+    feq = o3d.equilibrium(lat, r, ux, uy, uz)[:, 0]
+    a1 = o3d.noneq(lat, f, cc)
+    k = {2: 1 - 1 / tau, 3: 1 - 1 / tau3}
+    checked = 0
+    for n in range(2, lat.nmax + 1):
+        H = o3d.hermite(lat, n)
+        mask = o3d.basis(lat, n)
+        kn = k.get(n, 1 - 1 / tau4)
+        off = (3 ** n - 1) // 2
+        for b in np.flatnonzero(mask):
+            got = float(H[:, b] @ (fp - feq))
+            assert got == pytest.approx(kn * a1[off + b], rel=1e-9, abs=1e-15)
+            checked += 1
+    assert checked >= {"D3Q27": 22, "D3V39": 16, "D3Q103": 30}[name] - 4
+
+
+def test_mrt_shear_wave_viscosity_is_set_by_tau_alone(lats):
+    lat = lats["D3V39"]
+    nz, ny, nx, tau = 2, 48, 2, 0.8
+    U = 1e-4 * math.sqrt(lat.cs2)
+    y = (np.arange(ny) + 0.5) / ny
+    ux = np.broadcast_to((U * np.sin(2 * np.pi * y))[None, :, None], (nz, ny, nx)).copy()
+    z = np.zeros((nz, ny, nx))
+    f = o3d.equilibrium(lat, np.ones((nz, ny, nx)), ux, z, z)
+    k = 2 * np.pi / ny
+
+    def amp(ff):
+        _, vx, _, _ = o3d.moments(lat, ff)
+        return 2.0 / ny * float(np.sum(vx[0, :, 0] * np.sin(2 * np.pi * y)))
+
+    f = o3d.step(lat, f, tau, 20, tau3=0.55, tau4=1.4)
+    a1 = amp(f)
+    f = o3d.step(lat, f, tau, 300, tau3=0.55, tau4=1.4)
+    a2 = amp(f)
+    assert math.log(a1 / a2) / (300 * k * k) == pytest.approx(lat.cs2 * (tau - 0.5), rel=0.01)
