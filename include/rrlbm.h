@@ -148,7 +148,8 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
  * (Eq. GenRegCollision with one time per Hermite order, the MRT form of
  * Sec. II.C; rank 2 keeps the tau of lbm_init).  Both default to tau.  In
  * the thermal form tau3 sets the thermal diffusivity c_s^2 theta (tau3 - 1/2),
- * so Pr = (tau - 1/2) / (tau3 - 1/2).  Applies from the next step; ranks
+ * so Pr = (tau - 1/2) / (tau3 - 1/2).  On 3D contexts tau4 relaxes every
+ * rank >= 4 (D3Q27 reaches rank 6).  Applies from the next step; ranks
  * above the regularization order stay equilibrium.  LBM_EINVAL for a NULL
  * context or BGK, LBM_ETAU unless both are finite and > 1/2. */
 int lbm_set_relaxation(lbm_ctx* ctx, double tau3, double tau4);
@@ -184,8 +185,8 @@ const char* lbm_last_error(void);
  * are periodic nx by ny by nz; fields are [z][y][x] (nx*ny*nz doubles) and
  * populations exchanged with the caller are [i][z][y][x].  The layout is the
  * 2D one over the ny*nz rows r = z*ny + y.  A 3D context works with
- * lbm_step, lbm_step_count, lbm_populations and lbm_destroy; lbm_moments,
- * lbm_set_relaxation, batches and the closure reject it. */
+ * lbm_step, lbm_step_count, lbm_set_relaxation, lbm_populations and
+ * lbm_destroy; lbm_moments, batches and the closure reject it. */
 
 /* Velocities (ascending c_z, then c_y, then c_x) and weights of a 3D lattice;
  * host arrays of q entries (any may be NULL).  LBM_EINVAL for a 2D id. */

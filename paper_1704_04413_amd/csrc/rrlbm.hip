@@ -1007,7 +1007,6 @@ int lbm_set_relaxation(lbm_ctx* c, double tau3, double tau4)
 {
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (c->coll == COLL_BGK) return fail(LBM_EINVAL, "BGK has a single relaxation time");
-    if (c->dim == 3) return fail(LBM_EINVAL, "3D contexts have a single relaxation time");
     if (!std::isfinite(tau3) || !(tau3 > 0.5) || !std::isfinite(tau4) || !(tau4 > 0.5))
         return fail(LBM_ETAU, "tau3 and tau4 must be finite and > 1/2");
     c->tau3 = tau3;

@@ -167,8 +167,6 @@ def test_3d_contexts_reject_2d_calls(b):
     with pytest.raises(b.LbmError):
         b.lbm_moments(sim.ctx)
     with pytest.raises(b.LbmError):
-        b.lbm_set_relaxation(sim.ctx, 0.7, 0.7)
-    with pytest.raises(b.LbmError):
         b.lbm_batch_create([sim.ctx])
     sim.step(2)
     assert sim.steps == 2
@@ -221,3 +219,31 @@ def test_3d_cache_policies_give_the_same_states(o3d, b, name, flags, monkeypatch
         out.append(run_gpu(b, name, dims, 0.6, fields, 5, flags=flags)["f"])
     np.testing.assert_array_equal(out[0], out[1])
     np.testing.assert_array_equal(out[0], out[2])
+
+
+@pytest.mark.parametrize("name,coll,order", [("D3Q27", "RR", 6), ("D3Q27", "RR", 4), ("D3V39", "RR", 3),
+                                             ("D3Q103", "RR", 4), ("D3Q27", "PR", 6), ("D3Q19", "RR", 3)])
+def test_3d_per_order_relaxation(o3d, b, name, coll, order):
+    """lbm_set_relaxation on a 3D context: rank 3 relaxes with tau3, every rank
+    >= 4 with tau4 (oracle: o3_step_mrt), from the next step on."""
+    dims, tau, tau3, tau4, steps = (66, 5, 3), 0.8, 0.62, 1.3, 6
+    say(f"3D per-order relaxation {coll} {name} order {order}")
+    lat, fields, f0 = case(o3d, name, *dims, seed=8)
+    ocoll, flags = COLLS[coll]
+    rho, ux, uy, uz, noise = fields
+    sim = b.Simulation3D(name, *dims, tau, rho, ux, uy, uz, noise=noise, noise_amp=1e-6, flags=flags,
+                         reg_order=order)
+    sim.set_relaxation(tau3, tau4)
+    sim.step(steps)
+    got = sim.populations().cpu().numpy()
+    sim.close()
+    # the initial state is collided with the single time (the times are set
+    # after init); every step then streams and collides with the per-order
+    # times: S_n = C'(stream(C'(... stream(S_0)))) = C'(step'(stream(S_0), n - 1))
+    s0 = o3d.collide(lat, f0, tau, ocoll, order)
+    streamed = np.empty_like(s0)
+    for i in range(lat.Q):  # push streaming: f_i(x + c_i) = s0_i(x)
+        streamed[i] = np.roll(s0[i], shift=(int(lat.c[i, 2]), int(lat.c[i, 1]), int(lat.c[i, 0])), axis=(0, 1, 2))
+    want = o3d.collide(lat, o3d.step(lat, streamed, tau, steps - 1, ocoll, order, tau3=tau3, tau4=tau4), tau, ocoll,
+                       order, tau3=tau3, tau4=tau4)
+    check(got, want, 1e-12)
