@@ -172,6 +172,35 @@ int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* theta
  * f_out[i][y][x] (shifted storage is converted back to f = g + w). */
 int lbm_populations(lbm_ctx* ctx, double* f_out);
 
+/* ---- Checkpoints ---------------------------------------------------------
+ * The state of the explicit scheme of Sec. III.A between two steps is the
+ * post-collision population field (or, with LBM_STORE_MOMENTS, the moments it
+ * is built from) together with the step counter, which also keys the BF16
+ * stochastic rounding.  A checkpoint holds both, plus the relaxation times of
+ * lbm_set_relaxation: a 64-byte header (magic "RRLBMCK1", lattice, nx, ny,
+ * nz, flags, step count, tau, tau3, tau4) followed by the current state buffer
+ * exactly as it sits in device memory (storage type, library layout).  So
+ * k steps, lbm_save, lbm_load into a fresh context and n - k more steps give
+ * bit for bit the state of n steps.  Works for 2D and 3D contexts. */
+#define LBM_CHECKPOINT_HEADER_BYTES 64
+
+/* Bytes of a checkpoint of ctx (header + one state buffer); negative on error. */
+int64_t lbm_checkpoint_bytes(const lbm_ctx* ctx);
+
+/* Writes the checkpoint of the current step to dst, host or device memory
+ * owned by the caller, of dst_bytes >= lbm_checkpoint_bytes(ctx) bytes.
+ * Synchronizes the context's stream.  LBM_EINVAL for a NULL pointer or a
+ * short buffer, LBM_EDEVICE if a copy fails. */
+int lbm_save(lbm_ctx* ctx, void* dst, int64_t dst_bytes);
+
+/* Restores a checkpoint (host or device memory, src_bytes long) into ctx,
+ * which must have been created with the same lattice, grid, tau and flags as
+ * the context that wrote it (LBM_EINVAL otherwise, and for a short or foreign
+ * buffer; ctx is then unchanged).  The state goes to the first of ctx's
+ * buffers; the step count and tau3, tau4 are those of the checkpoint.
+ * Synchronizes the context's stream. */
+int lbm_load(lbm_ctx* ctx, const void* src, int64_t src_bytes);
+
 /* Frees the context's own scratch (not the caller's buffers).  NULL is a no-op. */
 void lbm_destroy(lbm_ctx* ctx);
 

@@ -37,7 +37,8 @@ EXPORTS = ["lbm_lattice_info", "lbm_lattice_velocities", "lbm_buffer_elems", "lb
            "lbm_batch_create", "lbm_batch_step", "lbm_batch_autotune", "lbm_batch_config", "lbm_batch_destroy",
            "lbm_closure_samples", "lbm_mlp_stats", "lbm_mlp_normalize", "lbm_mlp_create", "lbm_mlp_forward",
            "lbm_mlp_step", "lbm_mlp_destroy", "lbm_closure_set", "lbm_closure_fallbacks",
-           "lbm_lattice_velocities_3d", "lbm_buffer_elems_3d", "lbm_init_3d", "lbm_moments_3d"]
+           "lbm_lattice_velocities_3d", "lbm_buffer_elems_3d", "lbm_init_3d", "lbm_moments_3d",
+           "lbm_checkpoint_bytes", "lbm_save", "lbm_load"]
 LBM_MLP_NPARAM = 5776
 LBM_MLP_NNORM = 96
 
@@ -100,6 +101,10 @@ def lib():
         L.lbm_init_3d.argtypes = [ctypes.POINTER(vp), ci, ci, ci, ci, ctypes.c_double, ci, ctypes.c_uint32,
                                   vp, vp, vp, vp, vp, vp, vp, ctypes.c_double, vp]
         L.lbm_moments_3d.argtypes = [vp, vp, vp, vp, vp, dp]
+        L.lbm_checkpoint_bytes.argtypes = [vp]
+        L.lbm_checkpoint_bytes.restype = ctypes.c_int64
+        L.lbm_save.argtypes = [vp, vp, ctypes.c_int64]
+        L.lbm_load.argtypes = [vp, vp, ctypes.c_int64]
         _lib = L
     return _lib
 
@@ -179,6 +184,34 @@ def lbm_populations(ctx, f_out):
 
 def lbm_destroy(ctx):
     lib().lbm_destroy(ctypes.c_void_p(ctx))
+
+
+LBM_CHECKPOINT_HEADER_BYTES = 64
+
+
+def lbm_checkpoint_bytes(ctx) -> int:
+    n = lib().lbm_checkpoint_bytes(ctypes.c_void_p(ctx))
+    if n < 0:
+        raise LbmError(int(n), lbm_last_error())
+    return int(n)
+
+
+def _addr(buf):
+    """Address of a numpy array (host) or torch tensor (host or device)."""
+    if isinstance(buf, np.ndarray):
+        assert buf.flags["C_CONTIGUOUS"]
+        return ctypes.c_void_p(buf.ctypes.data), buf.nbytes
+    return ctypes.c_void_p(buf.data_ptr()), buf.numel() * buf.element_size()
+
+
+def lbm_save(ctx, dst):
+    p, n = _addr(dst)
+    _check(lib().lbm_save(ctypes.c_void_p(ctx), p, n))
+
+
+def lbm_load(ctx, src):
+    p, n = _addr(src)
+    _check(lib().lbm_load(ctypes.c_void_p(ctx), p, n))
 
 
 def lbm_lattice_velocities_3d(lattice):
@@ -337,6 +370,15 @@ class Simulation:
         t = self.torch.empty((self.q, self.ny, self.nx), dtype=self.torch.float64, device=self.device)
         lbm_populations(self.ctx, t)
         return t
+
+    def save(self) -> np.ndarray:
+        """Checkpoint of the current step (host bytes)."""
+        buf = np.empty(lbm_checkpoint_bytes(self.ctx), dtype=np.uint8)
+        lbm_save(self.ctx, buf)
+        return buf
+
+    def load(self, buf):
+        lbm_load(self.ctx, buf)
 
     def moments(self, sums=True, vorticity=True):
         torch = self.torch

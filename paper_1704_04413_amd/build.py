@@ -1,37 +1,100 @@
-"""Builds librrlbm.so (the HIP C-ABI library) in-tree for gfx950 with hipcc."""
+"""Builds librrlbm.so (the HIP C-ABI library) in-tree for gfx950 with hipcc.
+
+The kernels are split over translation units that compile in parallel: the
+2D step once per (lattice, storage) pair, the 3D step once per lattice, the
+moment representation once per lattice, the batch kernel once per storage,
+the closure, and the host-side C-ABI.  Objects go to _build/ next to this
+file and are linked into one shared library.
+"""
 from __future__ import annotations
 
+import glob
 import os
 import subprocess
 import sys
+import time
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librrlbm.so")
-SOURCES = [os.path.join(CSRC, "rrlbm.hip")]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # keep the compiler from emitting packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
 ]
 
+# (object name, source, defines); the heaviest units first so that the
+# parallel build ends soonest
+UNITS = (
+    [(f"step2d_{lat}_{st}", "step2d.hip", {"RR_LAT": lat, "RR_STORE": st}) for lat in (2, 1, 0) for st in (0, 1, 2)]
+    + [(f"step3d_{lat}", "step3d.hip", {"RR_LAT3": lat}) for lat in (6, 5, 4, 3)]
+    + [("closure", "closure.hip", {})]
+    + [(f"batch_{st}", "batch.hip", {"RR_STORE": st}) for st in (0, 1, 2)]
+    + [(f"mom_{lat}", "mom.hip", {"RR_LAT": lat}) for lat in (2, 1, 0)]
+    + [("api", "api.hip", {})]
+)
 
-def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None) -> str:
-    """Compile every HIP source into librrlbm.so (always recompiles)."""
+
+def _jobs() -> int:
+    n = os.environ.get("MAX_JOBS") or os.cpu_count() or 4
+    return max(1, min(16, int(n)))
+
+
+def _newest_source() -> float:
+    files = glob.glob(os.path.join(CSRC, "*")) + glob.glob(os.path.join(INCLUDE, "*.h"))
+    return max(os.path.getmtime(f) for f in files)
+
+
+def _compile(unit, extra, verbose, incremental, newest):
+    name, src, defs = unit
+    obj = os.path.join(OBJDIR, name + ".o")
+    if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
+        return name, 0.0, False
+    cmd = [HIPCC, *FLAGS, *extra, *[f"-D{k}={v}" for k, v in defs.items()], "-I", INCLUDE, "-I", CSRC,
+           "-c", "-o", obj + ".tmp", os.path.join(CSRC, src)]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    t0 = time.time()
+    subprocess.run(cmd, check=True)
+    os.replace(obj + ".tmp", obj)
+    return name, time.time() - t0, True
+
+
+def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None,
+          incremental: bool = False) -> str:
+    """Compile every unit (all of them unless `incremental`, which skips
+    objects newer than every source and header) and link librrlbm.so."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    extra = list(extra or [])
+    newest = _newest_source()
+    t0 = time.time()
+    with ThreadPoolExecutor(max_workers=_jobs()) as ex:
+        futs = [ex.submit(_compile, u, extra, verbose, incremental, newest) for u in UNITS]
+        done = [f.result() for f in futs]
+    if verbose:
+        for name, dt, built in done:
+            if built:
+                print(f"  {name}: {dt:.0f} s", flush=True)
     target = out or LIB
-    tmp = target + ".tmp"
-    cmd = [HIPCC, *FLAGS, *(extra or []), "-I", os.path.join(ROOT, "include"), "-I", CSRC,
-           "-o", tmp, *SOURCES]
+    objs = [os.path.join(OBJDIR, u[0] + ".o") for u in UNITS]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", target + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(tmp, target)
+    os.replace(target + ".tmp", target)
+    if verbose:
+        print(f"built {target} in {time.time() - t0:.0f} s", flush=True)
     return target
 
 
 if __name__ == "__main__":
-    build(verbose=True, extra=sys.argv[1:])
+    args = sys.argv[1:]
+    inc = "--incremental" in args
+    build(verbose=True, extra=[a for a in args if a != "--incremental"], incremental=inc)

@@ -30,6 +30,7 @@
 #include <cstdint>
 
 #include "collide.hpp"
+#include "step2d.hpp"
 
 namespace rr {
 

@@ -24,11 +24,10 @@
 // and by +/- pairs, using H^k_i = He_kx(c_x) He_ky(c_y) (App. C, 2D).
 #pragma once
 
+#include "common.hpp"
 #include "lattices.hpp"
 
 namespace rr {
-
-enum Coll { COLL_RR = 0, COLL_PR = 1, COLL_BGK = 2 };
 
 // Row moments: r[cy + R][p] = sum over velocities of row c_y of v_i c_x^p, and
 // then s[p][q] = sum_i v_i c_x^p c_y^q for p + q <= 4.
@@ -288,13 +287,6 @@ __device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k
         a1[0][4] = T(4) * uy * a1[0][3] + T(6) * by * yy;
     }
 }
-
-// Relaxation of one step: k_n = 1 - 1/tau_n for the non-equilibrium part of
-// rank n (Eq. GenRegCollision with one time per order, the Hermite MRT form;
-// tau_2 = tau, and 0 above the regularization order), inv_tau = 1/tau (BGK).
-struct Relax {
-    double k2, k3, k4, inv_tau;
-};
 
 // Step 5: relax and rebuild the populations,
 // C = (a0 + k_n a1) / norm over the basis, k_n of rank n (0 above N).

@@ -371,8 +371,6 @@ __global__ __launch_bounds__(256) void k_init3(Init3Args a)
 
 // rho, u per node and block sums of [rho, rho ux, rho uy, rho uz,
 // sum f |c|^2 / 2, |u|^2, |u|^4, non-finite].
-constexpr int MOM3_NS = 8;
-
 template <class L>
 __global__ __launch_bounds__(256) void k_moments3(const double* f, Layout lay, int ny, int nz, double* rho_o,
                                                   double* ux_o, double* uy_o, double* uz_o, double* partial)

@@ -19,8 +19,6 @@
 
 namespace rr {
 
-constexpr int MOM_K = 6;
-
 struct StoreMom {
     using elem = double;
     using math = double;

@@ -1,0 +1,375 @@
+// Kernels of the 2D population step: storage types (FP64, weight-shifted FP32
+// and BF16 with stochastic rounding), the fused pull stream-and-collide kernel,
+// the batched persistent kernel, the initial state, and the per-node
+// diagnostics.  Templates only; each translation unit instantiates the
+// (lattice, storage) pairs it serves.  The layout is the row-tiled one of
+// common.hpp.  One step is one launch of a pull kernel: the thread of node x
+// gathers f_i(x - c_i) from the source buffer (one fixed offset per plane, so
+// every stored value is read exactly once), collides in registers and writes
+// its Q post-collision values to the destination buffer, with the load and
+// store kinds of the cache policy that the buffer size selects (Policy).  The
+// two buffers alternate; the state kept between steps is post-collision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "collide.hpp"
+#include "common.hpp"
+
+namespace rr {
+
+// ---------------------------------------------------------------- storage
+
+struct StoreF64 {
+    using elem = double;
+    using math = double;
+    static constexpr bool shifted = false;
+    static constexpr bool conserve_in_double = false;
+    static constexpr bool dithered = false;
+    static __device__ __forceinline__ double load(const double* p) { return *p; }
+    static __device__ __forceinline__ double load_nt(const double* p) { return __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
+    static __device__ __forceinline__ void store_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
+};
+
+struct StoreF32 {
+    using elem = float;
+    using math = float;
+    static constexpr bool shifted = true;
+    static constexpr bool conserve_in_double = true;
+    static constexpr bool dithered = false;
+    static __device__ __forceinline__ float load(const float* p) { return *p; }
+    static __device__ __forceinline__ float load_nt(const float* p) { return __builtin_nontemporal_load(p); }
+    static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
+    static __device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+};
+
+// bfloat16 = the upper half of an IEEE float.  The initial state is rounded
+// to nearest even; every step rounds stochastically (store_nt_sr): with
+// deterministic rounding a near-uniform region sits at a fixed point of the
+// rounded update and its 2^-9 rounding bias acts coherently over thousands of
+// steps, while a rounding that is unbiased in expectation turns it into noise.
+struct StoreBF16 {
+    using elem = uint16_t;
+    using math = float;
+    static constexpr bool shifted = true;
+    static constexpr bool conserve_in_double = false;
+    static constexpr bool dithered = true;
+    static __device__ __forceinline__ float load(const uint16_t* p)
+    {
+        return __uint_as_float(uint32_t(*p) << 16);
+    }
+    static __device__ __forceinline__ float load_nt(const uint16_t* p)
+    {
+        return __uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16);
+    }
+    static __device__ __forceinline__ uint16_t round(float v)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u); // quiet NaN
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return uint16_t(u >> 16);
+    }
+    static __device__ __forceinline__ void store(uint16_t* p, float v) { *p = round(v); }
+    static __device__ __forceinline__ void store_nt(uint16_t* p, float v) { __builtin_nontemporal_store(round(v), p); }
+    // r: 16 uniform random bits; |v| rounds up with probability (dropped bits) / 2^16
+    static __device__ __forceinline__ uint16_t round_sr(float v, uint32_t r)
+    {
+        uint32_t u = __float_as_uint(v);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u); // quiet NaN
+        return uint16_t((u + r) >> 16);
+    }
+    static __device__ __forceinline__ void store_nt_sr(uint16_t* p, float v, uint32_t r)
+    {
+        __builtin_nontemporal_store(round_sr(v, r), p);
+    }
+    static __device__ __forceinline__ void store_sr(uint16_t* p, float v, uint32_t r) { *p = round_sr(v, r); }
+};
+
+// Counter-based random bits for stochastic rounding: a function of the node
+// (y nx + x of its own grid) and of the index of the state being written (0 for
+// the initial state, n after n steps) only, so results do not depend on launch
+// shape or batching.  The key is Wellons' "lowbias32" integer hash; the stream
+// per node is the 32-bit LCG of PCG (O'Neill), of which the top 16 bits are used.
+struct Dither {
+    uint32_t s;
+    static __device__ __forceinline__ uint32_t mix(uint32_t x)
+    {
+        x ^= x >> 16;
+        x *= 0x7feb352du;
+        x ^= x >> 15;
+        x *= 0x846ca68bu;
+        x ^= x >> 16;
+        return x;
+    }
+    __device__ __forceinline__ Dither(uint32_t node, uint32_t seq) : s(mix(node ^ mix(seq * 0x9e3779b9u + 0x6a09e667u))) {}
+    __device__ __forceinline__ uint32_t next16()
+    {
+        s = s * 747796405u + 2891336453u;
+        return s >> 16;
+    }
+};
+
+// Writes the Q post-collision values of one node (stochastic rounding where
+// the storage asks for it).
+template <class L, class S, class T, bool NT = true>
+__device__ __forceinline__ void store_node(typename S::elem* __restrict__ fout, int here, int te, const T (&v)[L::Q],
+                                           uint32_t node, uint32_t seq)
+{
+    // NT: non-temporal stores, for state buffers larger than the memory-side
+    // cache; ordinary stores leave the written state there for the next step
+    if constexpr (S::dithered) {
+        Dither dz(node, seq);
+        if constexpr (NT)
+            static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + here + int(I) * te, v[I], dz.next16()); });
+        else
+            static_for<L::Q>([&](auto I) { S::store_sr(fout + here + int(I) * te, v[I], dz.next16()); });
+    } else {
+        if constexpr (NT)
+            static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * te, v[I]); });
+        else
+            static_for<L::Q>([&](auto I) { S::store(fout + here + int(I) * te, v[I]); });
+    }
+}
+
+// ------------------------------------------------------------ step kernel
+
+// Minimum waves per SIMD the compiler must leave room for in the step
+// kernel (register budget); more resident waves keep more loads in flight
+// while other waves run the collision arithmetic.
+#ifndef RRLBM_WAVES_PER_EU
+#define RRLBM_WAVES_PER_EU 4
+#endif
+
+// The hardware hands consecutive workgroup ids to the 8 XCDs in turn; with
+// the remap, XCD k works on the k-th contiguous eighth of the tiles, so
+// neighbouring tiles share that XCD's L2.
+// With `reverse` the tiles are walked last to first: a step then starts on
+// the tiles the previous step wrote last, which are the ones still in the
+// memory-side cache.
+__device__ __forceinline__ int block_index(const StepArgs& a)
+{
+    int id = int(blockIdx.x);
+    if (a.xcd_remap) {
+        const int q = a.nblocks / 8, r = a.nblocks % 8;
+        const int xcd = id % 8, local = id / 8;
+        id = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    }
+    return a.reverse ? a.nblocks - 1 - id : id;
+}
+
+// One node: gather (pull, periodic, or local when !PULL), collide, store.
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, bool NT = true, bool NTLOAD = false>
+__device__ __forceinline__ void node_update(const typename S::elem* __restrict__ fin,
+                                            typename S::elem* __restrict__ fout, const Layout& lay, int x,
+                                            int y, const Relax& rx, uint32_t seq)
+{
+    using T = typename S::math;
+    constexpr int R = L::R;
+    const int nx = lay.nx, ny = lay.ny;
+
+    // periodic source columns / tile rows for every shift in [-R, R]
+    int xs[2 * R + 1], ys[2 * R + 1];
+    static_for<2 * R + 1>([&](auto D) {
+        constexpr int d = int(D) - R;
+        int xx = x - d, yy = y - d;
+        if constexpr (d > 0) {
+            xx += (xx < 0) ? nx : 0;
+            yy += (yy < 0) ? ny : 0;
+        } else if constexpr (d < 0) {
+            xx -= (xx >= nx) ? nx : 0;
+            yy -= (yy >= ny) ? ny : 0;
+        }
+        xs[D] = xx;
+        ys[D] = lay.row(yy);
+    });
+
+    T v[L::Q];
+    const int here = lay.row(y) + x;
+    static_for<L::Q>([&](auto I) {
+        constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
+        const int idx = (PULL ? ys[cy + R] + xs[cx + R] : here) + int(I) * lay.te;
+        if constexpr (NTLOAD)
+            v[I] = S::load_nt(fin + idx);
+        else
+            v[I] = S::load(fin + idx);
+    });
+
+    collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, rx);
+
+    store_node<L, S, T, NT>(fout, here, lay.te, v, uint32_t(y) * uint32_t(nx) + uint32_t(x), seq);
+}
+
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, int POL>
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU)))
+void k_stream_collide(StepArgs a)
+{
+    const int bid = block_index(a);
+    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
+    const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
+    if (x >= a.lay.nx || y >= a.lay.ny) return;
+    node_update<L, S, COLL, THERMAL, A13P, PULL, POL == POL_STREAM, POL == POL_KEEP>(
+        static_cast<const typename S::elem*>(a.fin), static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx,
+        a.seq);
+}
+
+// ---------------------------------------------------------- batch kernel
+
+// Persistent kernel: blocks stride over the work list (member, tile); item w
+// belongs to the member i with begin[i] <= w < begin[i+1].  Each item is a
+// tile_x by 4 patch of one member, walked 64 columns at a time.  `parity`
+// selects the buffer direction of this step for every member.
+template <class S>
+__global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ desc, const int* __restrict__ begin,
+                                                  int n, int total, int parity, int tile_x)
+{
+    using E = typename S::elem;
+    for (int w = int(blockIdx.x); w < total; w += int(gridDim.x)) {
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (begin[mid] <= w)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        const int i = __builtin_amdgcn_readfirstlane(lo);
+        const InstDesc& d = desc[i];
+        const int local = w - begin[i];
+        const int x0 = (local % d.bx_blocks) * tile_x;
+        const int y = (local / d.bx_blocks) * BY + int(threadIdx.y);
+        const int src = d.flip ^ parity;
+        const E* fin = static_cast<const E*>(d.buf[src]);
+        E* fout = static_cast<E*>(d.buf[src ^ 1]);
+        for (int sub = 0; sub < tile_x; sub += BX) {
+            const int x = x0 + sub + int(threadIdx.x);
+            if (x < d.lay.nx && y < d.lay.ny) {
+                switch (d.lattice) {
+                case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
+                case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
+                default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
+                }
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ init kernel
+
+template <class L, class S>
+__global__ __launch_bounds__(256) void k_init(InitArgs a)
+{
+    const int64_t n = int64_t(a.lay.nx) * a.lay.ny;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int here = a.lay.row(int(k / a.lay.nx)) + int(k % a.lay.nx);
+    double f[L::Q];
+    const double th = a.theta ? a.theta[k] : 1.0;
+    equilibrium_node<L, double, S::shifted>(a.rho[k], a.ux[k], a.uy[k], th, a.eq_order, f);
+    if (a.grad) {
+        const double du[2][2] = { { a.grad[k], a.grad[2 * n + k] }, { a.grad[n + k], a.grad[3 * n + k] } };
+        double f1[L::Q];
+        noneq_init_node<L, double>(a.rho[k], a.ux[k], a.uy[k], du, a.tau, a.eq_order, f1);
+        static_for<L::Q>([&](auto I) { f[I] += f1[I]; });
+    }
+    typename S::elem* out = static_cast<typename S::elem*>(a.f);
+    static_for<L::Q>([&](auto I) {
+        double v = f[I];
+        if (a.noise) v += a.noise_amp * L::v.w[I] * a.noise[int64_t(I) * n + k];
+        S::store(out + here + int(I) * a.lay.te, typename S::math(v));
+    });
+}
+
+// --------------------------------------------------- populations / moments
+
+template <class L, class S>
+__global__ __launch_bounds__(256) void k_populations(const void* fsrc, Layout lay, double* out)
+{
+    const int64_t n = int64_t(lay.nx) * lay.ny;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
+    const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
+    static_for<L::Q>([&](auto I) {
+        double v = double(S::load(f + here + int(I) * lay.te));
+        if (S::shifted) v += L::v.w[I];
+        out[int64_t(I) * n + k] = v;
+    });
+}
+
+template <int NS>
+__device__ __forceinline__ void block_sums(double (&val)[NS], double* partial)
+{
+    __shared__ double red[NS][256];
+    const int t = threadIdx.x;
+    for (int s = 0; s < NS; ++s) red[s][t] = val[s];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (t < w)
+            for (int s = 0; s < NS; ++s) red[s][t] += red[s][t + w];
+        __syncthreads();
+    }
+    if (t < NS) partial[int64_t(blockIdx.x) * NS + t] = red[t][0];
+}
+
+// Diagnostics of one node from its post-collision populations v (a NULL field
+// pointer is skipped).
+template <class L>
+__device__ __forceinline__ void node_diag(const double (&v)[L::Q], int thermal, int64_t k, double* rho_o,
+                                          double* ux_o, double* uy_o, double* th_o, double (&val)[MOM_NS])
+{
+    double r = 0, jx = 0, jy = 0, e2 = 0;
+    static_for<L::Q>([&](auto I) {
+        constexpr double cx = L::v.cx[I], cy = L::v.cy[I];
+        r += v[I];
+        jx += cx * v[I];
+        jy += cy * v[I];
+        e2 += (cx * cx + cy * cy) * v[I];
+    });
+    const double ux = jx / r, uy = jy / r;
+    const double u2 = ux * ux + uy * uy;
+    const double th = thermal ? (e2 - r * u2) / (2.0 * r * L::cs2) : 1.0;
+    if (rho_o) rho_o[k] = r;
+    if (ux_o) ux_o[k] = ux;
+    if (uy_o) uy_o[k] = uy;
+    if (th_o) th_o[k] = th;
+    const bool finite = std::isfinite(r) && std::isfinite(ux) && std::isfinite(uy) && std::isfinite(th);
+    if (finite) {
+        val[0] = r;
+        val[1] = jx;
+        val[2] = jy;
+        val[3] = 0.5 * e2;
+        val[4] = u2;
+        val[5] = u2 * u2;
+        val[7] = th;
+    } else {
+        val[6] = 1.0;
+    }
+}
+
+// rho, u, theta per node (FP64 arithmetic whatever the storage) and block sums
+// of [rho, rho ux, rho uy, sum f|c|^2/2, |u|^2, |u|^4, non-finite, theta].
+template <class L, class S>
+__global__ __launch_bounds__(256) void k_moments(const void* fsrc, Layout lay, int thermal, double* rho_o,
+                                                 double* ux_o, double* uy_o, double* th_o, double* partial)
+{
+    const int64_t n = int64_t(lay.nx) * lay.ny;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    double val[MOM_NS] = { 0, 0, 0, 0, 0, 0, 0, 0 };
+    if (k < n) {
+        const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
+        const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
+        double v[L::Q];
+        static_for<L::Q>([&](auto I) {
+            v[I] = double(S::load(f + here + int(I) * lay.te));
+            if (S::shifted) v[I] += L::v.w[I];
+        });
+        node_diag<L>(v, thermal, k, rho_o, ux_o, uy_o, th_o, val);
+    }
+    block_sums<MOM_NS>(val, partial);
+}
+
+} // namespace rr

@@ -1,0 +1,93 @@
+// The 3D step for one lattice of Table II, chosen at compile time: this file
+// is compiled once per lattice (RR_LAT3 = LBM_D3Q19, LBM_D3Q27, LBM_D3V39 or
+// LBM_D3Q103).  It provides the pull step for every collision and cache
+// policy, the initial state, the population dump and the diagnostics.
+#include "context.hpp"
+#include "step2d.hpp"
+#include "collide3d.hpp"
+
+#if !defined(RR_LAT3)
+#error "compile with -DRR_LAT3=<3D lattice id>"
+#endif
+
+namespace rr {
+namespace {
+
+#if RR_LAT3 == 3
+using Lat = D3Q19;
+#elif RR_LAT3 == 4
+using Lat = D3Q27;
+#elif RR_LAT3 == 5
+using Lat = D3V39;
+#elif RR_LAT3 == 6
+using Lat = D3Q103;
+#else
+#error "RR_LAT3 must be a 3D lattice"
+#endif
+
+template <int MODE>
+hipError_t step_t(const lbm_ctx* c, const void* fin, void* fout)
+{
+    const int rows = c->ny * c->nz;
+    const int bxn = (c->nx + BX - 1) / BX, byn = (rows + BY - 1) / BY;
+    // the cache policies are instantiated for the RR and BGK steps; PR streams
+    const int pol = MODE != C3_PR ? c->pol : POL_STREAM;
+    Step3Args a{ fin, fout, c->lay, c->ny, c->nz, bxn, bxn * byn, c->xcd_remap, relax_of(c), c->order,
+                 (pol == POL_CACHE && (c->steps & 1)) ? 1 : 0 };
+    const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
+    if constexpr (MODE != C3_PR) {
+        if (pol == POL_CACHE) {
+            k_stream_collide3<Lat, MODE, POL_CACHE><<<grid, block, 0, c->stream>>>(a);
+            return hipGetLastError();
+        }
+        if (pol == POL_KEEP) {
+            k_stream_collide3<Lat, MODE, POL_KEEP><<<grid, block, 0, c->stream>>>(a);
+            return hipGetLastError();
+        }
+    }
+    k_stream_collide3<Lat, MODE, POL_STREAM><<<grid, block, 0, c->stream>>>(a);
+    return hipGetLastError();
+}
+
+hipError_t step(const lbm_ctx* c, const void* fin, void* fout)
+{
+    switch (c->coll) {
+    case COLL_PR: return step_t<C3_PR>(c, fin, fout);
+    case COLL_BGK: return step_t<C3_BGK>(c, fin, fout);
+    default: return step_t<C3_RR>(c, fin, fout);
+    }
+}
+
+hipError_t init(const lbm_ctx* c, void* dst, const double* rho, const double* ux, const double* uy,
+                const double* uz, const double* noise, double noise_amp, int eq_order)
+{
+    const Init3Args ia{ dst, c->lay, c->ny, c->nz, rho, ux, uy, uz, noise, noise_amp, eq_order };
+    k_init3<Lat><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
+    return hipGetLastError();
+}
+
+hipError_t populations(const lbm_ctx* c, const void* src, double* out)
+{
+    const int64_t n = int64_t(c->nx) * c->ny * c->nz;
+    k_populations<Lat, StoreF64><<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream>>>(src, c->lay, out);
+    return hipGetLastError();
+}
+
+hipError_t moments(const lbm_ctx* c, double* r, double* ux, double* uy, double* uz, double* partial)
+{
+    k_moments3<Lat><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(
+        static_cast<const double*>(c->buf[c->cur]), c->lay, c->ny, c->nz, r, ux, uy, uz, partial);
+    return hipGetLastError();
+}
+
+} // namespace
+
+#define RR_OPS3D_NAME_(l) ops3d_##l
+#define RR_OPS3D_NAME(l) RR_OPS3D_NAME_(l)
+const Ops3D& RR_OPS3D_NAME(RR_LAT3)()
+{
+    static const Ops3D ops{ step, init, populations, moments };
+    return ops;
+}
+
+} // namespace rr

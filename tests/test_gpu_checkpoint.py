@@ -1,0 +1,125 @@
+"""Checkpoints through the C-ABI (lbm_save / lbm_load): the state of the
+explicit scheme of Sec. III.A between steps is the post-collision population
+field and the step count (which also keys the BF16 stochastic rounding), so
+n steps must equal k steps + save + load into a fresh context + n - k steps,
+bit for bit, for every storage, the thermal form, the moment representation
+and a 3D lattice; foreign or short checkpoints are rejected."""
+import numpy as np
+import pytest
+
+from paper_1704_04413_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1704_04413_amd import binding
+
+    binding.lib()
+    return binding, torch
+
+
+def make(b, lattice, n, flags, re=3e4, seed=4):
+    q, _, _, cs2 = b.lbm_lattice_info(lattice)
+    u0, tau = wl.shear_layer_params(cs2, n, re)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    theta = np.ones_like(rho) if flags & b.LBM_THERMAL else None
+    noise = wl.uniform_noise(seed, q, n, n)
+    return b.Simulation(lattice, n, n, tau, rho, ux, uy, theta=theta, noise=noise, noise_amp=1e-8, flags=flags)
+
+
+CASES = [("D2V37", 0), ("D2V37", 0x2), ("D2V37", 0x4), ("D2Q9", 0x2), ("D2V37", 0x1), ("D2V17", 0x8)]
+
+
+@pytest.mark.parametrize("lattice,flags", CASES)
+@pytest.mark.parametrize("where", ["host", "device"])
+def test_resume_is_bitwise(env, lattice, flags, where):
+    b, torch = env
+    n, total, k = 70, 9, 4
+    print(f"[case] checkpoint {lattice} flags={flags:#x} {n}x{n} {k}+{total - k} steps in {where} memory", flush=True)
+    ref = make(b, lattice, n, flags)
+    if not flags & 0x8:
+        ref.set_relaxation(0.61, 0.7)
+    ref.step(total)
+    want = ref.populations().cpu().numpy()
+    ref.close()
+
+    first = make(b, lattice, n, flags)
+    if not flags & 0x8:
+        first.set_relaxation(0.61, 0.7)
+    first.step(k)
+    nbytes = b.lbm_checkpoint_bytes(first.ctx)
+    if where == "host":
+        buf = first.save()
+    else:
+        buf = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        b.lbm_save(first.ctx, buf)
+    first.close()
+
+    # a fresh context created by the same arguments (another noise draw: the load replaces the state)
+    second = make(b, lattice, n, flags, seed=9)
+    second.load(buf)
+    assert second.steps == k
+    second.step(total - k)
+    got = second.populations().cpu().numpy()
+    assert second.steps == total
+    second.close()
+    assert np.array_equal(got, want), float(np.abs(got - want).max())
+
+
+def test_resume_3d_is_bitwise(env):
+    b, torch = env
+    n, total, k = 12, 5, 2
+    print(f"[case] checkpoint D3Q19 {n}^3 {k}+{total - k} steps", flush=True)
+    q, _, _, cs2 = b.lbm_lattice_info("D3Q19")
+    u0, tau = wl.shear_layer_params(cs2, n, 1e3)
+    fields = wl.shear_layer_fields_3d(n, n, n, u0)
+
+    def sim():
+        return b.Simulation3D("D3Q19", n, n, n, tau, *fields)
+
+    ref = sim()
+    ref.step(total)
+    want = ref.populations().cpu().numpy()
+    ref.close()
+    a = sim()
+    a.step(k)
+    buf = a.save()
+    a.close()
+    c = sim()
+    c.load(buf)
+    c.step(total - k)
+    got = c.populations().cpu().numpy()
+    c.close()
+    assert np.array_equal(got, want)
+
+
+def test_foreign_or_short_checkpoints_are_rejected(env):
+    b, torch = env
+    print("[case] checkpoint rejection", flush=True)
+    s = make(b, "D2V37", 64, 0)
+    s.step(3)
+    buf = s.save()
+    assert buf.nbytes == b.LBM_CHECKPOINT_HEADER_BYTES + 8 * b.lbm_buffer_elems("D2V37", 64, 64)
+    before = s.populations().cpu().numpy()
+    other = make(b, "D2V37", 64, 0x2)  # other storage
+    with pytest.raises(b.LbmError):
+        other.load(buf)
+    assert other.steps == 0
+    other.close()
+    with pytest.raises(b.LbmError):
+        s.load(buf[:-1].copy())  # short
+    bad = buf.copy()
+    bad[0] ^= 1  # magic
+    with pytest.raises(b.LbmError):
+        s.load(bad)
+    with pytest.raises(b.LbmError):
+        b.lbm_save(s.ctx, np.empty(16, dtype=np.uint8))
+    assert s.steps == 3
+    assert np.array_equal(s.populations().cpu().numpy(), before)
+    s.close()

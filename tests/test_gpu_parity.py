@@ -169,6 +169,11 @@ def test_fp64_minimum_grids(orc, b, name, nx, ny):
     got = run_gpu(b, name, nx, ny, 0.7, (rho, ux, uy, None, noise * (1e-3 / 1e-8)), 7)
     want = orc.collide(lat, orc.step(lat, f0, 0.7, 7), 0.7)
     check(got["f"], want, 1e-12)
+    # the +-2 vorticity stencil wraps more than once on axes shorter than 2
+    _, vx, vy, _ = orc.moments(lat, want)
+    w = orc.vorticity(vx, vy)
+    np.testing.assert_allclose(got["vort"], w, rtol=0, atol=1e-11)
+    assert got["sums"][6] == pytest.approx(float(np.sum(w * w)), rel=1e-9, abs=1e-20)
 
 
 def test_zero_steps_and_uniform_steady_state(orc, b):
