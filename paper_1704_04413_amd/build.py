@@ -8,8 +8,8 @@ file and are linked into one shared library.
 """
 from __future__ import annotations
 
-import glob
 import os
+import re
 import subprocess
 import sys
 import time
@@ -47,14 +47,25 @@ def _jobs() -> int:
     return max(1, min(16, int(n)))
 
 
-def _newest_source() -> float:
-    files = glob.glob(os.path.join(CSRC, "*")) + glob.glob(os.path.join(INCLUDE, "*.h"))
-    return max(os.path.getmtime(f) for f in files)
+def _deps(src: str) -> set[str]:
+    """The source and every project header it includes, transitively."""
+    seen, todo = set(), [os.path.join(CSRC, src)]
+    while todo:
+        path = todo.pop()
+        if path in seen or not os.path.exists(path):
+            continue
+        seen.add(path)
+        for line in open(path):
+            m = re.match(r'\s*#\s*include\s*"([^"]+)"', line)
+            if m:
+                todo += [os.path.join(d, m.group(1)) for d in (CSRC, INCLUDE)]
+    return seen
 
 
-def _compile(unit, extra, verbose, incremental, newest):
+def _compile(unit, extra, verbose, incremental):
     name, src, defs = unit
     obj = os.path.join(OBJDIR, name + ".o")
+    newest = max(os.path.getmtime(f) for f in _deps(src))
     if incremental and os.path.exists(obj) and os.path.getmtime(obj) >= newest:
         return name, 0.0, False
     cmd = [HIPCC, *FLAGS, *extra, *[f"-D{k}={v}" for k, v in defs.items()], "-I", INCLUDE, "-I", CSRC,
@@ -70,13 +81,13 @@ def _compile(unit, extra, verbose, incremental, newest):
 def build(verbose: bool = False, extra: list[str] | None = None, out: str | None = None,
           incremental: bool = False) -> str:
     """Compile every unit (all of them unless `incremental`, which skips
-    objects newer than every source and header) and link librrlbm.so."""
+    objects newer than their source and the headers it includes) and link
+    librrlbm.so."""
     os.makedirs(OBJDIR, exist_ok=True)
     extra = list(extra or [])
-    newest = _newest_source()
     t0 = time.time()
     with ThreadPoolExecutor(max_workers=_jobs()) as ex:
-        futs = [ex.submit(_compile, u, extra, verbose, incremental, newest) for u in UNITS]
+        futs = [ex.submit(_compile, u, extra, verbose, incremental) for u in UNITS]
         done = [f.result() for f in futs]
     if verbose:
         for name, dt, built in done:

@@ -17,7 +17,7 @@
 // The state between steps is post-collision, pulled like the 2D step.
 #pragma once
 
-#include "collide.hpp"
+#include "common.hpp"
 #include "lattices3d.hpp"
 
 namespace rr {

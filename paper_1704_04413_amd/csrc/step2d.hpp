@@ -18,122 +18,9 @@
 
 #include "collide.hpp"
 #include "common.hpp"
+#include "storage.hpp"
 
 namespace rr {
-
-// ---------------------------------------------------------------- storage
-
-struct StoreF64 {
-    using elem = double;
-    using math = double;
-    static constexpr bool shifted = false;
-    static constexpr bool conserve_in_double = false;
-    static constexpr bool dithered = false;
-    static __device__ __forceinline__ double load(const double* p) { return *p; }
-    static __device__ __forceinline__ double load_nt(const double* p) { return __builtin_nontemporal_load(p); }
-    static __device__ __forceinline__ void store(double* p, double v) { *p = v; }
-    static __device__ __forceinline__ void store_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
-};
-
-struct StoreF32 {
-    using elem = float;
-    using math = float;
-    static constexpr bool shifted = true;
-    static constexpr bool conserve_in_double = true;
-    static constexpr bool dithered = false;
-    static __device__ __forceinline__ float load(const float* p) { return *p; }
-    static __device__ __forceinline__ float load_nt(const float* p) { return __builtin_nontemporal_load(p); }
-    static __device__ __forceinline__ void store(float* p, float v) { *p = v; }
-    static __device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
-};
-
-// bfloat16 = the upper half of an IEEE float.  The initial state is rounded
-// to nearest even; every step rounds stochastically (store_nt_sr): with
-// deterministic rounding a near-uniform region sits at a fixed point of the
-// rounded update and its 2^-9 rounding bias acts coherently over thousands of
-// steps, while a rounding that is unbiased in expectation turns it into noise.
-struct StoreBF16 {
-    using elem = uint16_t;
-    using math = float;
-    static constexpr bool shifted = true;
-    static constexpr bool conserve_in_double = false;
-    static constexpr bool dithered = true;
-    static __device__ __forceinline__ float load(const uint16_t* p)
-    {
-        return __uint_as_float(uint32_t(*p) << 16);
-    }
-    static __device__ __forceinline__ float load_nt(const uint16_t* p)
-    {
-        return __uint_as_float(uint32_t(__builtin_nontemporal_load(p)) << 16);
-    }
-    static __device__ __forceinline__ uint16_t round(float v)
-    {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u); // quiet NaN
-        u += 0x7fffu + ((u >> 16) & 1u);
-        return uint16_t(u >> 16);
-    }
-    static __device__ __forceinline__ void store(uint16_t* p, float v) { *p = round(v); }
-    static __device__ __forceinline__ void store_nt(uint16_t* p, float v) { __builtin_nontemporal_store(round(v), p); }
-    // r: 16 uniform random bits; |v| rounds up with probability (dropped bits) / 2^16
-    static __device__ __forceinline__ uint16_t round_sr(float v, uint32_t r)
-    {
-        uint32_t u = __float_as_uint(v);
-        if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40u); // quiet NaN
-        return uint16_t((u + r) >> 16);
-    }
-    static __device__ __forceinline__ void store_nt_sr(uint16_t* p, float v, uint32_t r)
-    {
-        __builtin_nontemporal_store(round_sr(v, r), p);
-    }
-    static __device__ __forceinline__ void store_sr(uint16_t* p, float v, uint32_t r) { *p = round_sr(v, r); }
-};
-
-// Counter-based random bits for stochastic rounding: a function of the node
-// (y nx + x of its own grid) and of the index of the state being written (0 for
-// the initial state, n after n steps) only, so results do not depend on launch
-// shape or batching.  The key is Wellons' "lowbias32" integer hash; the stream
-// per node is the 32-bit LCG of PCG (O'Neill), of which the top 16 bits are used.
-struct Dither {
-    uint32_t s;
-    static __device__ __forceinline__ uint32_t mix(uint32_t x)
-    {
-        x ^= x >> 16;
-        x *= 0x7feb352du;
-        x ^= x >> 15;
-        x *= 0x846ca68bu;
-        x ^= x >> 16;
-        return x;
-    }
-    __device__ __forceinline__ Dither(uint32_t node, uint32_t seq) : s(mix(node ^ mix(seq * 0x9e3779b9u + 0x6a09e667u))) {}
-    __device__ __forceinline__ uint32_t next16()
-    {
-        s = s * 747796405u + 2891336453u;
-        return s >> 16;
-    }
-};
-
-// Writes the Q post-collision values of one node (stochastic rounding where
-// the storage asks for it).
-template <class L, class S, class T, bool NT = true>
-__device__ __forceinline__ void store_node(typename S::elem* __restrict__ fout, int here, int te, const T (&v)[L::Q],
-                                           uint32_t node, uint32_t seq)
-{
-    // NT: non-temporal stores, for state buffers larger than the memory-side
-    // cache; ordinary stores leave the written state there for the next step
-    if constexpr (S::dithered) {
-        Dither dz(node, seq);
-        if constexpr (NT)
-            static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + here + int(I) * te, v[I], dz.next16()); });
-        else
-            static_for<L::Q>([&](auto I) { S::store_sr(fout + here + int(I) * te, v[I], dz.next16()); });
-    } else {
-        if constexpr (NT)
-            static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * te, v[I]); });
-        else
-            static_for<L::Q>([&](auto I) { S::store(fout + here + int(I) * te, v[I]); });
-    }
-}
 
 // ------------------------------------------------------------ step kernel
 
@@ -284,36 +171,6 @@ __global__ __launch_bounds__(256) void k_init(InitArgs a)
 }
 
 // --------------------------------------------------- populations / moments
-
-template <class L, class S>
-__global__ __launch_bounds__(256) void k_populations(const void* fsrc, Layout lay, double* out)
-{
-    const int64_t n = int64_t(lay.nx) * lay.ny;
-    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
-    const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
-    static_for<L::Q>([&](auto I) {
-        double v = double(S::load(f + here + int(I) * lay.te));
-        if (S::shifted) v += L::v.w[I];
-        out[int64_t(I) * n + k] = v;
-    });
-}
-
-template <int NS>
-__device__ __forceinline__ void block_sums(double (&val)[NS], double* partial)
-{
-    __shared__ double red[NS][256];
-    const int t = threadIdx.x;
-    for (int s = 0; s < NS; ++s) red[s][t] = val[s];
-    __syncthreads();
-    for (int w = 128; w > 0; w >>= 1) {
-        if (t < w)
-            for (int s = 0; s < NS; ++s) red[s][t] += red[s][t + w];
-        __syncthreads();
-    }
-    if (t < NS) partial[int64_t(blockIdx.x) * NS + t] = red[t][0];
-}
 
 // Diagnostics of one node from its post-collision populations v (a NULL field
 // pointer is skipped).

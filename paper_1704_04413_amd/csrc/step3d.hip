@@ -3,7 +3,7 @@
 // LBM_D3Q103).  It provides the pull step for every collision and cache
 // policy, the initial state, the population dump and the diagnostics.
 #include "context.hpp"
-#include "step2d.hpp"
+#include "storage.hpp"
 #include "collide3d.hpp"
 
 #if !defined(RR_LAT3)
