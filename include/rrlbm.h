@@ -168,6 +168,25 @@ int lbm_set_relaxation(lbm_ctx* ctx, double tau3, double tau4);
 int lbm_moments(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* theta, double* vort,
                 double* sums);
 
+/* Allocation-free lbm_moments, for callers that cannot allocate memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments and results (bit for bit) as lbm_moments, which
+ * allocates device and pinned scratch on its first call; this variant
+ * allocates nothing and uses instead a device array the library holds on
+ * every GPU it runs on until the process ends (LBM_NOALLOC_MAX_NODES / 256 *
+ * 10 + 10 doubles, about 5 MiB).  Limits:
+ *   - nx * ny <= LBM_NOALLOC_MAX_NODES (LBM_EINVAL beyond);
+ *   - ux and uy are required whenever vort or sums is (the vorticity reads
+ *     them); rho, theta, vort may be NULL (that field is not written);
+ *   - calls that overlap on one GPU (other streams, other threads) share that
+ *     array and race: serialize them;
+ *   - with sums = NULL the call only launches kernels on the context's
+ *     stream; with sums it synchronizes that stream.
+ * 2D contexts only (LBM_EINVAL for a 3D one). */
+#define LBM_NOALLOC_MAX_NODES (1 << 24)
+int lbm_moments_noalloc(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* theta, double* vort,
+                        double* sums);
+
 /* Copies the current post-collision populations into the device FP64 array
  * f_out[i][y][x] (shifted storage is converted back to f = g + w). */
 int lbm_populations(lbm_ctx* ctx, double* f_out);

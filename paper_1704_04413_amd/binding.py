@@ -38,7 +38,8 @@ EXPORTS = ["lbm_lattice_info", "lbm_lattice_velocities", "lbm_buffer_elems", "lb
            "lbm_closure_samples", "lbm_mlp_stats", "lbm_mlp_normalize", "lbm_mlp_create", "lbm_mlp_forward",
            "lbm_mlp_step", "lbm_mlp_destroy", "lbm_closure_set", "lbm_closure_fallbacks",
            "lbm_lattice_velocities_3d", "lbm_buffer_elems_3d", "lbm_init_3d", "lbm_moments_3d",
-           "lbm_checkpoint_bytes", "lbm_save", "lbm_load"]
+           "lbm_checkpoint_bytes", "lbm_save", "lbm_load", "lbm_moments_noalloc"]
+LBM_NOALLOC_MAX_NODES = 1 << 24
 LBM_MLP_NPARAM = 5776
 LBM_MLP_NNORM = 96
 
@@ -71,6 +72,7 @@ def lib():
         L.lbm_step_count.argtypes = [vp]
         L.lbm_step_count.restype = ctypes.c_int64
         L.lbm_moments.argtypes = [vp, vp, vp, vp, vp, vp, dp]
+        L.lbm_moments_noalloc.argtypes = [vp, vp, vp, vp, vp, vp, dp]
         L.lbm_populations.argtypes = [vp, vp]
         L.lbm_destroy.argtypes = [vp]
         L.lbm_destroy.restype = None
@@ -175,6 +177,13 @@ def lbm_moments(ctx, rho=None, ux=None, uy=None, theta=None, vort=None, sums=Fal
     out = (ctypes.c_double * LBM_NSUMS)() if sums else None
     _check(lib().lbm_moments(ctypes.c_void_p(ctx), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), _ptr(vort),
                              out))
+    return np.array(list(out)) if sums else None
+
+
+def lbm_moments_noalloc(ctx, rho=None, ux=None, uy=None, theta=None, vort=None, sums=False):
+    out = (ctypes.c_double * LBM_NSUMS)() if sums else None
+    _check(lib().lbm_moments_noalloc(ctypes.c_void_p(ctx), _ptr(rho), _ptr(ux), _ptr(uy), _ptr(theta), _ptr(vort),
+                                     out))
     return np.array(list(out)) if sums else None
 
 

@@ -12,6 +12,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -128,6 +129,60 @@ __global__ __launch_bounds__(256) void k_vorticity(const double* ux, const doubl
         __syncthreads();
     }
     if (t < VORT_NS) partial[int64_t(blockIdx.x) * VORT_NS + t] = red[t][0];
+}
+
+// ---- allocation-free diagnostics (lbm_moments_noalloc)
+
+constexpr int64_t NOALLOC_MAX_BLOCKS = LBM_NOALLOC_MAX_NODES / 256;
+constexpr int64_t NOALLOC_SCRATCH = NOALLOC_MAX_BLOCKS * (MOM_NS + VORT_NS) + LBM_NSUMS;
+
+// Per-block partial sums and the final sums of lbm_moments_noalloc.  Each GPU
+// holds its own copy for the life of the process.  On the host this name is
+// only a stand-in for the device array: kernels and copies get the address
+// from noalloc_scratch_ptr().
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH];
+
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[256] = {}; // per device id
+} // namespace
+
+// Device address of `scratch` on the current device, looked up once per device.
+hipError_t noalloc_scratch_ptr(double** out)
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 256) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
+// The LBM_NSUMS totals from the per-block partial sums, on the device: one
+// thread per sum, the blocks added in order with the same compensated
+// (Neumaier) summation as the host path, so both give the same bits.
+__global__ __launch_bounds__(64) void k_reduce_sums(const double* part, int64_t nblk, double* sums)
+{
+    const int s = int(threadIdx.x);
+    if (s >= MOM_NS + VORT_NS) return;
+    const double* base = s < MOM_NS ? part + s : part + MOM_NS * nblk + (s - MOM_NS);
+    const int stride = s < MOM_NS ? MOM_NS : VORT_NS;
+    const int slot = s < MOM_NS ? (s < 6 ? s : s + 2) : 6 + (s - MOM_NS); // [0..5, 8, 9] then [6, 7]
+    double acc = 0.0, comp = 0.0;
+    for (int64_t i = 0; i < nblk; ++i) {
+        const double v = base[i * stride];
+        const double t = acc + v;
+        comp += (fabs(acc) >= fabs(v)) ? (acc - t) + v : (v - t) + acc;
+        acc = t;
+    }
+    sums[slot] = acc + comp;
 }
 
 } // namespace rr
@@ -346,7 +401,11 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     const int64_t n = int64_t(nx) * ny;
     c->nblk = (n + 255) / 256;
 
-    hipError_t he = hipSuccess;
+    hipError_t he = noalloc_scratch_ptr(&c->noalloc_scratch);
+    if (he != hipSuccess) {
+        delete c;
+        return fail(LBM_EDEVICE, std::string("allocation-free scratch lookup: ") + hipGetErrorString(he));
+    }
     const int eq_order = (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq;
     if (c->store == ST_MOM) {
         const InitArgs ia{ f_a, c->lay, rho, ux, uy, theta, grad, noise, noise_amp, eq_order, tau };
@@ -411,6 +470,29 @@ int lbm_moments(lbm_ctx* c, double* rho, double* ux, double* uy, double* theta, 
                                hipMemcpyDeviceToHost, c->stream));
         HIP_TRY(hipStreamSynchronize(c->stream));
         reduce_sums(c->partial_host, c->nblk, sums);
+    }
+    return LBM_OK;
+}
+
+int lbm_moments_noalloc(lbm_ctx* c, double* rho, double* ux, double* uy, double* theta, double* vort, double* sums)
+{
+    if (!c) return fail(LBM_EINVAL, "ctx is NULL");
+    if (c->dim == 3) return fail(LBM_EINVAL, "3D context: use lbm_moments_3d");
+    if ((vort || sums) && (!ux || !uy))
+        return fail(LBM_EINVAL, "ux and uy are required when vort or sums is requested");
+    if (c->nblk > NOALLOC_MAX_BLOCKS)
+        return fail(LBM_EINVAL, "grid of " + std::to_string(int64_t(c->nx) * c->ny) +
+                                    " nodes exceeds the allocation-free limit of " +
+                                    std::to_string(int64_t(LBM_NOALLOC_MAX_NODES)) + " nodes");
+    if (!c->noalloc_scratch) return fail(LBM_EDEVICE, "no allocation-free scratch for this context");
+    double* part = c->noalloc_scratch;
+    HIP_TRY(moments_launch(c, rho, ux, uy, theta, vort || sums, vort, part));
+    if (sums) {
+        double* dsums = part + NOALLOC_MAX_BLOCKS * (MOM_NS + VORT_NS);
+        k_reduce_sums<<<dim3(1), dim3(64), 0, c->stream>>>(part, c->nblk, dsums);
+        HIP_TRY(hipGetLastError());
+        HIP_TRY(hipMemcpyAsync(sums, dsums, sizeof(double) * LBM_NSUMS, hipMemcpyDeviceToHost, c->stream));
+        HIP_TRY(hipStreamSynchronize(c->stream));
     }
     return LBM_OK;
 }

@@ -41,6 +41,7 @@ struct lbm_ctx {
     double* partial = nullptr;
     double* partial_host = nullptr;
     int64_t nblk = 0;
+    double* noalloc_scratch = nullptr; // this GPU's allocation-free scratch (lbm_moments_noalloc)
     // learned closure (isothermal D2V37 only)
     bool closure = false;
     rr::MlpInfer* cl_frags = nullptr;
