@@ -28,8 +28,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 METRIC = "MLUPS and % of HBM roofline per lattice; closure/low-precision vs plain at stated error"
-STORAGE_FLAGS = {"fp64": 0, "fp32": 0x2, "bf16": 0x4, "moments": 0x8}
-STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2}
+STORAGE_FLAGS = {"fp64": 0, "fp32": 0x2, "bf16": 0x4, "moments": 0x8, "fp32d": 0x2 | 0x400}
+STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp32d": 4}
 
 
 def bytes_per_node(q: int, storage: str) -> int:
@@ -38,9 +38,13 @@ def bytes_per_node(q: int, storage: str) -> int:
     return 2 * 6 * 8 if storage == "moments" else 2 * q * STORAGE_BYTES[storage]
 
 
-def kernel_source_hash() -> str:
+def kernel_source_hash(unit: str = "step2d.hip") -> str:
+    """Hash of one kernel unit's source and the headers it includes (a
+    counter summary is valid only while they are unchanged)."""
+    from paper_1704_04413_amd import build
+
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1704_04413_amd", "csrc", "*"))):
+    for p in sorted(build._deps(unit)):
         with open(p, "rb") as f:
             h.update(os.path.basename(p).encode())
             h.update(f.read())
@@ -70,8 +74,7 @@ def read_traffic(name: str):
 # Turning rocprofv3 output into the summaries under profiles/ (runs on any
 # host, after the profiled runs on the GPU).
 
-PROFILE_RUN = ("python3 bench.py --steps 20 --warmup 2 --no-cpu-baseline --no-sweep --no-batch --no-3d --no-studies "
-               "--closure none")
+PROFILE_RUN = "python3 bench.py --steps 20 --warmup 2 --only-headline"
 
 
 def _pmc_per_kernel(csv_dir: str, counter: str):
@@ -157,7 +160,7 @@ def summarize_trace(args) -> str:
     out = [f"# rocprofv3 kernel trace: {args.lattice} {args.storage.upper()} {args.n}x{args.n} shear layer (pull stream-collide)",
            "", "Command (repo root on an MI355X):", "",
            f"    rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o run -- python3 bench.py --steps 50 --warmup 5 "
-           f"--no-cpu-baseline --no-sweep --no-batch --no-3d --no-studies --closure none --lattice {args.lattice} --n {args.n}{flag}",
+           f"--only-headline --lattice {args.lattice} --n {args.n}{flag}",
            "", f"Summary: `python3 bench.py --lattice {args.lattice} --n {args.n}{flag} --summarize-trace <run_results.db> <bench output>`",
            "", "From the `top_kernels` view of the run's database (durations in microseconds):", "",
            "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
@@ -209,16 +212,18 @@ def summarize_trace3d(args) -> str:
     return path
 
 
-def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0):
+def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0, noise=True, coll=0):
+    """The shear-layer workload (noise=False skips the 1e-8 w_i noise, which
+    changes nothing in the timing of a large grid)."""
     q, reach, n_eq, cs2 = b.lbm_lattice_info(lattice)
     u0, tau = wl.shear_layer_params(cs2, n, re)
     rho, ux, uy = wl.shear_layer_fields(n, n, u0)
-    flags = STORAGE_FLAGS[storage] | (b.LBM_THERMAL if thermal else 0)
+    flags = STORAGE_FLAGS[storage] | (b.LBM_THERMAL if thermal else 0) | coll
     theta = np.ones_like(rho) if thermal else None
-    noise = wl.uniform_noise(seed, q, n, n)
-    sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, theta=theta, noise=noise, noise_amp=1e-8,
+    nz = wl.uniform_noise(seed, q, n, n) if noise else None
+    sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, theta=theta, noise=nz, noise_amp=1e-8 if noise else 0.0,
                        flags=flags)
-    return sim, dict(q=q, tau=tau, u0=u0, rho=rho, ux=ux, uy=uy, noise=noise)
+    return sim, dict(q=q, tau=tau, u0=u0, rho=rho, ux=ux, uy=uy, noise=nz)
 
 
 def make_sim3(b, wl, lattice, n, re=1e5, flags=0, seed=0):
@@ -269,6 +274,42 @@ def time_steps(torch, sim, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     return t1 - t0, e0.elapsed_time(e1) / steps
+
+
+def time_regions(torch, sim, steps, regions=5):
+    """Average launch duration (ms) of each of `regions` timed regions of
+    `steps` launches (HIP events at both ends of each region, on the
+    library's stream); the state keeps evolving between regions."""
+    stream = sim.stream
+    out = []
+    for _ in range(regions):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        sim.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1) / steps)
+    return out
+
+
+def roofline_point(torch, b, wl, lattice, n, storage, steps=100, regions=5, thermal=False, coll=0):
+    """Median-of-regions step time of one workload and its fraction of the
+    8 TB/s HBM peak (algorithmic bytes 2 Q sizeof per node)."""
+    sim, meta = make_sim(b, wl, lattice, n, storage, thermal=thermal, noise=False, coll=coll)
+    sim.step(5)
+    ms = time_regions(torch, sim, steps, regions)
+    bad = int(sim.moments(vorticity=False)["sums"][8])
+    sim.close()
+    med = float(np.median(ms))
+    bpl = bytes_per_node(meta["q"], storage) * n * n
+    gbs = bpl / (med * 1e-3) / 1e9
+    buf = bpl // 2 if storage != "moments" else 6 * 8 * n * n
+    return {"lattice": lattice, "storage": storage, "thermal": thermal,
+            "collision": {0: "RR", 0x10: "PR", 0x20: "BGK"}[coll], "n": n,
+            "buffer_MiB": round(buf / 2 ** 20, 1), "MLUPS": round(n * n / (med * 1e-3) / 1e6, 1),
+            "kernel_ms_median": round(med, 5), "kernel_ms_regions": [round(x, 5) for x in ms],
+            "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": bad}
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
@@ -358,9 +399,17 @@ def batched_suite(torch, b, wl, storage="fp32", steps=40):
     }
 
 
-def cpu_baseline(wl, lattice_name, n, steps, seed=0):
-    """The oracle as it stands, timed on the host cores on `steps` steps of
-    the full grid (MLUPS)."""
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(wl, lattice_name, n, steps, seed=0):
     import oracle as orc
 
     lat = orc.lattice(lattice_name)
@@ -371,8 +420,26 @@ def cpu_baseline(wl, lattice_name, n, steps, seed=0):
     t0 = time.perf_counter()
     orc.step(lat, f, tau, steps)
     dt = time.perf_counter() - t0
-    return dict(value=round(n * n * steps / dt / 1e6, 4), unit="MLUPS", cores=orc.threads(), kind="oracle",
-                sample=f"{steps} steps of the {lattice_name} {n}x{n} FP64 RR shear layer ({dt:.1f} s)")
+    return n * n * steps / dt / 1e6, dt, orc.threads()
+
+
+def cpu_baseline(wl, lattice_name, n, steps, steps_1t=2, seed=0):
+    """The oracle as it stands, timed on the host cores on `steps` steps of
+    the full grid (MLUPS), and on one thread (a child process with
+    OMP_NUM_THREADS=1) on `steps_1t` steps."""
+    import subprocess
+
+    mlups, dt, threads = _oracle_rate(wl, lattice_name, n, steps, seed)
+    code = (f"import sys; sys.path.insert(0, {ROOT!r}); import bench; from paper_1704_04413_amd import workloads as wl; "
+            f"r = bench._oracle_rate(wl, {lattice_name!r}, {n}, {steps_1t}); print(r[0], r[1], r[2])")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    one = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, check=True)
+    m1, dt1, th1 = one.stdout.split()[-3:]
+    return dict(value=round(mlups, 4), unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{steps} steps of the {lattice_name} {n}x{n} FP64 RR shear layer ({dt:.1f} s)",
+                cpu_model=cpu_model(), host_cpus=os.cpu_count(),
+                one_thread={"value": round(float(m1), 4), "unit": "MLUPS", "threads": int(th1),
+                            "sample": f"{steps_1t} steps of the same grid ({float(dt1):.1f} s)"})
 
 
 def main():
@@ -396,6 +463,12 @@ def main():
     ap.add_argument("--no-studies", action="store_true", help="skip the precision, Sod and stability studies")
     ap.add_argument("--closure", choices=["full", "small", "none"], default="full",
                     help="learned-closure study: D2V37 256^2 coarse / 1024^2 fine (full) or 64^2 / 256^2")
+    ap.add_argument("--only-headline", action="store_true",
+                    help="time the headline workload only (no sweeps, studies, closure or CPU baseline)")
+    ap.add_argument("--no-hbm-points", action="store_true",
+                    help="skip the out-of-cache roofline points (buffers of 0.5-1.2 GB)")
+    ap.add_argument("--regions", type=int, default=5, help="timed regions for the median step time")
+    ap.add_argument("--region-steps", type=int, default=200, help="steps per region of the median step time")
     ap.add_argument("--copy-only", action="store_true", help="only run 1 GiB device copies (counter calibration)")
     ap.add_argument("--summarize-pmc", nargs=4, metavar="DIR",
                     help="write the traffic summary from rocprofv3 --pmc csv dirs: step FETCH_SIZE, step WRITE_SIZE, "
@@ -441,9 +514,18 @@ def main():
                                                   only=only)}), flush=True)
         return
 
+    if args.only_headline:
+        args.no_sweep = args.no_batch = args.no_3d = args.no_studies = args.no_cpu_baseline = True
+        args.no_hbm_points = True
+        args.closure = "none"
+        args.regions = 0
+
     sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage)
     wall, kms = time_steps(torch, sim, args.steps, args.warmup)
+    med = time_regions(torch, sim, args.region_steps, args.regions) if args.regions > 0 else []
     mom = sim.moments()
+    buffer_mib = b.lbm_buffer_elems(args.lattice, args.n, args.n, STORAGE_FLAGS[args.storage]) * \
+        (8 if args.storage in ("fp64", "moments") else STORAGE_BYTES[args.storage]) / 2 ** 20
     sim.close()
     nodes = args.n * args.n
     mlups = nodes * args.steps / wall / 1e6
@@ -480,24 +562,64 @@ def main():
             "traffic": traffic,
             "bytes_per_launch": bytes_per_launch,
             "kernel_ms_avg": round(kms, 5),
+            "buffer_MiB": round(buffer_mib, 1),
+            "memory": ("cache-assisted: the state buffer is within the 256-320 MiB band where the step keeps "
+                       "what it writes in the 256 MiB memory-side cache (the out-of-cache point is "
+                       "roofline_out_of_cache)") if 256 < buffer_mib <= 320 else
+                      ("cache-resident" if buffer_mib <= 256 else "out of cache"),
         },
         "nonfinite_nodes": int(mom["sums"][8]),
     }
+    if med:
+        mk = float(np.median(med))
+        out["median_of_regions"] = {
+            "regions": len(med), "steps_per_region": args.region_steps,
+            "kernel_ms_regions": [round(x, 5) for x in med], "kernel_ms_median": round(mk, 5),
+            "MLUPS": round(nodes / (mk * 1e-3) / 1e6, 1),
+            "frac_hbm": round(bytes_per_launch / (mk * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if not args.no_hbm_points:
+        # the same step with state buffers of 0.5-1.2 GB, far above the 256 MiB
+        # memory-side cache: these fractions are HBM bandwidth
+        pt = roofline_point(torch, b, wl, "D2V37", 2048, "fp64")
+        pt["traffic"] = read_traffic("d2v37_fp64_2048_traffic.txt")
+        out["roofline_out_of_cache"] = pt
+        cases = [("D2Q9", 4096, "fp64", False, 0), ("D2V17", 2048, "fp64", False, 0),
+                 ("D2V37", 2048, "fp64", True, 0), ("D2V37", 2048, "fp64", False, 0x20),
+                 ("D2V37", 2048, "fp64", False, 0x10), ("D2Q9", 4096, "fp32", False, 0),
+                 ("D2V17", 3072, "fp32", False, 0), ("D2V37", 2048, "fp32", False, 0),
+                 ("D2V37", 2048, "fp32d", False, 0),
+                 ("D2V37", 4096, "bf16", False, 0), ("D2Q9", 4096, "moments", False, 0),
+                 ("D2V17", 4096, "moments", False, 0), ("D2V37", 4096, "moments", False, 0)]
+        out["per_lattice_hbm"] = [roofline_point(torch, b, wl, lat, n, st, steps=50, thermal=th, coll=co)
+                                  for lat, n, st, th, co in cases]
     if not args.no_sweep:
+        # 1024^2: buffers of 37-310 MB, inside or about the size of the 256 MiB
+        # memory-side cache, so these are MLUPS only (no HBM fraction); the
+        # BGK and PR lines give the cost of the regularization on the GPU
         sweep = []
-        cases = [("D2Q9", "fp64", False), ("D2V17", "fp64", False), ("D2V37", "fp64", False),
-                 ("D2V37", "fp64", True), ("D2Q9", "fp32", False), ("D2V17", "fp32", False),
-                 ("D2V37", "fp32", False), ("D2V37", "bf16", False), ("D2Q9", "moments", False),
-                 ("D2V17", "moments", False), ("D2V37", "moments", False)]
-        for lat, st, th in cases:
-            s2, m2 = make_sim(b, wl, lat, args.n, st, thermal=th)
-            w2, k2 = time_steps(torch, s2, 50, 5)
+        cases = [("D2Q9", "fp64", False, 0), ("D2V17", "fp64", False, 0), ("D2V37", "fp64", False, 0),
+                 ("D2Q9", "fp64", False, 0x20), ("D2V17", "fp64", False, 0x20), ("D2V37", "fp64", False, 0x20),
+                 ("D2Q9", "fp64", False, 0x10), ("D2V17", "fp64", False, 0x10), ("D2V37", "fp64", False, 0x10),
+                 ("D2V37", "fp64", True, 0), ("D2Q9", "fp32", False, 0), ("D2V17", "fp32", False, 0),
+                 ("D2V37", "fp32", False, 0), ("D2V37", "fp32d", False, 0), ("D2V37", "bf16", False, 0),
+                 ("D2Q9", "moments", False, 0),
+                 ("D2V17", "moments", False, 0), ("D2V37", "moments", False, 0)]
+        for lat, st, th, co in cases:
+            s2, m2 = make_sim(b, wl, lat, args.n, st, thermal=th, coll=co, noise=False)
+            s2.step(5)
+            k2 = float(np.median(time_regions(torch, s2, 50, 3)))
             s2.close()
-            bpl = bytes_per_node(m2["q"], st) * nodes
-            gbs = bpl / (k2 * 1e-3) / 1e9
-            sweep.append({"lattice": lat, "storage": st, "thermal": th, "MLUPS": round(nodes * 50 / w2 / 1e6, 1),
-                          "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+            sweep.append({"lattice": lat, "storage": st, "thermal": th,
+                          "collision": {0: "RR", 0x10: "PR", 0x20: "BGK"}[co],
+                          "MLUPS": round(nodes / (k2 * 1e-3) / 1e6, 1), "memory": "cache-resident or cache-assisted"})
+        rr = {(r["lattice"]): r["MLUPS"] for r in sweep if r["storage"] == "fp64" and r["collision"] == "RR"
+              and not r["thermal"]}
+        ratios = {}
+        for r in sweep:
+            if r["storage"] == "fp64" and not r["thermal"] and r["collision"] != "RR":
+                ratios[f"{r['lattice']} t_RR/t_{r['collision']}"] = round(r["MLUPS"] / rr[r["lattice"]], 3)
         out["per_lattice"] = sweep
+        out["cost_ratios_1024"] = ratios
         out["copy_GBs"] = round(copy_bandwidth(torch), 1)
     if not args.no_3d:
         out["lattices_3d"] = suite_3d(torch, b, wl, n=args.n3)

@@ -40,6 +40,9 @@
  *   of these alone (Eq. GenRegCollision, Eq. MalaspinasRecursiveRelation), so
  *   a step rebuilds each pulled population from its source node's moments.
  *   The sequence of states equals that of LBM_STORE_FP64 up to rounding.
+ *   LBM_STORE_FP32 | LBM_MATH_FP64 keeps the float storage of g_i and does
+ *   the collision in double, so each value is rounded to float once per step
+ *   (at the store); batches and the closure do not take it.
  *
  * Environment (read when a context is created; none changes any result)
  *   RRLBM_CACHE_POLICY=0/1/2  forces the cache policy of the step: 0 ordinary
@@ -80,6 +83,7 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_COLL_BGK 0x20u      /* BGK collision (Sec. III.A)                      */
 #define LBM_EQ_INIT_ORDER2 0x100u /* initial f^(0) truncated at Hermite order 2    */
 #define LBM_A13_PROJECTED 0x200u  /* thermal RR: keep the projected a1^(3)         */
+#define LBM_MATH_FP64 0x400u      /* with LBM_STORE_FP32: double arithmetic        */
 
 /* Error codes. */
 #define LBM_OK 0

@@ -26,6 +26,7 @@ LBM_COLL_PR = 0x10
 LBM_COLL_BGK = 0x20
 LBM_EQ_INIT_ORDER2 = 0x100
 LBM_A13_PROJECTED = 0x200
+LBM_MATH_FP64 = 0x400
 LBM_NSUMS = 10
 LBM_NSUMS_3D = 8
 

@@ -41,6 +41,9 @@ const Ops2D& ops2d_1_2();
 const Ops2D& ops2d_2_0();
 const Ops2D& ops2d_2_1();
 const Ops2D& ops2d_2_2();
+const Ops2D& ops2d_0_3();
+const Ops2D& ops2d_1_3();
+const Ops2D& ops2d_2_3();
 const Ops3D& ops3d_3();
 const Ops3D& ops3d_4();
 const Ops3D& ops3d_5();
@@ -58,9 +61,9 @@ hipError_t batch_launch_2(const InstDesc*, const int*, int, int, int, int, int, 
 const Ops2D& ops2d(int lattice, int store)
 {
     using Get = const Ops2D& (*)();
-    static const Get table[3][3] = { { ops2d_0_0, ops2d_0_1, ops2d_0_2 },
-                                     { ops2d_1_0, ops2d_1_1, ops2d_1_2 },
-                                     { ops2d_2_0, ops2d_2_1, ops2d_2_2 } };
+    static const Get table[3][4] = { { ops2d_0_0, ops2d_0_1, ops2d_0_2, ops2d_0_3 },
+                                     { ops2d_1_0, ops2d_1_1, ops2d_1_2, ops2d_1_3 },
+                                     { ops2d_2_0, ops2d_2_1, ops2d_2_2, ops2d_2_3 } };
     return table[lattice][store]();
 }
 
@@ -258,8 +261,10 @@ int validate(int lattice, int nx, int ny, double tau, int reg_order, uint32_t fl
     if (layout_elems(li->q, nx, ny) >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "grid too large");
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_ETAU, "tau must be finite and > 1/2");
     const uint32_t known = LBM_THERMAL | LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS | LBM_COLL_PR |
-                           LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_A13_PROJECTED;
+                           LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_A13_PROJECTED | LBM_MATH_FP64;
     if (flags & ~known) return fail(LBM_EINVAL, "unknown flag bits");
+    if ((flags & LBM_MATH_FP64) && !(flags & LBM_STORE_FP32))
+        return fail(LBM_EINVAL, "LBM_MATH_FP64 goes with LBM_STORE_FP32");
     const uint32_t stores = flags & (LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS);
     if (stores & (stores - 1)) return fail(LBM_EINVAL, "two storage flags");
     if ((flags & LBM_STORE_MOMENTS) && (flags & (LBM_THERMAL | LBM_COLL_PR | LBM_COLL_BGK | LBM_A13_PROJECTED)))
@@ -288,7 +293,7 @@ double neumaier(const double* x, int64_t n, int stride)
 int64_t store_bytes(const lbm_ctx* c)
 {
     if (c->store == ST_MOM) return int64_t(sizeof(double)) * MOM_K * c->nx * c->ny;
-    const int64_t esz = c->store == ST_F32 ? 4 : c->store == ST_BF16 ? 2 : 8;
+    const int64_t esz = (c->store == ST_F32 || c->store == ST_F32D) ? 4 : c->store == ST_BF16 ? 2 : 8;
     return esz * layout_elems(c->q, c->nx, c->ny * c->nz);
 }
 
@@ -383,7 +388,7 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     c->tau4 = tau;
     c->order = (flags & LBM_COLL_BGK) ? 2 : reg_order;
     c->flags = flags;
-    c->store = (flags & LBM_STORE_FP32)      ? ST_F32
+    c->store = (flags & LBM_STORE_FP32)      ? ((flags & LBM_MATH_FP64) ? ST_F32D : ST_F32)
                : (flags & LBM_STORE_BF16)    ? ST_BF16
                : (flags & LBM_STORE_MOMENTS) ? ST_MOM
                                              : ST_F64;
@@ -835,7 +840,8 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, i
         if (c->dim == 3) return fail(LBM_EINVAL, "batch members must be 2D");
         if (c->coll != COLL_RR || c->thermal)
             return fail(LBM_EINVAL, "batch members must use the isothermal recursive regularization");
-        if (c->store == ST_MOM) return fail(LBM_EINVAL, "batch members must store populations");
+        if (c->store == ST_MOM || c->store == ST_F32D)
+            return fail(LBM_EINVAL, "batch members must store FP64, FP32 or BF16 populations with arithmetic of the same width");
         if (c->store != ctxs[0]->store) return fail(LBM_EINVAL, "batch members must share the storage type");
         if (c->stream != ctxs[0]->stream) return fail(LBM_EINVAL, "batch members must share the stream");
         for (int j = 0; j < i; ++j)

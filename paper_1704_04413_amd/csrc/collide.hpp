@@ -75,9 +75,10 @@ __device__ __forceinline__ void raw_moments(const T (&v)[L::Q], T (&s)[5][5])
     });
 }
 
-// out_i = w_i sum_{kx,ky in basis} He_kx(c_x) He_ky(c_y) C[kx][ky].
-template <class L, class T>
-__device__ __forceinline__ void reconstruct(const T (&C)[5][5], T (&out)[L::Q])
+// emit(i, w_i sum_{kx,ky in basis} He_kx(c_x) He_ky(c_y) C[kx][ky]) for every
+// velocity i (i as a compile-time constant), row by row.
+template <class L, class T, class Emit>
+__device__ __forceinline__ void reconstruct_emit(const T (&C)[5][5], Emit&& emit)
 {
     constexpr int R = L::R;
     constexpr double cs2 = L::cs2;
@@ -118,12 +119,19 @@ __device__ __forceinline__ void reconstruct(const T (&C)[5][5], T (&out)[L::Q])
                         }
                     });
                     constexpr double w = L::v.w[ip];
-                    out[ip] = T(w) * (e + o);
-                    if constexpr (cx != 0) out[im] = T(w) * (e - o);
+                    emit(std::integral_constant<int, ip>{}, T(w) * (e + o));
+                    if constexpr (cx != 0) emit(std::integral_constant<int, im>{}, T(w) * (e - o));
                 }
             });
         });
     });
+}
+
+// out_i = w_i sum_{kx,ky in basis} He_kx(c_x) He_ky(c_y) C[kx][ky].
+template <class L, class T>
+__device__ __forceinline__ void reconstruct(const T (&C)[5][5], T (&out)[L::Q])
+{
+    reconstruct_emit<L, T>(C, [&](auto I, T val) { out[I] = val; });
 }
 
 // Coefficient C[kx][ky] = value / (kx! ky! c_s^2(kx+ky)) restricted to the basis.
@@ -395,9 +403,9 @@ __device__ __forceinline__ void collide_node(T (&v)[L::Q], const Relax& rx)
                 }
             });
         });
-        T eq[L::Q];
-        reconstruct<L, T>(k.C, eq);
-        static_for<L::Q>([&](auto I) { v[I] = keep * v[I] + inv_tau * eq[I]; });
+        // each equilibrium population is folded into its own population as
+        // soon as it is built, so the Q equilibrium values are never all live
+        reconstruct_emit<L, T>(k.C, [&](auto I, T eq) { v[I] = keep * v[I] + inv_tau * eq; });
         inv.restore(v);
         return;
     }

@@ -15,7 +15,9 @@
 
 namespace rr {
 
-enum StoreKind { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_MOM = 3 };
+// Population storage kinds (ST_F32D: FP32 storage with FP64 arithmetic) and
+// the moment representation.
+enum StoreKind { ST_F64 = 0, ST_F32 = 1, ST_BF16 = 2, ST_F32D = 3, ST_MOM = 4 };
 
 struct MlpInfer; // matrix-core weight fragments of the closure network
 
@@ -85,7 +87,7 @@ struct Ops2D {
     // fields (any may be NULL) and per-block sums into `partial` (nblk blocks of MOM_NS)
     hipError_t (*moments)(const lbm_ctx* c, double* r, double* ux, double* uy, double* th, double* partial);
 };
-// lattice LBM_D2Q9..LBM_D2V37, store ST_F64..ST_BF16
+// lattice LBM_D2Q9..LBM_D2V37, store ST_F64..ST_F32D
 const Ops2D& ops2d(int lattice, int store);
 
 // One 3D lattice: the kernels of step3d.hip compiled for it.

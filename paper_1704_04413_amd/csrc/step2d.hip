@@ -1,8 +1,9 @@
 // The 2D population step for one (lattice, storage) pair, chosen at compile
 // time: this file is compiled once per pair (RR_LAT = LBM_D2Q9, LBM_D2V17 or
-// LBM_D2V37; RR_STORE = ST_F64, ST_F32 or ST_BF16), so the pairs build in
-// parallel.  It provides the step launch (every collision, thermal variant and
-// cache policy), the initial state, the population dump and the diagnostics.
+// LBM_D2V37; RR_STORE = ST_F64, ST_F32, ST_BF16 or ST_F32D), so the pairs
+// build in parallel.  It provides the step launch (every collision, thermal
+// variant and cache policy), the initial state, the population dump and the
+// diagnostics.
 #include "context.hpp"
 #include "step2d.hpp"
 
@@ -29,6 +30,8 @@ using Sto = StoreF64;
 using Sto = StoreF32;
 #elif RR_STORE == 2
 using Sto = StoreBF16;
+#elif RR_STORE == 3
+using Sto = StoreF32D;
 #else
 #error "RR_STORE must be a population storage"
 #endif

@@ -39,6 +39,21 @@ struct StoreF32 {
     static __device__ __forceinline__ void store_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
 };
 
+// FP32 storage with double arithmetic: the same weight-shifted floats in HBM,
+// every moment, coefficient and reconstruction in double (the float rounding
+// happens once per value, at the store).
+struct StoreF32D {
+    using elem = float;
+    using math = double;
+    static constexpr bool shifted = true;
+    static constexpr bool conserve_in_double = false;
+    static constexpr bool dithered = false;
+    static __device__ __forceinline__ double load(const float* p) { return double(*p); }
+    static __device__ __forceinline__ double load_nt(const float* p) { return double(__builtin_nontemporal_load(p)); }
+    static __device__ __forceinline__ void store(float* p, double v) { *p = float(v); }
+    static __device__ __forceinline__ void store_nt(float* p, double v) { __builtin_nontemporal_store(float(v), p); }
+};
+
 // bfloat16 = the upper half of an IEEE float.  The initial state is rounded
 // to nearest even; every step rounds stochastically (store_nt_sr): with
 // deterministic rounding a near-uniform region sits at a fixed point of the

@@ -16,7 +16,8 @@ import numpy as np
 from . import binding as b
 from . import workloads as wl
 
-STORE = {"fp64": 0, "fp32": b.LBM_STORE_FP32, "bf16": b.LBM_STORE_BF16}
+STORE = {"fp64": 0, "fp32": b.LBM_STORE_FP32, "bf16": b.LBM_STORE_BF16,
+         "fp32d": b.LBM_STORE_FP32 | b.LBM_MATH_FP64}
 
 
 def _flow_stats(s, n, u0):
@@ -60,10 +61,11 @@ def shear_run(torch, lattice, n, re, storage, steps, every, keep_fields_at=()):
 
 
 def precision_study(torch, lattices=("D2V17", "D2V37"), sizes=(512, 1024), res=(3e4, 1e5, 1e6), steps=10000,
-                    every=500):
-    """FP32 and BF16 weight-shifted storage against the FP64 plain form:
-    blow-up steps, velocity relative L2 error at the last common checkpoint,
-    largest relative deviation of the KE / enstrophy means."""
+                    every=500, storages=("fp32", "fp32d", "bf16")):
+    """Weight-shifted storage (FP32 with float or double arithmetic, BF16)
+    against the FP64 plain form: blow-up steps, velocity relative L2 error at
+    the last common checkpoint, largest relative deviation of the KE /
+    enstrophy means."""
     out = []
     t0 = time.perf_counter()
     for lat in lattices:
@@ -71,7 +73,7 @@ def precision_study(torch, lattices=("D2V17", "D2V37"), sizes=(512, 1024), res=(
             for re in res:
                 ref, fref = shear_run(torch, lat, n, re, "fp64", steps, every, keep_fields_at=range(0, steps + 1, every))
                 row = dict(lattice=lat, n=n, re=re, tau=ref["tau"], blow_up_fp64=ref["blow_up_step"])
-                for st in ("fp32", "bf16"):
+                for st in storages:
                     r, f = shear_run(torch, lat, n, re, st, steps, every, keep_fields_at=range(0, steps + 1, every))
                     common = sorted(set(fref) & set(f))
                     k = common[-1]

@@ -121,9 +121,19 @@ def test_adam_step_and_training(env):
     grad = torch.zeros(mlp.NPARAM, dtype=torch.float32, device="cuda")
     l0 = b.lbm_mlp_step(m, xg, tg, None, n, 1e-3, grad, want_loss=True)
     g = grad.cpu().numpy().astype(np.float64)
-    want, _, _ = mlp.adam(th, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
+    want, mo, vo = mlp.adam(th, g, np.zeros_like(g), np.zeros_like(g), 1, 1e-3)
     got = theta.cpu().numpy().astype(np.float64)
     np.testing.assert_allclose(got, want, rtol=1e-5, atol=1e-7)
+    # steps 2..5: the oracle's Adam fed the GPU's gradient of each step (the
+    # moments and bias corrections now depend on the betas and on t)
+    for t, lr in zip(range(2, 6), (1e-3, 5e-4, 2e-3, 1e-3)):
+        b.lbm_mlp_step(m, xg, tg, None, n, lr, grad, want_loss=False)
+        g = grad.cpu().numpy().astype(np.float64)
+        want, mo, vo = mlp.adam(want, g, mo, vo, t, lr)
+        got = theta.cpu().numpy().astype(np.float64)
+        err = np.abs(got - want).max()
+        print(f"[parity] adam step {t}: max |dtheta| {err:.3e}", flush=True)
+        np.testing.assert_allclose(got, want, rtol=1e-5, atol=2e-7)
     for _ in range(300):
         loss = b.lbm_mlp_step(m, xg, tg, None, n, 2e-3, None, want_loss=False)
     loss = b.lbm_mlp_step(m, xg, tg, None, n, 0.0, None, want_loss=True)

@@ -3,7 +3,8 @@ the FP64 oracle, and the D2Q9 128^2 shear layer run to 2000 steps.
 
 Bounds:
   * FP32 storage: every stored value carries a relative rounding of 2^-24 per
-    step and the float arithmetic adds a few more.  Mass and momentum are
+    step and the float arithmetic adds a few more (with double arithmetic,
+    LBM_MATH_FP64, only the store rounds: bound 5e-7).  Mass and momentum are
     restored from double sums at every node, so what accumulates is rounding
     noise, not a drift: measured 1.0e-7 .. 2.5e-7 relative L2 after 300 steps;
     bound 1e-6 (a float-summed restore gives a few 1e-6, no restore 1e-5).
@@ -36,7 +37,7 @@ def rel_l2(ax, ay, bx, by):
 
 
 @pytest.mark.parametrize("name", ["D2Q9", "D2V17", "D2V37"])
-@pytest.mark.parametrize("storage,bound", [("fp32", 1e-6), ("bf16", 2e-2)])
+@pytest.mark.parametrize("storage,bound", [("fp32", 1e-6), ("fp32d", 5e-7), ("bf16", 2e-2)])
 def test_shifted_storage_velocity_error(orc, b, name, storage, bound):
     steps, n = 300, 64
     print(f"[case] {storage} {name} {n}^2 x {steps}", flush=True)
@@ -44,7 +45,7 @@ def test_shifted_storage_velocity_error(orc, b, name, storage, bound):
     u0, tau = wl.shear_layer_params(lat.cs2, n, 1e4)
     rho, ux, uy = wl.shear_layer_fields(n, n, u0)
     noise = wl.uniform_noise(2, lat.Q, n, n)
-    flags = b.LBM_STORE_FP32 if storage == "fp32" else b.LBM_STORE_BF16
+    flags = {"fp32": b.LBM_STORE_FP32, "fp32d": b.LBM_STORE_FP32 | b.LBM_MATH_FP64, "bf16": b.LBM_STORE_BF16}[storage]
     sim = b.Simulation(name, n, n, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, flags=flags)
     sim.step(steps)
     m = sim.moments()
@@ -113,7 +114,8 @@ def test_config0_d2q9_128_2000_steps(orc, b):
 
 
 @pytest.mark.parametrize("name", ["D2Q9", "D2V17", "D2V37"])
-def test_fp32_uniform_flow_keeps_mass_and_momentum(b, name):
+@pytest.mark.parametrize("math64", [False, True])
+def test_fp32_uniform_flow_keeps_mass_and_momentum(b, name, math64):
     """A uniform flow is a fixed point of the collision.  Float constants make
     a float rebuild return rho u (1 + eps) with eps ~ 2e-8, the same at every
     node and step (6e-5 after 3000 steps), and a restore towards float-summed
@@ -128,8 +130,9 @@ def test_fp32_uniform_flow_keeps_mass_and_momentum(b, name):
     u0 = 0.1 * np.sqrt(cs2)
     rho = np.ones((n, n))
     ux, uy = np.full((n, n), u0), np.full((n, n), 0.3 * u0)
-    print(f"[case] fp32 uniform flow {name} {n}^2 x {steps}", flush=True)
-    sim = b.Simulation(name, n, n, 0.5005, rho, ux, uy, flags=b.LBM_STORE_FP32)
+    print(f"[case] fp32 uniform flow {name} {n}^2 x {steps} double arithmetic={math64}", flush=True)
+    sim = b.Simulation(name, n, n, 0.5005, rho, ux, uy,
+                       flags=b.LBM_STORE_FP32 | (b.LBM_MATH_FP64 if math64 else 0))
     s0 = sim.moments(vorticity=False)["sums"].copy()
     sim.step(steps)
     s1 = sim.moments(vorticity=False)["sums"]
@@ -137,7 +140,8 @@ def test_fp32_uniform_flow_keeps_mass_and_momentum(b, name):
     torch.cuda.synchronize()
     dm = abs(s1[0] - s0[0]) / s0[0]
     dj = max(abs(s1[1] - s0[1]) / abs(s0[1]), abs(s1[2] - s0[2]) / abs(s0[2]))
-    print(f"[precision] fp32 uniform {name}: mass {dm:.2e}, momentum {dj:.2e}", flush=True)
+    print(f"[precision] fp32 uniform {name} double arithmetic={math64}: mass {dm:.2e}, momentum {dj:.2e}",
+          flush=True)
     assert s1[8] == 0
     assert dm <= 2e-8
     assert dj <= 2e-7
