@@ -631,6 +631,11 @@ def main():
         out["precision"] = studies.precision_study(torch)
         out["sod"] = studies.sod_study(torch)
         out["stability"] = studies.stability_range(torch)
+        out["re3e4_study"] = studies.comparison_study(torch)
+        machs = [round(0.40 + 0.01 * k, 2) for k in range(36)]
+        out["stability_scan_d2v37"] = [
+            studies.stability_scan(torch, "D2V37", [("RR", 2), ("RR", 3), ("RR", 4), ("PR", 4)], re, machs)
+            for re in (3e5, 1e6)]
     if args.closure != "none":
         from paper_1704_04413_amd import closure as cl
 

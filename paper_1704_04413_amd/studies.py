@@ -254,3 +254,153 @@ def stability_range(torch, res=(1e4, 3e4, 1e5, 3e5, 1e6), n=128, noneq_start=Tru
     return dict(n=n, criterion="<u^2>(t) < <u^2>(0) for t <= 2 n/(M0 c_s), no non-finite node",
                 start="f0+f1" if noneq_start else "f0", resolution=0.01, rows=rows,
                 seconds=round(time.perf_counter() - t0, 1))
+
+
+# ---- the Re = 3e4 comparison of Sec. III.B (Figs. 2-4) ---------------------
+
+PAPER_MACH = {"D2Q9": 0.2, "D2V17": 0.35, "D2V37": 0.57}
+
+
+def shear_history(torch, lattice, n, re, mach, coll, order, samples_per_tc=40, horizon_tc=2.0, noise_seed=0):
+    """One run of the doubly periodic shear layer started from f^(0) + f^(1)
+    (analytic gradients, Sec. III.B): the spatial mean and standard deviation
+    of the kinetic energy and of the enstrophy at t = k t_c / samples_per_tc
+    (nearest step), k = 0 .. horizon_tc * samples_per_tc, t_c = n / u0; the
+    first sample where the paper's stability criterion fails (<|u|^2>(t) >=
+    <|u|^2>(0), or a non-finite node), and the first where the run has
+    blown up (a non-finite node, or <|u|^2> above twice its initial value).
+    The run continues past a failed criterion until it blows up."""
+    q, _, _, cs2 = b.lbm_lattice_info(lattice)
+    u0, tau = wl.shear_layer_params(cs2, n, re, mach)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    grad = wl.shear_layer_gradients(n, n, u0)
+    sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, noise=wl.uniform_noise(noise_seed, q, n, n),
+                       noise_amp=1e-8, reg_order=order, flags=COLLISIONS[coll], grad=grad)
+    tc = n / u0
+    nsamp = int(round(horizon_tc * samples_per_tc))
+    marks = [int(round(k * tc / samples_per_tc)) for k in range(nsamp + 1)]
+    hist, fail, blow, u2_0, u2max = [], None, None, None, 0.0
+    for k, step in enumerate(marks):
+        sim.step(step - sim.steps)
+        s = sim.moments(vorticity=True)["sums"]
+        u2 = s[4]
+        u2_0 = u2 if u2_0 is None else u2_0
+        if s[8] > 0 or not np.isfinite(u2) or u2 > 2.0 * u2_0:
+            blow = k
+            fail = k if fail is None else fail
+            break
+        if fail is None and k > 0 and u2 >= u2_0:
+            fail = k
+        u2max = max(u2max, u2 / u2_0)
+        hist.append(_flow_stats(s, n, u0))
+    sim.close()
+    return dict(t_over_tc=[k / samples_per_tc for k in range(len(hist))], stats=np.array(hist),
+                samples_per_tc=samples_per_tc, unstable_at=None if fail is None else fail / samples_per_tc,
+                blow_up_at=None if blow is None else blow / samples_per_tc, max_u2_ratio=u2max, tau=tau, u0=u0)
+
+
+def _history_error(run, ref):
+    """max_t |X - X_ref| / max_t |X_ref| for X = KE mean, KE std, enstrophy
+    mean, enstrophy std, over the samples both runs reached before either
+    failed the stability criterion."""
+    m = min(len(run["stats"]), len(ref["stats"]))
+    for r in (run, ref):
+        if r["unstable_at"] is not None:
+            m = min(m, int(round(r["unstable_at"] * r["samples_per_tc"])))
+    if m == 0:
+        return None
+    a, r = run["stats"][:m], ref["stats"][:m]
+    scale = np.abs(ref["stats"]).max(axis=0)
+    e = np.abs(a - r).max(axis=0) / scale
+    return dict(zip(("ke_mean", "ke_std", "ens_mean", "ens_std"), (round(float(x), 5) for x in e)))
+
+
+def comparison_study(torch, re=3e4, sizes=(128, 256), ref_n=2048, convergence=(512, 1024), samples_per_tc=40):
+    """The Re = 3e4 study of Figs. 2-4: BGK, PR and RR at every order 2..N_eq
+    on D2Q9 (M0 0.2), D2V17 (0.35) and D2V37 (0.57), on L^2 grids for L in
+    `sizes`, against a BGK reference on ref_n^2 (per lattice; RR at full order
+    on the same grid where BGK blows up before 2 t_c), up to 2 t_c;
+    plus the mesh convergence of RR at full order.  Reports, per run, where
+    the stability criterion failed (t/t_c) and the largest deviation of the
+    four statistics from the reference over the common samples, relative to
+    the reference's largest value."""
+    out = []
+    t0 = time.perf_counter()
+    for lat, mach in PAPER_MACH.items():
+        n_eq = b.lbm_lattice_info(lat)[2]
+        ref = shear_history(torch, lat, ref_n, re, mach, "BGK", 2, samples_per_tc)
+        ref_coll, bgk_ref_blow = "BGK", ref["blow_up_at"]
+        if ref["blow_up_at"] is not None:
+            # the BGK reference did not last 2 t_c: RR at full order on the same grid instead
+            ref = shear_history(torch, lat, ref_n, re, mach, "RR", n_eq, samples_per_tc)
+            ref_coll = f"RR{n_eq}"
+        rows = []
+        variants = [("BGK", 2)] + [("PR", k) for k in range(2, n_eq + 1)] + [("RR", k) for k in range(2, n_eq + 1)]
+        for n in sizes:
+            for coll, order in variants:
+                run = shear_history(torch, lat, n, re, mach, coll, order, samples_per_tc)
+                rows.append(dict(n=n, collision=coll, order=order if coll != "BGK" else None,
+                                 tau=run["tau"], unstable_at_t_over_tc=run["unstable_at"],
+                                 blow_up_at_t_over_tc=run["blow_up_at"],
+                                 max_u2_over_initial=round(run["max_u2_ratio"], 6),
+                                 error_vs_ref=_history_error(run, ref)))
+        conv = []
+        for n in tuple(sizes) + tuple(convergence):
+            run = shear_history(torch, lat, n, re, mach, "RR", n_eq, samples_per_tc)
+            conv.append(dict(n=n, unstable_at_t_over_tc=run["unstable_at"], blow_up_at_t_over_tc=run["blow_up_at"],
+                             max_u2_over_initial=round(run["max_u2_ratio"], 6), error_vs_ref=_history_error(run, ref)))
+        samples = list(range(0, 2 * samples_per_tc + 1, samples_per_tc // 4))
+        out.append(dict(lattice=lat, mach=mach, re=re, reference=dict(
+            n=ref_n, collision=ref_coll, bgk_blow_up_at_t_over_tc=bgk_ref_blow,
+            unstable_at_t_over_tc=ref["unstable_at"], blow_up_at_t_over_tc=ref["blow_up_at"],
+            max_u2_over_initial=round(ref["max_u2_ratio"], 6),
+            at_t_over_tc=[ref["t_over_tc"][k] for k in samples if k < len(ref["stats"])],
+            ke_mean=[round(float(ref["stats"][k, 0]), 6) for k in samples if k < len(ref["stats"])],
+            ke_std=[round(float(ref["stats"][k, 1]), 6) for k in samples if k < len(ref["stats"])],
+            ens_mean=[round(float(ref["stats"][k, 2]), 4) for k in samples if k < len(ref["stats"])],
+            ens_std=[round(float(ref["stats"][k, 3]), 4) for k in samples if k < len(ref["stats"])]),
+            runs=rows, rr_convergence=conv))
+    return dict(criterion="<u^2>(t) < <u^2>(0) for t <= 2 t_c, no non-finite node",
+                blow_up="a non-finite node or <u^2>(t) > 2 <u^2>(0); runs continue past the criterion until then",
+                start="f0 + f1 (analytic gradients), f0 at the lattice's full order", samples_per_tc=samples_per_tc,
+                error="max_t |X - X_ref| / max_t |X_ref| over the samples both runs reached", lattices=out,
+                seconds=round(time.perf_counter() - t0, 1))
+
+
+def stability_scan(torch, lattice, variants, re, machs, n=128, every=1):
+    """Stable or not (Sec. III.B criterion, checked every `every` steps) for
+    each M0 of a grid, and the t/t_c where a run fails: shows whether the
+    stable set is an interval [0, M0max] as bisection assumes."""
+    rows = []
+    for coll, order in variants:
+        res, blows, peaks = [], [], []
+        for m in machs:
+            q, _, _, cs2 = b.lbm_lattice_info(lattice)
+            u0, tau = wl.shear_layer_params(cs2, n, re, m)
+            rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+            sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, noise=wl.uniform_noise(0, q, n, n), noise_amp=1e-8,
+                               reg_order=order, flags=COLLISIONS[coll], grad=wl.shear_layer_gradients(n, n, u0))
+            horizon = int(np.ceil(2.0 * n / u0))
+            u2_0, fail, blow, u2max = None, None, None, 0.0
+            while True:
+                s = sim.moments(vorticity=False)["sums"]
+                u2 = s[4]
+                u2_0 = u2 if u2_0 is None else u2_0
+                if s[8] > 0 or not np.isfinite(u2) or u2 > 2.0 * u2_0:
+                    blow = sim.steps
+                    fail = sim.steps if fail is None else fail
+                    break
+                if fail is None and sim.steps > 0 and u2 >= u2_0:
+                    fail = sim.steps
+                u2max = max(u2max, u2 / u2_0)
+                if sim.steps >= horizon:
+                    break
+                sim.step(min(every, horizon - sim.steps))
+            sim.close()
+            res.append(None if fail is None else round(fail * u0 / n, 4))
+            blows.append(None if blow is None else round(blow * u0 / n, 4))
+            peaks.append(round(u2max, 6))
+        rows.append(dict(collision=coll, order=order, unstable_at_t_over_tc=res, blow_up_at_t_over_tc=blows,
+                         max_u2_over_initial=peaks))
+    return dict(lattice=lattice, re=re, n=n, every=every, machs=[round(m, 4) for m in machs], rows=rows,
+                blow_up="a non-finite node or <u^2>(t) > 2 <u^2>(0) before 2 t_c")
