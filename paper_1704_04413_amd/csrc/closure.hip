@@ -14,15 +14,29 @@ using namespace rr;
 
 namespace rr {
 
+namespace {
+
+template <class S>
+void closure_launch(const lbm_ctx* c, const StepArgs& a, const ClosureArgs& ca)
+{
+    const dim3 grid(unsigned(a.nblocks)), block(BX, BY);
+    switch (c->pol) {
+    case POL_CACHE: k_stream_collide_closure<S, POL_CACHE><<<grid, block, 0, c->stream>>>(a, ca); break;
+    case POL_KEEP: k_stream_collide_closure<S, POL_KEEP><<<grid, block, 0, c->stream>>>(a, ca); break;
+    default: k_stream_collide_closure<S, POL_STREAM><<<grid, block, 0, c->stream>>>(a, ca); break;
+    }
+}
+
+} // namespace
+
 hipError_t closure_step(const lbm_ctx* c, const void* fin, void* fout)
 {
     const StepArgs a = step_args(c, fin, fout, true);
-    const dim3 grid(unsigned(a.nblocks)), block(BX, BY);
     const ClosureArgs ca{ c->cl_frags, c->cl_norm, 1.0 - 0.5 / c->tau, c->cl_fallbacks };
     switch (c->store) {
-    case ST_F32: k_stream_collide_closure<StoreF32><<<grid, block, 0, c->stream>>>(a, ca); break;
-    case ST_BF16: k_stream_collide_closure<StoreBF16><<<grid, block, 0, c->stream>>>(a, ca); break;
-    default: k_stream_collide_closure<StoreF64><<<grid, block, 0, c->stream>>>(a, ca); break;
+    case ST_F32: closure_launch<StoreF32>(c, a, ca); break;
+    case ST_BF16: closure_launch<StoreBF16>(c, a, ca); break;
+    default: closure_launch<StoreF64>(c, a, ca); break;
     }
     return hipGetLastError();
 }
