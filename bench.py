@@ -640,7 +640,9 @@ def main():
         from paper_1704_04413_amd import closure as cl
 
         if args.closure == "full":
-            out["closure"] = cl.experiment(torch)
+            # the paper's D2V37 Mach (Fig. 4), where ranks 3-4 carry weight, and the workload's Mach 0.1
+            out["closure"] = cl.experiment(torch, snaps=tuple(range(100, 1001, 100)), mach=0.57)
+            out["closure_mach01"] = cl.experiment(torch)
         else:
             out["closure"] = cl.experiment(torch, range(6), range(6, 8), 64, 4, 3e4, tuple(range(50, 401, 50)),
                                            1500, 8192)

@@ -47,28 +47,42 @@ def init_theta(seed: int) -> np.ndarray:
     return th
 
 
-def generate_samples(torch, seeds, n_coarse=256, factor=4, re=3e4, snaps=tuple(range(150, 1501, 150))):
+def _stats(sums, n, u0):
+    """Mean kinetic energy |u|^2 / (2 u0^2) and mean enstrophy omega^2 (n/u0)^2 / 2
+    from the library's sums (Sec. III.B diagnostics)."""
+    return 0.5 * sums[4] / (n * n) / u0 ** 2, 0.5 * (n / u0) ** 2 * sums[6] / (n * n)
+
+
+def generate_samples(torch, seeds, n_coarse=256, factor=4, re=3e4, snaps=tuple(range(150, 1501, 150)), mach=0.1):
     """Runs the plain method on the fine grid for each seed and restricts it
     at coarse steps `snaps`.  Returns raw x [N, 8], r [N, 16] (device
-    float32), the per-snapshot restricted velocities and timing."""
-    u0, tau_f, _ = grid_params(n_coarse, factor, re)
+    float32), the per-snapshot restricted velocities with the fine run's
+    mean kinetic energy and enstrophy, and timing."""
+    u0, tau_f, _ = grid_params(n_coarse, factor, re, mach)
     nf, nc = n_coarse * factor, n_coarse * n_coarse
     xs, rs, ref = [], [], {}
     t0 = time.perf_counter()
+    dropped = []
     for seed in seeds:
         rho, ux, uy = wl.shear_layer_fields(nf, nf, u0, **flow_of(seed))
         sim = b.Simulation("D2V37", nf, nf, tau_f, rho, ux, uy)
         for k in snaps:
             sim.step(factor * k - sim.steps)
+            sums = sim.moments(vorticity=True)["sums"]
+            if sums[8] > 0:  # the fine run blew up: no samples from here on
+                dropped.append((seed, k))
+                break
             x = torch.empty((nc, 8), dtype=torch.float32, device=sim.device)
             r = torch.empty((nc, 16), dtype=torch.float32, device=sim.device)
             b.lbm_closure_samples(sim.ctx, factor, x, r)
             xs.append(x)
             rs.append(r)
+            ke, ens = _stats(sums, nf, u0)
             ref[(seed, k)] = (x[:, 1].reshape(n_coarse, n_coarse).double().cpu().numpy(),
-                              x[:, 2].reshape(n_coarse, n_coarse).double().cpu().numpy())
+                              x[:, 2].reshape(n_coarse, n_coarse).double().cpu().numpy(), ke, ens)
         sim.close()
     torch.cuda.synchronize()
+    ref["dropped"] = dropped
     return torch.cat(xs), torch.cat(rs), ref, time.perf_counter() - t0
 
 
@@ -126,9 +140,10 @@ def a_priori(torch, theta, norm, x_raw, r_raw):
                 fallback_fraction=float(1.0 - inside.mean()))
 
 
-def coarse_run(torch, seed, snaps, n_coarse=256, factor=4, re=3e4, theta=None, norm=None):
-    """Coarse plain (theta None) or closure run; velocities at `snaps`."""
-    u0, tau_f, tau_c = grid_params(n_coarse, factor, re)
+def coarse_run(torch, seed, snaps, n_coarse=256, factor=4, re=3e4, theta=None, norm=None, mach=0.1):
+    """Coarse plain (theta None) or closure run; velocities, non-finite count,
+    mean kinetic energy and enstrophy at `snaps`."""
+    u0, tau_f, tau_c = grid_params(n_coarse, factor, re, mach)
     rho, ux, uy = wl.shear_layer_fields(n_coarse, n_coarse, u0, **flow_of(seed))
     sim = b.Simulation("D2V37", n_coarse, n_coarse, tau_c, rho, ux, uy)
     if theta is not None:
@@ -136,16 +151,17 @@ def coarse_run(torch, seed, snaps, n_coarse=256, factor=4, re=3e4, theta=None, n
     out = {}
     for k in snaps:
         sim.step(k - sim.steps)
-        mo = sim.moments(vorticity=False)
-        out[k] = (mo["ux"].cpu().numpy(), mo["uy"].cpu().numpy(), int(mo["sums"][8]))
+        mo = sim.moments(vorticity=True)
+        out[k] = (mo["ux"].cpu().numpy(), mo["uy"].cpu().numpy(), int(mo["sums"][8])) + \
+            _stats(mo["sums"], n_coarse, u0)
     fb = b.lbm_closure_fallbacks(sim.ctx) if theta is not None else 0
     sim.close()
     return out, fb
 
 
 def velocity_error(run, ref, seed, k):
-    ux, uy, _ = run[k]
-    rx, ry = ref[(seed, k)]
+    ux, uy = run[k][:2]
+    rx, ry = ref[(seed, k)][:2]
     return float(np.sqrt(np.sum((ux - rx) ** 2 + (uy - ry) ** 2) / np.sum(rx ** 2 + ry ** 2)))
 
 
@@ -169,26 +185,39 @@ def step_rate(torch, n, steps=200, theta=None, norm=None, re=3e4):
 
 
 def experiment(torch, train_seeds=range(16), test_seeds=range(16, 20), n_coarse=256, factor=4, re=3e4,
-               snaps=tuple(range(150, 1501, 150)), steps=4000, batch=16384):
-    """The whole closure study; returns a JSON-ready dict."""
-    x, r, _, t_gen = generate_samples(torch, list(train_seeds), n_coarse, factor, re, snaps)
-    xh, rh, ref, t_gen2 = generate_samples(torch, list(test_seeds), n_coarse, factor, re, snaps)
+               snaps=tuple(range(150, 1501, 150)), steps=4000, batch=16384, mach=0.1):
+    """The whole closure study; returns a JSON-ready dict.  A posteriori, per
+    held-out seed and evaluation step: the coarse velocity's relative L2
+    distance to the restricted fine run (plain and closure) and the signed
+    gain 1 - err_closure / err_plain; the relative errors of the mean
+    kinetic energy and enstrophy against the fine run's own."""
+    x, r, ref_train, t_gen = generate_samples(torch, list(train_seeds), n_coarse, factor, re, snaps, mach)
+    xh, rh, ref, t_gen2 = generate_samples(torch, list(test_seeds), n_coarse, factor, re, snaps, mach)
     n_train = int(x.shape[0])
     theta, norm, log, t_train = train(torch, x, r, steps, batch)
     del x, r
     ap = a_priori(torch, theta, norm, xh, rh)
     post = []
     for seed in test_seeds:
-        plain, _ = coarse_run(torch, seed, snaps, n_coarse, factor, re)
-        clos, fb = coarse_run(torch, seed, snaps, n_coarse, factor, re, theta, norm)
+        plain, _ = coarse_run(torch, seed, snaps, n_coarse, factor, re, mach=mach)
+        clos, fb = coarse_run(torch, seed, snaps, n_coarse, factor, re, theta, norm, mach=mach)
         for k in (snaps[len(snaps) // 2], snaps[-1]):
-            post.append(dict(seed=seed, step=k, err_plain=velocity_error(plain, ref, seed, k),
-                             err_closure=velocity_error(clos, ref, seed, k)))
+            if (seed, k) not in ref:
+                continue
+            ep, ec = velocity_error(plain, ref, seed, k), velocity_error(clos, ref, seed, k)
+            ke_f, ens_f = ref[(seed, k)][2:]
+            post.append(dict(seed=seed, step=k, err_plain=ep, err_closure=ec, gain=1.0 - ec / ep,
+                             ke_err_plain=abs(plain[k][3] / ke_f - 1), ke_err_closure=abs(clos[k][3] / ke_f - 1),
+                             ens_err_plain=abs(plain[k][4] / ens_f - 1), ens_err_closure=abs(clos[k][4] / ens_f - 1),
+                             nonfinite=plain[k][2] + clos[k][2]))
         post[-1]["fallback_nodes"] = fb
+        post[-1]["fallback_fraction"] = fb / float(n_coarse * n_coarse * snaps[-1])
     rates = {f"{n}": dict(plain=round(step_rate(torch, n), 1),
                           closure=round(step_rate(torch, n, theta=theta, norm=norm), 1))
-             for n in (n_coarse, n_coarse * factor)}
+             for n in sorted({n_coarse, n_coarse * factor, 2048})}
     return dict(train_seeds=list(train_seeds), test_seeds=list(test_seeds), n_coarse=n_coarse, factor=factor,
-                re=re, train_samples=n_train, test_samples=int(xh.shape[0]),
+                re=re, mach=mach, train_samples=n_train, test_samples=int(xh.shape[0]),
+                fine_runs_blown_up=dict(train=ref_train["dropped"], test=ref["dropped"]),
+                mean_gain=float(np.mean([p["gain"] for p in post])),
                 seconds=dict(fine_runs=round(t_gen + t_gen2, 2), training=round(t_train, 2)),
                 loss_log=log, a_priori=ap, a_posteriori=post, MLUPS=rates)

@@ -249,11 +249,11 @@ int lbm_closure_set(lbm_ctx* c, const float* theta, const float* norm)
     if (!c->cl_frags) {
         HIP_TRY(hipMalloc(&c->cl_frags, sizeof(MlpInfer)));
         HIP_TRY(hipMalloc(&c->cl_norm, sizeof(float) * NORM_N));
-        HIP_TRY(hipMalloc(&c->cl_fallbacks, sizeof(unsigned long long)));
+        HIP_TRY(hipMalloc(&c->cl_fallbacks, sizeof(unsigned long long) * FALLBACK_SLOTS));
     }
     HIP_TRY(launch_frags(theta, c->cl_frags, nullptr, c->stream));
     HIP_TRY(hipMemcpyAsync(c->cl_norm, norm, sizeof(float) * NORM_N, hipMemcpyDeviceToDevice, c->stream));
-    HIP_TRY(hipMemsetAsync(c->cl_fallbacks, 0, sizeof(unsigned long long), c->stream));
+    HIP_TRY(hipMemsetAsync(c->cl_fallbacks, 0, sizeof(unsigned long long) * FALLBACK_SLOTS, c->stream));
     c->closure = true;
     return LBM_OK;
 }
@@ -265,10 +265,12 @@ int lbm_closure_fallbacks(lbm_ctx* c, int64_t* count)
         *count = 0;
         return LBM_OK;
     }
-    unsigned long long v = 0;
-    HIP_TRY(hipMemcpyAsync(&v, c->cl_fallbacks, sizeof(v), hipMemcpyDeviceToHost, c->stream));
+    unsigned long long v[FALLBACK_SLOTS] = {};
+    HIP_TRY(hipMemcpyAsync(v, c->cl_fallbacks, sizeof(v), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(hipStreamSynchronize(c->stream));
-    *count = int64_t(v);
+    unsigned long long total = 0;
+    for (unsigned long long x : v) total += x;
+    *count = int64_t(total);
     return LBM_OK;
 }
 

@@ -198,11 +198,15 @@ __device__ __forceinline__ void closure_features(const NodeCoeffs<T>& k, T s, fl
     f[6] = float(s * k.a1[0][2]);
 }
 
+// Fallback counters are spread over this many slots (by block) so that waves
+// of different blocks rarely add to the same address.
+constexpr int FALLBACK_SLOTS = 64;
+
 struct ClosureArgs {
     const MlpInfer* frags;
     const float* norm;
     double s;             // 1 - 1/(2 tau)
-    unsigned long long* fallbacks; // running count of nodes that kept the plain recursion
+    unsigned long long* fallbacks; // FALLBACK_SLOTS running counts of nodes that kept the plain recursion
 };
 
 // Register budget of the fused closure step, as the minimum number of waves
@@ -305,7 +309,8 @@ void k_stream_collide_closure(StepArgs a, ClosureArgs c)
         r[o] = yo * snorm[NORM_OUT_STD + o] + snorm[NORM_OUT_MEAN + o];
     }
     const unsigned long long missed = __ballot(valid && !ok);
-    if (lane == 0 && missed) atomicAdd(c.fallbacks, (unsigned long long)__popcll(missed));
+    if (lane == 0 && missed)
+        atomicAdd(c.fallbacks + (blockIdx.x & (FALLBACK_SLOTS - 1)), (unsigned long long)__popcll(missed));
     if (ok) {
         const T inv_s = T(1) / s;
         k.a1[3][0] += T(r[0]) * inv_s;
