@@ -156,12 +156,15 @@ def summarize_trace(args) -> str:
     live = json.loads(line)
     roof = live["roofline"]
     flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
-    name = f"{args.lattice.lower()}_{args.storage}_{args.n}_kernel_trace.md"
-    out = [f"# rocprofv3 kernel trace: {args.lattice} {args.storage.upper()} {args.n}x{args.n} shear layer (pull stream-collide)",
+    mode = "--only-closure" if args.only_closure else "--only-headline"
+    what = "fused closure step" if args.only_closure else "pull stream-collide"
+    name = f"{args.lattice.lower()}_{'closure' if args.only_closure else args.storage}_{args.n}_kernel_trace.md"
+    out = [f"# rocprofv3 kernel trace: {args.lattice} {args.storage.upper()} {args.n}x{args.n} shear layer ({what})",
            "", "Command (repo root on an MI355X):", "",
            f"    rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o run -- python3 bench.py --steps 50 --warmup 5 "
-           f"--only-headline --lattice {args.lattice} --n {args.n}{flag}",
-           "", f"Summary: `python3 bench.py --lattice {args.lattice} --n {args.n}{flag} --summarize-trace <run_results.db> <bench output>`",
+           f"{mode} --lattice {args.lattice} --n {args.n}{flag}",
+           "", f"Summary: `python3 bench.py --lattice {args.lattice} --n {args.n}{flag}{' --only-closure' if args.only_closure else ''} "
+               f"--summarize-trace <run_results.db> <bench output>`",
            "", "From the `top_kernels` view of the run's database (durations in microseconds):", "",
            "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
     for n, c, tot, avg, pct in rows:
@@ -174,6 +177,111 @@ def summarize_trace(args) -> str:
     path = os.path.join(ROOT, "profiles", name)
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
+    return path
+
+
+def _pmc_sums(csv_dir: str, kernel_hint: str):
+    """{counter: mean value per dispatch} for the busiest kernel whose name
+    contains kernel_hint, from one rocprofv3 --pmc csv run."""
+    import csv
+
+    per = {}
+    for path in glob.glob(os.path.join(csv_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if kernel_hint in row["Kernel_Name"]:
+                    per.setdefault((row["Kernel_Name"], row["Counter_Name"]), []).append(float(row["Counter_Value"]))
+    if not per:
+        raise SystemExit(f"no dispatch of a kernel matching {kernel_hint!r} in {csv_dir}")
+    kname = max({k for k, _ in per}, key=lambda k: sum(len(v) for (kk, _), v in per.items() if kk == k))
+    return kname, {c: float(np.mean(v)) for (k, c), v in per.items() if k == kname}
+
+
+def summarize_requests(args) -> str:
+    """Cross-check of the FETCH_SIZE / WRITE_SIZE calibration with request
+    counters: bytes = 128 R128 + 64 R64 + 32 R32 for reads and 64 W64 +
+    32 (W - W64) for writes, for the step kernel and for a 1 GiB device copy
+    (profiles/<lattice>_<storage>_<n>_requests.txt)."""
+    rd_dir, wr_dir, crd_dir, cwr_dir = args.summarize_requests
+    kname, rd = _pmc_sums(rd_dir, "k_stream_collide")
+    _, wr = _pmc_sums(wr_dir, "k_stream_collide")
+    cname, crd = _pmc_sums(crd_dir, "")
+    _, cwr = _pmc_sums(cwr_dir, "")
+
+    def rbytes(d):
+        return 128 * d["TCC_EA0_RDREQ_128B_sum"] + 64 * d["TCC_EA0_RDREQ_64B_sum"] + 32 * d["TCC_EA0_RDREQ_32B_sum"]
+
+    def wbytes(d):
+        return 64 * d["TCC_EA0_WRREQ_64B_sum"] + 32 * (d["TCC_EA0_WRREQ_sum"] - d["TCC_EA0_WRREQ_64B_sum"])
+
+    q = {"D2Q9": 9, "D2V17": 17, "D2V37": 37}[args.lattice]
+    alg = bytes_per_node(q, args.storage) * args.n * args.n
+    gib = float(1 << 30)
+    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    rdc = "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_32B_sum"
+    wrc = "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum"
+    lines = [
+        f"# Request-counter cross-check of HBM traffic: {args.lattice} {args.storage.upper()} {args.n}x{args.n} step",
+        "#",
+        "# Commands (repo root on an MI355X):",
+        f"#   rocprofv3 --pmc {rdc} --output-format csv -d {rd_dir} -o run -- {PROFILE_RUN} --lattice {args.lattice} --n {args.n}{flag}",
+        f"#   rocprofv3 --pmc {wrc} --output-format csv -d {wr_dir} -o run -- {PROFILE_RUN} --lattice {args.lattice} --n {args.n}{flag}",
+        f"#   the same two with -- python3 bench.py --copy-only (dirs {crd_dir}, {cwr_dir})",
+        f"# Summary: python3 bench.py --lattice {args.lattice} --n {args.n}{flag} --summarize-requests {rd_dir} {wr_dir} {crd_dir} {cwr_dir}",
+        "#",
+        f"# copy kernel {cname[:60]}: reads 128B/64B/32B = {crd['TCC_EA0_RDREQ_128B_sum']:.0f}/{crd['TCC_EA0_RDREQ_64B_sum']:.0f}/"
+        f"{crd['TCC_EA0_RDREQ_32B_sum']:.0f} of {crd['TCC_EA0_RDREQ_sum']:.0f} requests -> {rbytes(crd) / gib:.4f} GiB read (1 GiB copied)",
+        f"#   writes 64B {cwr['TCC_EA0_WRREQ_64B_sum']:.0f} of {cwr['TCC_EA0_WRREQ_sum']:.0f} -> {wbytes(cwr) / gib:.4f} GiB written",
+        f"# step kernel: reads 128B/64B/32B = {rd['TCC_EA0_RDREQ_128B_sum']:.0f}/{rd['TCC_EA0_RDREQ_64B_sum']:.0f}/"
+        f"{rd['TCC_EA0_RDREQ_32B_sum']:.0f} of {rd['TCC_EA0_RDREQ_sum']:.0f} requests -> {rbytes(rd) / 1e6:.1f} MB read",
+        f"#   writes 64B {wr['TCC_EA0_WRREQ_64B_sum']:.0f} of {wr['TCC_EA0_WRREQ_sum']:.0f} -> {wbytes(wr) / 1e6:.1f} MB written",
+        f"#   -> measured / algorithmic ({alg / 1e6:.1f} MB) = {(rbytes(rd) + wbytes(wr)) / alg:.4f}",
+        f"kernel: {kname}",
+        f"kernel_source_hash: {kernel_source_hash()}",
+        f"copy_read_over_true: {rbytes(crd) / gib:.6f}",
+        f"copy_write_over_true: {wbytes(cwr) / gib:.6f}",
+        f"read_bytes_per_launch: {rbytes(rd):.0f}",
+        f"write_bytes_per_launch: {wbytes(wr):.0f}",
+        f"hbm_bytes_per_launch: {rbytes(rd) + wbytes(wr):.0f}",
+    ]
+    path = os.path.join(ROOT, "profiles", f"{args.lattice.lower()}_{args.storage}_{args.n}_requests.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
+
+
+def summarize_valu(args) -> str:
+    """VALU instruction mix and busy fraction of the step kernel from one
+    rocprofv3 --pmc run (profiles/<lattice>_<storage>_<n>_valu.txt)."""
+    (vdir,) = args.summarize_valu
+    kname, d = _pmc_sums(vdir, "k_mom_step" if args.storage == "moments" else "k_stream_collide")
+    nodes = args.n * args.n
+    f64 = d["SQ_INSTS_VALU_FMA_F64"] + d["SQ_INSTS_VALU_MUL_F64"] + d["SQ_INSTS_VALU_ADD_F64"]
+    flops = 64 * (2 * d["SQ_INSTS_VALU_FMA_F64"] + d["SQ_INSTS_VALU_MUL_F64"] + d["SQ_INSTS_VALU_ADD_F64"])
+    cus, xccs = 256, 8
+    # SQ_ACTIVE_INST_VALU counts quad-cycles summed over every SIMD; GRBM_GUI_ACTIVE
+    # comes summed over the 8 XCCs: per XCC (the kernel's duration in cycles) is 1/8
+    busy = 100.0 * d["SQ_ACTIVE_INST_VALU"] / cus / (d["GRBM_GUI_ACTIVE"] / xccs)
+    counters = "SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE"
+    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    lines = [
+        f"# VALU profile: {args.lattice} {args.storage} {args.n}x{args.n} step (rocprofv3 PMC)",
+        "#",
+        f"#   rocprofv3 --pmc {counters} --output-format csv -d {vdir} -o run -- {PROFILE_RUN} --lattice {args.lattice} --n {args.n}{flag}",
+        f"# Summary: python3 bench.py --lattice {args.lattice} --n {args.n}{flag} --summarize-valu {vdir}",
+        "#",
+        f"# per node: {d['SQ_INSTS_VALU'] * 64 / nodes:.0f} VALU instructions (lane view), of which FP64 "
+        f"{f64 * 64 / nodes:.0f} (FMA {d['SQ_INSTS_VALU_FMA_F64'] * 64 / nodes:.0f}); {flops / nodes:.0f} FP64 flops",
+        f"# VALUBusy = 100 SQ_ACTIVE_INST_VALU / {cus} CUs / (GRBM_GUI_ACTIVE / {xccs} XCCs) = {busy:.1f}%",
+        f"kernel: {kname}",
+        f"kernel_source_hash: {kernel_source_hash('mom.hip' if args.storage == 'moments' else 'step2d.hip')}",
+        f"valu_insts_per_node: {d['SQ_INSTS_VALU'] * 64 / nodes:.1f}",
+        f"fp64_flops_per_node: {flops / nodes:.1f}",
+        f"valu_busy_percent: {busy:.2f}",
+    ]
+    path = os.path.join(ROOT, "profiles", f"{args.lattice.lower()}_{args.storage}_{args.n}_valu.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
     return path
 
 
@@ -463,6 +571,11 @@ def main():
     ap.add_argument("--no-studies", action="store_true", help="skip the precision, Sod and stability studies")
     ap.add_argument("--closure", choices=["full", "small", "none"], default="full",
                     help="learned-closure study: D2V37 256^2 coarse / 1024^2 fine (full) or 64^2 / 256^2")
+    ap.add_argument("--only-closure", action="store_true",
+                    help="time the fused closure step (D2V37, random network) at --n only")
+    ap.add_argument("--summarize-requests", nargs=4, metavar="DIR",
+                    help="request-counter cross-check from --pmc csv dirs: step reads, step writes, copy reads, copy writes")
+    ap.add_argument("--summarize-valu", nargs=1, metavar="DIR", help="VALU summary from one --pmc csv dir")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline workload only (no sweeps, studies, closure or CPU baseline)")
     ap.add_argument("--no-hbm-points", action="store_true",
@@ -482,6 +595,12 @@ def main():
         return
     if args.summarize_trace:
         print(summarize_trace(args))
+        return
+    if args.summarize_requests:
+        print(summarize_requests(args))
+        return
+    if args.summarize_valu:
+        print(summarize_valu(args))
         return
     if args.summarize_trace3d:
         print(summarize_trace3d(args))
@@ -512,6 +631,30 @@ def main():
         only = None if args.only_3d == "all" else tuple(args.only_3d.split(":"))
         print(json.dumps({"lattices_3d": suite_3d(torch, b, wl, n=args.n3, steps=args.steps, warmup=args.warmup,
                                                   only=only)}), flush=True)
+        return
+
+    if args.only_closure:
+        # the fused closure step with a random network (every node inside a wide
+        # normalisation range): its cost does not depend on the weights
+        from paper_1704_04413_amd import closure as cl
+
+        theta = torch.as_tensor(cl.init_theta(3)).cuda()
+        nv = np.zeros(b.LBM_MLP_NNORM)
+        nv[8:16] = 1.0
+        nv[16:24], nv[24:32] = -1e30, 1e30
+        nv[48:64] = 1e-6
+        nv[64:80], nv[80:96] = -1e30, 1e30
+        norm = torch.as_tensor(nv, dtype=torch.float32).cuda()
+        sim, meta = make_sim(b, wl, "D2V37", args.n, args.storage, re=3e4, noise=False)
+        b.lbm_closure_set(sim.ctx, theta, norm)
+        wall, kms = time_steps(torch, sim, args.steps, args.warmup)
+        sim.close()
+        bpl = bytes_per_node(meta["q"], args.storage) * args.n * args.n
+        print(json.dumps({"closure_step": True, "value": round(args.n * args.n * args.steps / wall / 1e6, 2),
+                          "unit": "MLUPS", "steps": args.steps,
+                          "roofline": {"bytes_per_launch": bpl, "kernel_ms_avg": round(kms, 5),
+                                       "achieved": round(bpl / (kms * 1e-3) / 1e9, 1),
+                                       "frac": round(bpl / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}), flush=True)
         return
 
     if args.only_headline:
