@@ -320,6 +320,54 @@ def summarize_trace3d(args) -> str:
     return path
 
 
+def summarize_trace_batch(args) -> str:
+    """Writes profiles/batch64_fp32_kernel_trace.md from the rocpd database of
+    a --kernel-trace --stats run of `bench.py --only-batch` and that run's JSON
+    line.  The timed steps are the last `steps` dispatches of each persistent
+    batch kernel (the autotuner's trials come before them)."""
+    import sqlite3
+
+    db, bench_json = args.summarize_trace_batch
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, total_calls, total_duration, average, percentage from top_kernels").fetchall()
+    line = [ln for ln in open(bench_json) if ln.startswith("{")][-1]
+    live = json.loads(line)["batched"]
+    k = live["steps"]
+    disp = con.execute("select name, duration, grid_x, workgroup_x, workgroup_y, vgpr_count, accum_vgpr_count, "
+                       "sgpr_count, scratch_size from kernels where name like '%k_batch<%' order by start").fetchall()
+    names = sorted({d[0] for d in disp})
+    cmd = f"rocprofv3 --kernel-trace --stats -d gpurun_out/profb -o run -- python3 bench.py --only-batch --steps {k}"
+    out = [f"# rocprofv3 kernel trace: batch of {live['workload']}", "",
+           "Command (repo root on an MI355X):", "", f"    {cmd}", "",
+           "Summary: `python3 bench.py --summarize-trace-batch <run_results.db> <bench output>`", "",
+           "From the `top_kernels` view (durations in microseconds; the run also times one launch per instance "
+           "per step, and the autotuner's trials):", "",
+           "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
+    for name, c, tot, avg, pct in rows[:12]:
+        out.append(f"| `{name[:110]}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
+    out += ["", f"Timed region: the last {k} dispatches of each batch kernel (tile_x {live['tile_x']}, "
+                f"{live['blocks_per_cu']} blocks per CU after autotuning):", "",
+            "| kernel | grid | block | VGPR | AGPR | SGPR | scratch | average us |", "|---|---|---|---|---|---|---|---|"]
+    total_us = 0.0
+    for nm in names:
+        last = [d for d in disp if d[0] == nm][-k:]
+        avg = float(np.mean([d[1] for d in last])) / 1e3
+        total_us += avg
+        d = last[-1]
+        out.append(f"| `{nm[:80]}` | {d[2]} | {d[3]}x{d[4]} | {d[5]} | {d[6]} | {d[7]} | {d[8]} | {avg:.2f} |")
+    nbytes = live["bytes_per_step"]
+    out += ["", f"Algorithmic bytes per step (every member: 2 Q bytes-per-value per node): {nbytes} B.",
+            f"Kernel time per step {total_us:.2f} us -> {nbytes / (total_us * 1e-6) / 1e9:.1f} GB/s = "
+            f"{nbytes / (total_us * 1e-6) / 1e9 / HBM_PEAK_GBS * 100:.1f}% of the 8 TB/s HBM3E peak.",
+            f"Live HIP-event timing of the replayed graph in the same run: {live['batched_ms_per_step'] * 1e3:.2f} us "
+            f"per step ({live['batched_MLUPS']} MLUPS, {live['batched_frac_hbm'] * 100:.1f}% of peak).",
+            f"kernel_source_hash: {kernel_source_hash('batch.hip')}"]
+    path = os.path.join(ROOT, "profiles", "batch64_fp32_kernel_trace.md")
+    with open(path, "w") as f:
+        f.write("\n".join(out) + "\n")
+    return path
+
+
 def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0, noise=True, coll=0):
     """The shear-layer workload (noise=False skips the 1e-8 w_i noise, which
     changes nothing in the timing of a large grid)."""
@@ -497,6 +545,7 @@ def batched_suite(torch, b, wl, storage="fp32", steps=40):
                     f"{storage} shifted storage",
         "nodes": nodes, "bytes_per_step": nbytes, "steps": steps,
         "batched_MLUPS": round(nodes * steps / t_bat / 1e6, 1),
+        "batched_ms_per_step": round(t_bat / steps * 1e3, 5),
         "batched_GBs": round(nbytes * steps / t_bat / 1e9, 1),
         "batched_frac_hbm": round(nbytes * steps / t_bat / 1e9 / HBM_PEAK_GBS, 4),
         "per_instance_MLUPS": round(nodes * steps / t_sep / 1e6, 1),
@@ -576,6 +625,10 @@ def main():
     ap.add_argument("--summarize-requests", nargs=4, metavar="DIR",
                     help="request-counter cross-check from --pmc csv dirs: step reads, step writes, copy reads, copy writes")
     ap.add_argument("--summarize-valu", nargs=1, metavar="DIR", help="VALU summary from one --pmc csv dir")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="time the 64-instance batch (FP32, autotuned) alone and print its line")
+    ap.add_argument("--summarize-trace-batch", nargs=2, metavar=("DB", "BENCH_OUT"),
+                    help="write the batch kernel-trace summary from a rocprofv3 database and that run's output")
     ap.add_argument("--only-headline", action="store_true",
                     help="time the headline workload only (no sweeps, studies, closure or CPU baseline)")
     ap.add_argument("--no-hbm-points", action="store_true",
@@ -605,6 +658,9 @@ def main():
     if args.summarize_trace3d:
         print(summarize_trace3d(args))
         return
+    if args.summarize_trace_batch:
+        print(summarize_trace_batch(args))
+        return
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -631,6 +687,10 @@ def main():
         only = None if args.only_3d == "all" else tuple(args.only_3d.split(":"))
         print(json.dumps({"lattices_3d": suite_3d(torch, b, wl, n=args.n3, steps=args.steps, warmup=args.warmup,
                                                   only=only)}), flush=True)
+        return
+
+    if args.only_batch:
+        print(json.dumps({"batched": batched_suite(torch, b, wl, steps=args.steps)}), flush=True)
         return
 
     if args.only_closure:

@@ -52,6 +52,10 @@
  *     (1 up to 128 MiB, 2 from 256 to 320 MiB, 0 otherwise; 3D: RR and BGK).
  *   RRLBM_XCD_REMAP=0  keeps the hardware's round-robin order of blocks over
  *     the 8 XCDs instead of giving each XCD a contiguous band of tiles.
+ *   RRLBM_BATCH_SPLIT=1/2  (read by lbm_batch_create) gives each lattice of a
+ *     batch its own work list and persistent kernel, recorded as concurrent
+ *     graph branches (1) or one after another (2); by default one kernel walks
+ *     a single mixed list.
  */
 #ifndef RRLBM_H
 #define RRLBM_H

@@ -54,9 +54,9 @@ hipError_t mom_launch_1(const lbm_ctx*, int, const void*, void*, const InitArgs*
                         double*, double*);
 hipError_t mom_launch_2(const lbm_ctx*, int, const void*, void*, const InitArgs*, double*, double*, double*, double*,
                         double*, double*);
-hipError_t batch_launch_0(const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
-hipError_t batch_launch_1(const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
-hipError_t batch_launch_2(const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
+hipError_t batch_launch_0(int, const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
+hipError_t batch_launch_1(int, const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
+hipError_t batch_launch_2(int, const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
 
 const Ops2D& ops2d(int lattice, int store)
 {
@@ -87,13 +87,13 @@ hipError_t mom_launch_any(const lbm_ctx* c, int what, const void* fin, void* fou
     }
 }
 
-hipError_t batch_launch(int store, const InstDesc* desc, const int* begin, int n, int total, int parity, int tile_x,
-                        int grid, hipStream_t st)
+hipError_t batch_launch(int store, int lattice, const InstDesc* desc, const int* begin, int n, int total, int parity,
+                        int tile_x, int grid, hipStream_t st)
 {
     switch (store) {
-    case ST_F32: return batch_launch_1(desc, begin, n, total, parity, tile_x, grid, st);
-    case ST_BF16: return batch_launch_2(desc, begin, n, total, parity, tile_x, grid, st);
-    default: return batch_launch_0(desc, begin, n, total, parity, tile_x, grid, st);
+    case ST_F32: return batch_launch_1(lattice, desc, begin, n, total, parity, tile_x, grid, st);
+    case ST_BF16: return batch_launch_2(lattice, desc, begin, n, total, parity, tile_x, grid, st);
+    default: return batch_launch_0(lattice, desc, begin, n, total, parity, tile_x, grid, st);
     }
 }
 
@@ -714,16 +714,33 @@ __global__ void k_batch_advance(InstDesc* desc, int n)
     if (i < n) desc[i].seq += 2u;
 }
 
+// By default one persistent kernel walks a single mixed work list and
+// switches on each tile's lattice.  RRLBM_BATCH_SPLIT=1 groups the members by
+// lattice instead: desc[] lists them lattice by lattice, each lattice has its
+// own work list (begin offsets) and its own kernel compiled for that lattice
+// alone (so D2Q9 tiles do not run with the register budget D2V37 needs), and
+// the lattices' launches are independent branches of the graph;
+// RRLBM_BATCH_SPLIT=2 keeps the grouping but records the launches one after
+// another.  The three forms gave the same throughput within 3%.
 struct lbm_batch {
     std::vector<lbm_ctx*> members;
+    std::vector<int> order;       // desc[k] describes members[order[k]]
     std::vector<InstDesc> desc;
-    std::vector<int> begin;
+    std::vector<int> begin;       // per group: count + 1 offsets
+    struct Group {
+        int lattice;              // -1: mixed list
+        int first, n;             // desc[first .. first + n)
+        int begin_off, total;     // begin[begin_off ..], work items
+    };
+    std::vector<Group> groups;
+    bool split = false;    // one work list and kernel per lattice
+    bool branches = false; // the groups' launches as independent graph branches
     int store = ST_F64;
-    hipStream_t stream = nullptr;  // members' stream: every replay goes there
-    hipStream_t capture = nullptr; // private stream used only to record the graph
+    hipStream_t stream = nullptr;        // members' stream: every replay goes there
+    hipStream_t capture[3] = {};         // private streams used only to record the graph
+    hipEvent_t fork = nullptr, join[2] = {};
     InstDesc* d_desc = nullptr;
     int* d_begin = nullptr;
-    int total = 0;
     int tile_x = 64, bpc = 4, num_cu = 256;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -731,11 +748,20 @@ struct lbm_batch {
 
 namespace {
 
+hipError_t launch_group(const lbm_batch* b, const lbm_batch::Group& g, hipStream_t st, int parity)
+{
+    const int grid = std::min(g.total, b->num_cu * b->bpc);
+    return batch_launch(b->store, g.lattice, b->d_desc + g.first, b->d_begin + g.begin_off, g.n, g.total, parity,
+                        b->tile_x, grid, st);
+}
+
 hipError_t launch_batch_any(const lbm_batch* b, hipStream_t st, int parity)
 {
-    const int grid = std::min(b->total, b->num_cu * b->bpc);
-    return batch_launch(b->store, b->d_desc, b->d_begin, int(b->members.size()), b->total, parity, b->tile_x, grid,
-                        st);
+    for (const auto& g : b->groups) {
+        const hipError_t e = launch_group(b, g, st, parity);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 void batch_release_graph(lbm_batch* b)
@@ -746,47 +772,82 @@ void batch_release_graph(lbm_batch* b)
     b->graph = nullptr;
 }
 
-// Rebuilds the work list for the current tile width, uploads it with every
+// Records the two-step graph: each group's parity-0 and parity-1 launches in
+// a branch of its own (a capture stream per group, forked from and joined to
+// the first), then the BF16 key advance.
+hipError_t batch_capture(lbm_batch* b)
+{
+    const int ng = b->branches ? int(b->groups.size()) : 1;
+    hipStream_t c0 = b->capture[0];
+    hipError_t e = hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    hipError_t le = hipEventRecord(b->fork, c0);
+    for (int g = 1; g < ng && le == hipSuccess; ++g) le = hipStreamWaitEvent(b->capture[g], b->fork, 0);
+    for (int g = 0; g < int(b->groups.size()) && le == hipSuccess; ++g) {
+        hipStream_t st = b->capture[b->branches ? g : 0];
+        le = launch_group(b, b->groups[g], st, 0);
+        if (le == hipSuccess) le = launch_group(b, b->groups[g], st, 1);
+    }
+    for (int g = 1; g < ng && le == hipSuccess; ++g) {
+        le = hipEventRecord(b->join[g - 1], b->capture[g]);
+        if (le == hipSuccess) le = hipStreamWaitEvent(c0, b->join[g - 1], 0);
+    }
+    if (le == hipSuccess && b->store == ST_BF16) {
+        const int n = int(b->desc.size());
+        k_batch_advance<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c0>>>(b->d_desc, n);
+        le = hipGetLastError();
+    }
+    const hipError_t ec = hipStreamEndCapture(c0, &b->graph);
+    return le != hipSuccess ? le : ec;
+}
+
+// Rebuilds the work lists for the current tile width, uploads them with every
 // member's buffer parity, and records the two-step graph.
 int batch_prepare(lbm_batch* b)
 {
     const int n = int(b->members.size());
-    b->desc.resize(n);
-    b->begin.assign(n + 1, 0);
-    int64_t total = 0;
-    for (int i = 0; i < n; ++i) {
-        const lbm_ctx* c = b->members[i];
-        InstDesc& d = b->desc[i];
-        d.buf[0] = c->buf[0];
-        d.buf[1] = c->buf[1];
-        d.lay = c->lay;
-        d.lattice = c->lattice;
-        d.bx_blocks = (c->nx + b->tile_x - 1) / b->tile_x;
-        d.flip = c->cur;
-        d.rx = relax_of(c);
-        d.seq = uint32_t(c->steps + 1);
-        b->begin[i] = int(total);
-        total += int64_t(d.bx_blocks) * ((c->ny + BY - 1) / BY);
+    b->order.clear();
+    b->groups.clear();
+    const int lats[3] = { LBM_D2Q9, LBM_D2V17, LBM_D2V37 };
+    for (int li = 0; li < (b->split ? 3 : 1); ++li) {
+        lbm_batch::Group g{ b->split ? lats[li] : -1, int(b->order.size()), 0, 0, 0 };
+        for (int i = 0; i < n; ++i)
+            if (!b->split || b->members[i]->lattice == lats[li]) b->order.push_back(i);
+        g.n = int(b->order.size()) - g.first;
+        if (g.n > 0) b->groups.push_back(g);
     }
-    if (total >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "batch work list too long");
-    b->begin[n] = int(total);
-    b->total = int(total);
+    b->desc.resize(n);
+    b->begin.clear();
+    for (auto& g : b->groups) {
+        g.begin_off = int(b->begin.size());
+        int64_t total = 0;
+        for (int k = g.first; k < g.first + g.n; ++k) {
+            const lbm_ctx* c = b->members[b->order[k]];
+            InstDesc& d = b->desc[k];
+            d.buf[0] = c->buf[0];
+            d.buf[1] = c->buf[1];
+            d.lay = c->lay;
+            d.lattice = c->lattice;
+            d.bx_blocks = (c->nx + b->tile_x - 1) / b->tile_x;
+            d.flip = c->cur;
+            d.rx = relax_of(c);
+            d.seq = uint32_t(c->steps + 1);
+            b->begin.push_back(int(total));
+            total += int64_t(d.bx_blocks) * ((c->ny + BY - 1) / BY);
+        }
+        if (total >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "batch work list too long");
+        b->begin.push_back(int(total));
+        g.total = int(total);
+    }
     HIP_TRY(hipMemcpyAsync(b->d_desc, b->desc.data(), sizeof(InstDesc) * n, hipMemcpyHostToDevice, b->stream));
-    HIP_TRY(hipMemcpyAsync(b->d_begin, b->begin.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice, b->stream));
+    HIP_TRY(hipMemcpyAsync(b->d_begin, b->begin.data(), sizeof(int) * b->begin.size(), hipMemcpyHostToDevice,
+                           b->stream));
     HIP_TRY(hipStreamSynchronize(b->stream));
     batch_release_graph(b);
-    HIP_TRY(hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal));
-    hipError_t e0 = launch_batch_any(b, b->capture, 0);
-    hipError_t e1 = (e0 == hipSuccess) ? launch_batch_any(b, b->capture, 1) : e0;
-    if (e1 == hipSuccess && b->store == ST_BF16) {
-        k_batch_advance<<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, b->capture>>>(b->d_desc, n);
-        e1 = hipGetLastError();
-    }
-    hipError_t ec = hipStreamEndCapture(b->capture, &b->graph);
-    if (e0 != hipSuccess || e1 != hipSuccess || ec != hipSuccess) {
+    const hipError_t e = batch_capture(b);
+    if (e != hipSuccess) {
         batch_release_graph(b);
-        return fail(LBM_EDEVICE, std::string("batch graph capture: ") +
-                                     hipGetErrorString(e0 != hipSuccess ? e0 : e1 != hipSuccess ? e1 : ec));
+        return fail(LBM_EDEVICE, std::string("batch graph capture: ") + hipGetErrorString(e));
     }
     HIP_TRY(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     return LBM_OK;
@@ -799,9 +860,9 @@ int batch_sync_parity(lbm_batch* b)
 {
     const bool dither = b->store == ST_BF16;
     bool stale = false;
-    for (size_t i = 0; i < b->members.size(); ++i) {
-        InstDesc& d = b->desc[i];
-        const lbm_ctx* c = b->members[i];
+    for (size_t k = 0; k < b->desc.size(); ++k) {
+        InstDesc& d = b->desc[k];
+        const lbm_ctx* c = b->members[b->order[k]];
         if (d.flip != c->cur) {
             d.flip = c->cur;
             stale = true;
@@ -860,10 +921,20 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, i
         hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu < 1)
         e = fail(LBM_EDEVICE, "cannot query the compute-unit count");
     b->num_cu = ncu;
-    if (!e && (hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking) != hipSuccess ||
-               hipMalloc(&b->d_desc, sizeof(InstDesc) * n) != hipSuccess ||
-               hipMalloc(&b->d_begin, sizeof(int) * (n + 1)) != hipSuccess))
-        e = fail(LBM_EDEVICE, "batch device allocation failed");
+    if (const char* sp = std::getenv("RRLBM_BATCH_SPLIT")) {
+        b->split = std::atoi(sp) != 0;
+        b->branches = std::atoi(sp) == 1;
+    }
+    if (!e) {
+        bool ok = true;
+        for (auto& cs : b->capture) ok = ok && hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+        for (auto& ev : b->join) ok = ok && hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
+        // at most 3 groups: n + 3 begin offsets
+        ok = ok && hipMalloc(&b->d_desc, sizeof(InstDesc) * n) == hipSuccess &&
+             hipMalloc(&b->d_begin, sizeof(int) * (n + 3)) == hipSuccess;
+        if (!ok) e = fail(LBM_EDEVICE, "batch device allocation failed");
+    }
     if (!e) e = batch_prepare(b);
     if (e) {
         lbm_batch_destroy(b);
@@ -950,11 +1021,15 @@ int lbm_batch_config(const lbm_batch* b, int* tile_x, int* blocks_per_cu)
 void lbm_batch_destroy(lbm_batch* b)
 {
     if (!b) return;
-    if (b->stream || b->capture) (void)hipStreamSynchronize(b->stream);
+    (void)hipStreamSynchronize(b->stream);
     batch_release_graph(b);
     if (b->d_desc) (void)hipFree(b->d_desc);
     if (b->d_begin) (void)hipFree(b->d_begin);
-    if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (auto cs : b->capture)
+        if (cs) (void)hipStreamDestroy(cs);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    for (auto ev : b->join)
+        if (ev) (void)hipEventDestroy(ev);
     delete b;
 }
 

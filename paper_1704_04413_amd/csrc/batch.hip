@@ -1,6 +1,7 @@
-// The persistent batch kernel for one storage kind, chosen at compile time
-// (RR_STORE = ST_F64, ST_F32 or ST_BF16); it walks a work list of tiles that
-// spans members of every 2D lattice.
+// The persistent batch kernels for one storage kind, chosen at compile time
+// (RR_STORE = ST_F64, ST_F32 or ST_BF16): one per 2D lattice, each walking
+// the work list of that lattice's members, and one that walks a list mixing
+// every lattice.
 #include "context.hpp"
 #include "step2d.hpp"
 
@@ -20,12 +21,19 @@ using BatchSto = StoreBF16;
 #error "RR_STORE must be a population storage"
 #endif
 
+// lattice: LBM_D2Q9..LBM_D2V37 when every member of the list has it, -1 for a mixed list.
 #define RR_BATCH_NAME_(s) batch_launch_##s
 #define RR_BATCH_NAME(s) RR_BATCH_NAME_(s)
-hipError_t RR_BATCH_NAME(RR_STORE)(const InstDesc* desc, const int* begin, int n, int total, int parity, int tile_x,
-                                   int grid, hipStream_t st)
+hipError_t RR_BATCH_NAME(RR_STORE)(int lattice, const InstDesc* desc, const int* begin, int n, int total, int parity,
+                                   int tile_x, int grid, hipStream_t st)
 {
-    k_batch<BatchSto><<<dim3(unsigned(grid)), dim3(BX, BY), 0, st>>>(desc, begin, n, total, parity, tile_x);
+    const dim3 g = dim3(unsigned(grid)), blk = dim3(BX, BY);
+    switch (lattice) {
+    case LBM_D2Q9: k_batch<BatchSto, 0><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+    case LBM_D2V17: k_batch<BatchSto, 1><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+    case LBM_D2V37: k_batch<BatchSto, 2><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+    default: k_batch<BatchSto, -1><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+    }
     return hipGetLastError();
 }
 

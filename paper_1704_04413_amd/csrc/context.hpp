@@ -107,8 +107,9 @@ hipError_t mom_launch_any(const lbm_ctx* c, int what, const void* fin = nullptr,
                           double* ux = nullptr, double* uy = nullptr, double* th = nullptr,
                           double* partial = nullptr);
 
-// Persistent batch launch for one storage kind (batch.hip).
-hipError_t batch_launch(int store, const InstDesc* desc, const int* begin, int n, int total, int parity,
+// Persistent batch launch for one storage kind (batch.hip) over a work list
+// whose members all have `lattice` (or mix lattices: -1).
+hipError_t batch_launch(int store, int lattice, const InstDesc* desc, const int* begin, int n, int total, int parity,
                         int tile_x, int grid, hipStream_t st);
 
 // Fused closure step of an isothermal RR D2V37 context (closure.hip).

@@ -109,7 +109,9 @@ void k_stream_collide(StepArgs a)
 // belongs to the member i with begin[i] <= w < begin[i+1].  Each item is a
 // tile_x by 4 patch of one member, walked 64 columns at a time.  `parity`
 // selects the buffer direction of this step for every member.
-template <class S>
+// LAT: the one lattice of every member of this work list (its own register
+// budget), or -1 for a list that mixes lattices (one switch per work item).
+template <class S, int LAT>
 __global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ desc, const int* __restrict__ begin,
                                                   int n, int total, int parity, int tile_x)
 {
@@ -134,10 +136,19 @@ __global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ d
         for (int sub = 0; sub < tile_x; sub += BX) {
             const int x = x0 + sub + int(threadIdx.x);
             if (x < d.lay.nx && y < d.lay.ny) {
-                switch (d.lattice) {
-                case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
-                case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
-                default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, d.seq + uint32_t(parity)); break;
+                const uint32_t seq = d.seq + uint32_t(parity);
+                if constexpr (LAT == 0) {
+                    node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, seq);
+                } else if constexpr (LAT == 1) {
+                    node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, seq);
+                } else if constexpr (LAT == 2) {
+                    node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, seq);
+                } else {
+                    switch (d.lattice) {
+                    case 0: node_update<D2Q9, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, seq); break;
+                    case 1: node_update<D2V17, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, seq); break;
+                    default: node_update<D2V37, S, COLL_RR, false, false, true>(fin, fout, d.lay, x, y, d.rx, seq); break;
+                    }
                 }
             }
         }

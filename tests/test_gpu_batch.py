@@ -34,15 +34,22 @@ def make(orc, b, name, nx, ny, seed, flags=0):
     return sim, lat, tau, f0
 
 
+# RRLBM_BATCH_SPLIT: one mixed work list (0), one list and kernel per lattice
+# as concurrent graph branches (1) or recorded one after another (2)
+SPLIT_MODES = ["0", "1", "2"]
+
+
 def check(got, want, atol):
     err = float(np.abs(np.asarray(got) - np.asarray(want)).max())
     print(f"[parity] max diff {err:.3e} (bound {atol:.0e})", flush=True)
     assert err <= atol, err
 
 
+@pytest.mark.parametrize("split", SPLIT_MODES)
 @pytest.mark.parametrize("tile_x,bpc", [(64, 4), (128, 2), (256, 16)])
-def test_batch_fp64_against_oracle(orc, b, tile_x, bpc):
-    print(f"[case] batch fp64 tile_x={tile_x} bpc={bpc}", flush=True)
+def test_batch_fp64_against_oracle(orc, b, tile_x, bpc, split, monkeypatch):
+    monkeypatch.setenv("RRLBM_BATCH_SPLIT", split)
+    print(f"[case] batch fp64 tile_x={tile_x} bpc={bpc} split={split}", flush=True)
     made = [make(orc, b, name, nx, ny, seed) for seed, (name, nx, ny) in enumerate(MEMBERS)]
     batch = b.lbm_batch_create([m[0].ctx for m in made], tile_x, bpc)
     b.lbm_batch_step(batch, 4)
@@ -77,14 +84,16 @@ def test_batch_matches_individual_steps(orc, b, storage):
         check(gx, gy, 1e-7 if storage == "fp32" else 2e-3)
 
 
+@pytest.mark.parametrize("split", SPLIT_MODES)
 @pytest.mark.parametrize("storage", ["fp32", "bf16"])
-def test_batch_interleaved_with_single_steps(orc, b, storage):
+def test_batch_interleaved_with_single_steps(orc, b, storage, split, monkeypatch):
     """Batch calls with odd step counts and members stepped on their own in
     between: the buffer parities and the BF16 dither keys (the index of the
     state being written) must follow, so every stored value equals that of a
     member stepped alone (a wrong key would change about half the BF16
     values)."""
-    print(f"[case] batch {storage} interleaved", flush=True)
+    monkeypatch.setenv("RRLBM_BATCH_SPLIT", split)
+    print(f"[case] batch {storage} interleaved split={split}", flush=True)
     flags = b.LBM_STORE_FP32 if storage == "fp32" else b.LBM_STORE_BF16
     batched = [make(orc, b, name, nx, ny, seed, flags)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
     single = [make(orc, b, name, nx, ny, seed, flags)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
@@ -144,10 +153,12 @@ def test_batch_rejects_mixed_members(orc, b):
     assert lat.Q == 37
 
 
-def test_batch_follows_per_order_relaxation(orc, b):
+@pytest.mark.parametrize("split", SPLIT_MODES)
+def test_batch_follows_per_order_relaxation(orc, b, split, monkeypatch):
     """A member's rank-3/4 times changed after the batch was built reach the
     replayed graph (the descriptors are refreshed)."""
-    print("[case] batch per-order relaxation", flush=True)
+    monkeypatch.setenv("RRLBM_BATCH_SPLIT", split)
+    print(f"[case] batch per-order relaxation split={split}", flush=True)
     batched = [make(orc, b, name, nx, ny, seed, b.LBM_STORE_FP32)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
     single = [make(orc, b, name, nx, ny, seed, b.LBM_STORE_FP32)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
     batch = b.lbm_batch_create([s.ctx for s in batched], 64, 4)
