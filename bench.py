@@ -51,6 +51,11 @@ def kernel_source_hash(unit: str = "step2d.hip") -> str:
     return h.hexdigest()[:16]
 
 
+def kernel_unit(storage: str = "fp64", closure: bool = False) -> str:
+    """The source unit of the kernel a profile of this storage covers."""
+    return "closure.hip" if closure else "mom.hip" if storage == "moments" else "step2d.hip"
+
+
 def read_traffic(name: str):
     """HBM bytes per launch measured by rocprofv3 counters (profiles/<name>),
     valid only if the kernel sources have not changed since."""
@@ -62,7 +67,7 @@ def read_traffic(name: str):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_hash") != kernel_source_hash():
+    if kv.get("kernel_source_hash") != kernel_source_hash("mom.hip" if "_moments_" in name else "step2d.hip"):
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -130,7 +135,7 @@ def summarize_pmc(args) -> str:
         f"#   -> read {rd / 1e6:.1f} MB, written {wr / 1e6:.1f} MB per launch; algorithmic {alg_formula} = {alg / 1e6:.1f} MB",
         f"#   -> measured / algorithmic = {(rd + wr) / alg:.4f}",
         f"kernel: {kname}",
-        f"kernel_source_hash: {kernel_source_hash()}",
+        f"kernel_source_hash: {kernel_source_hash(kernel_unit(args.storage))}",
         f"fetch_scale: {fs:.6f}",
         f"write_scale: {ws:.6f}",
         f"read_bytes_per_launch: {rd:.0f}",
@@ -173,7 +178,7 @@ def summarize_trace(args) -> str:
                 f"average {roof['kernel_ms_avg'] * 1e3:.2f} us per launch (events at both ends of the region).",
             "", f"Algorithmic bytes per launch: {roof['bytes_per_launch']} B -> {roof['achieved']:.1f} GB/s = "
                 f"{roof['frac'] * 100:.1f}% of the 8 TB/s HBM3E peak.",
-            f"kernel_source_hash: {kernel_source_hash()}"]
+            f"kernel_source_hash: {kernel_source_hash(kernel_unit(args.storage, args.only_closure))}"]
     path = os.path.join(ROOT, "profiles", name)
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
@@ -274,7 +279,7 @@ def summarize_valu(args) -> str:
         f"{f64 * 64 / nodes:.0f} (FMA {d['SQ_INSTS_VALU_FMA_F64'] * 64 / nodes:.0f}); {flops / nodes:.0f} FP64 flops",
         f"# VALUBusy = 100 SQ_ACTIVE_INST_VALU / {cus} CUs / (GRBM_GUI_ACTIVE / {xccs} XCCs) = {busy:.1f}%",
         f"kernel: {kname}",
-        f"kernel_source_hash: {kernel_source_hash('mom.hip' if args.storage == 'moments' else 'step2d.hip')}",
+        f"kernel_source_hash: {kernel_source_hash(kernel_unit(args.storage))}",
         f"valu_insts_per_node: {d['SQ_INSTS_VALU'] * 64 / nodes:.1f}",
         f"fp64_flops_per_node: {flops / nodes:.1f}",
         f"valu_busy_percent: {busy:.2f}",
@@ -313,7 +318,7 @@ def summarize_trace3d(args) -> str:
     for r in cases:
         out.append(f"| {r['lattice']} | {r['collision']} | {r['kernel_ms_avg'] * 1e3:.1f} | {r['kernel_GBs']:.0f} | "
                    f"{r['frac_hbm'] * 100:.1f} |")
-    out += ["", f"kernel_source_hash: {kernel_source_hash()}"]
+    out += ["", f"kernel_source_hash: {kernel_source_hash('step3d.hip')}"]
     path = os.path.join(ROOT, "profiles", f"lattices3d_{n}_kernel_trace.md")
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")

@@ -65,8 +65,9 @@ hipError_t launch(const lbm_ctx* c, int what, const void* fin, void* fout, const
         k_mom_moments<L, ORDER><<<dim3(unsigned(c->nblk)), block, 0, c->stream>>>(m, n, rx, r, ux, uy, th, partial);
         break;
     default: {
-        const int bxn = (c->nx + BX - 1) / BX, byn = (c->ny + BY - 1) / BY;
-        const dim3 g(unsigned(bxn * byn)), blk(BX, BY);
+        constexpr int OX = BX - 2 * L::R;
+        const int bxn = (c->nx + OX - 1) / OX, byn = (c->ny + MOM_ROWS - 1) / MOM_ROWS;
+        const dim3 g(unsigned(bxn * byn)), blk(BX, MOM_ROWS);
         const double* a = static_cast<const double*>(fin);
         double* o = static_cast<double*>(fout);
         if (c->tau3 == c->tau && c->tau4 == c->tau)

@@ -149,24 +149,198 @@ __device__ __forceinline__ void node_state(const double (&v)[L::Q], double (&m)[
     m[5] = pyy - r * L::cs2 - r * uy * uy;
 }
 
-// One step on a BX x BY tile: the tile's moments and a halo of the lattice
-// reach are staged in LDS (periodic wrap), each thread pulls its Q
-// populations from there and writes its node's new moments.
+// ------------------------------------------------------------- the step
+//
+// The step works by velocity rows.  Every velocity with c_y = K pulls from
+// the row y - K, so the populations of that class that a row of outputs needs
+// were all produced on one source row, each at the source column x - c_x.  One
+// pass per class: each thread rebuilds, at its source node, the node's
+// coefficients
+//   C[a][b] = r u_x^a u_y^b + k_n a1^(a,b)    (n = a + b),
+// with a1^(3), a1^(4) from u and a1^(2) (Eq. MalaspinasRecursiveRelation at
+// theta = 1), contracts them with the class's c_y factor once,
+//   t[a] = sum_b He_b(K) C[a][b] / (a! b! c_s^2(a+b)),
+// and gets every population (c_x, K) of the class as w sum_a He_a(c_x) t[a]
+// (c_x and -c_x from one even and one odd part: Eq. GenRegCollision).  The
+// population (c_x, K) computed at source lane l is the one the output lane
+// l + c_x pulls, so a wave moves it c_x lanes with cross-lane moves and adds
+// it to that output's moment sums.  Per node that is 2R+1 coefficient builds
+// instead of Q (one per pulled population), and the c_y part of the Hermite
+// products is shared by a whole class.
+//
+// A block is one 64-wide segment of source columns by MOM_ROWS rows, one wave
+// per row; its outputs are the 64 - 2R inner columns (the outer R on each side
+// are the x halo of the pulls).  The moments of the rows the block reads
+// (its own and R above and below) are staged in LDS once.
+
+constexpr int MOM_ROWS = 16;
+
+// Coefficients C of a node with moments (r, u, a1^(2)) (see above); entries
+// outside the lattice basis are never read.
 template <class L, int ORDER, bool PO>
-__global__ __launch_bounds__(BX* BY) void k_mom_step(const double* __restrict__ min, double* __restrict__ mout, int nx,
-                                                     int ny, int bx_blocks, Relax rx)
+__device__ __forceinline__ void mom_coeffs(double r, double ux, double uy, double axx, double axy, double ayy,
+                                           const Relax& rx, double (&C)[5][5])
 {
-    constexpr int R = L::R, TW = BX + 2 * R, TH = BY + 2 * R;
-    __shared__ double sm[MOM_K][TH][TW];
-    const int x0 = int(blockIdx.x % unsigned(bx_blocks)) * BX;
-    const int y0 = int(blockIdx.x / unsigned(bx_blocks)) * BY;
+    const double k2 = rx.k2, k3 = PO ? rx.k3 : rx.k2, k4 = PO ? rx.k4 : rx.k2;
+    const double rux = r * ux, ruy = r * uy;
+    const double rxx = rux * ux, rxy = rux * uy, ryy = ruy * uy;
+    C[0][0] = r;
+    C[1][0] = rux;
+    C[0][1] = ruy;
+    C[2][0] = rxx + k2 * axx;
+    C[1][1] = rxy + k2 * axy;
+    C[0][2] = ryy + k2 * ayy;
+    // rank 3: a1_30 = 3 ux xx, a1_21 = 2 ux xy + uy xx, a1_12 = 2 uy xy + ux yy, a1_03 = 3 uy yy
+    if constexpr (ORDER >= 3) {
+        const double bxx = k3 * axx, bxy = k3 * axy, byy = k3 * ayy;
+        C[3][0] = ux * (rxx + 3.0 * bxx);
+        C[2][1] = uy * (rxx + bxx) + 2.0 * ux * bxy;
+        C[1][2] = ux * (ryy + byy) + 2.0 * uy * bxy;
+        C[0][3] = uy * (ryy + 3.0 * byy);
+    } else {
+        C[3][0] = ux * rxx;
+        C[2][1] = uy * rxx;
+        C[1][2] = ux * ryy;
+        C[0][3] = uy * ryy;
+    }
+    // rank 4: a1_40 = 6 ux^2 xx, a1_31 = 3 (ux^2 xy + ux uy xx),
+    //         a1_22 = uy^2 xx + ux^2 yy + 4 ux uy xy, a1_13 = 3 (uy^2 xy + ux uy yy), a1_04 = 6 uy^2 yy
+    const double x2 = ux * ux, xy = ux * uy, y2 = uy * uy;
+    if constexpr (ORDER >= 4) {
+        const double cxx = k4 * axx, cxy = k4 * axy, cyy = k4 * ayy;
+        C[4][0] = x2 * (rxx + 6.0 * cxx);
+        C[3][1] = ux * (uy * (rxx + 3.0 * cxx) + 3.0 * ux * cxy);
+        C[2][2] = y2 * (rxx + cxx) + x2 * cyy + 4.0 * xy * cxy;
+        C[1][3] = uy * (ux * (ryy + 3.0 * cyy) + 3.0 * uy * cxy);
+        C[0][4] = y2 * (ryy + 6.0 * cyy);
+    } else {
+        C[4][0] = x2 * rxx;
+        C[3][1] = xy * rxx;
+        C[2][2] = y2 * rxx;
+        C[1][3] = xy * ryy;
+        C[0][4] = y2 * ryy;
+    }
+}
+
+// Whether t[a] of class K has any term.
+template <class L>
+constexpr bool class_col(int a, int k)
+{
+    for (int b = 0; b < 5; ++b)
+        if (L::basis(a, b) && he(b, double(k), L::cs2) != 0.0) return true;
+    return false;
+}
+
+// Post-collision populations of the velocities (c_x, K) of a node with
+// coefficients C: emit(c_x, f) for each (c_x as a compile-time constant).
+template <class L, int K, class Emit>
+__device__ __forceinline__ void class_pops(const double (&C)[5][5], Emit&& emit)
+{
+    constexpr double cs2 = L::cs2;
+    double t[5];
+    static_for<5>([&](auto A) {
+        double s = 0.0;
+        static_for<5>([&](auto B) {
+            if constexpr (L::basis(int(A), int(B))) {
+                constexpr double h = he(int(B), double(K), cs2) * inv_norm<L>(int(A), int(B));
+                if constexpr (h != 0.0) s += h * C[A][B];
+            }
+        });
+        t[A] = s;
+    });
+    static_for<L::R + 1>([&](auto XI) {
+        constexpr int cx = int(XI);
+        constexpr int ip = vel_index<L>(cx, K);
+        if constexpr (ip >= 0) {
+            constexpr double w = L::v.w[ip];
+            double e = 0.0, o = 0.0;
+            static_for<5>([&](auto A) {
+                constexpr double h = w * he(int(A), double(cx), cs2);
+                if constexpr (class_col<L>(int(A), K) && h != 0.0) {
+                    if constexpr (int(A) % 2 == 0)
+                        e += h * t[A];
+                    else
+                        o += h * t[A];
+                }
+            });
+            if constexpr (cx == 0) {
+                emit(std::integral_constant<int, 0>{}, e);
+            } else {
+                emit(std::integral_constant<int, cx>{}, e + o);
+                emit(std::integral_constant<int, -cx>{}, e - o);
+            }
+        }
+    });
+}
+
+// Number of velocities with c_y = k.
+template <class L>
+constexpr int class_size(int k)
+{
+    int c = 0;
+    for (int i = 0; i < L::Q; ++i) c += L::v.cy[i] == k ? 1 : 0;
+    return c;
+}
+
+// Populations of class K at a node with moments m: through the coefficients
+// when the class has three velocities or more, otherwise one at a time
+// (mom_pop), which is cheaper for one or two.
+template <class L, int K, int ORDER, bool PO, class Emit>
+__device__ __forceinline__ void class_from_moments(const double (&m)[MOM_K], const Relax& rx, Emit&& emit)
+{
+    if constexpr (class_size<L>(K) >= 3) {
+        double C[5][5];
+        mom_coeffs<L, ORDER, PO>(m[0], m[1], m[2], m[3], m[4], m[5], rx, C);
+        class_pops<L, K>(C, emit);
+    } else {
+        static_for<2 * L::R + 1>([&](auto XI) {
+            constexpr int cx = int(XI) - L::R;
+            constexpr int ip = vel_index<L>(cx, K);
+            if constexpr (ip >= 0)
+                emit(std::integral_constant<int, cx>{},
+                     mom_pop<L, ip, ORDER, PO>(m[0], m[1], m[2], m[3], m[4], m[5], rx));
+        });
+    }
+}
+
+// Value of v held by lane (lane - D) of the wave (D in [-3, 3]), by |D|
+// one-lane wave shifts of both halves (DPP wave_shr:1 / wave_shl:1); lanes
+// whose source is outside the wave get zero.
+template <int D>
+__device__ __forceinline__ double lane_from(double v)
+{
+    if constexpr (D == 0) {
+        return v;
+    } else {
+        const long long b = __double_as_longlong(v);
+        int lo = int(b), hi = int(b >> 32);
+        constexpr int ctrl = D > 0 ? 0x138 : 0x130;
+        static_for<(D > 0 ? D : -D)>([&](auto) {
+            lo = __builtin_amdgcn_mov_dpp(lo, ctrl, 0xF, 0xF, true);
+            hi = __builtin_amdgcn_mov_dpp(hi, ctrl, 0xF, 0xF, true);
+        });
+        return __longlong_as_double((long long)(unsigned)lo | ((long long)hi << 32));
+    }
+}
+
+// Eight waves per SIMD: 64 VGPRs, and the 67.6 KB of staged moments of a
+// 16-row block let two blocks share a CU.
+template <class L, int ORDER, bool PO>
+__global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(8))) void k_mom_step(
+    const double* __restrict__ min, double* __restrict__ mout, int nx, int ny, int bx_blocks, Relax rx)
+{
+    constexpr int R = L::R, OX = BX - 2 * R, SH = MOM_ROWS + 2 * R, NC = 2 * R + 1;
+    __shared__ double sm[MOM_K][SH][BX];
+    const int x0 = int(blockIdx.x % unsigned(bx_blocks)) * OX;
+    const int y0 = int(blockIdx.x / unsigned(bx_blocks)) * MOM_ROWS;
     const int64_t n = int64_t(nx) * ny;
-    const int tid = int(threadIdx.y) * BX + int(threadIdx.x);
-    // the staged window covers columns x0 - R .. x0 + BX + R - 1: one wrap at
-    // most when the grid is at least that wide, a modulo otherwise
-    const bool wide = nx >= TW && ny >= TH;
-    for (int e = tid; e < TH * TW; e += BX * BY) {
-        const int ly = e / TW, lx = e - ly * TW;
+    const int lane = int(threadIdx.x), ty = int(threadIdx.y);
+    // stage source columns x0 - R .. x0 - R + 63, rows y0 - R .. y0 + MOM_ROWS
+    // + R - 1 (periodic: one wrap at most when the grid is at least that
+    // large, a modulo otherwise)
+    const bool wide = nx >= BX && ny >= SH;
+    for (int e = ty * BX + lane; e < SH * BX; e += BX * MOM_ROWS) {
+        const int ly = e / BX, lx = e - ly * BX;
         int gx = x0 + lx - R, gy = y0 + ly - R;
         if (wide) {
             gx += gx < 0 ? nx : 0;
@@ -181,22 +355,39 @@ __global__ __launch_bounds__(BX* BY) void k_mom_step(const double* __restrict__ 
         static_for<MOM_K>([&](auto M) { sm[M][ly][lx] = min[int64_t(M) * n + g]; });
     }
     __syncthreads();
-    const int x = x0 + int(threadIdx.x), y = y0 + int(threadIdx.y);
-    if (x >= nx || y >= ny) return;
-    // accumulate the moments of the arriving populations one at a time
+    const int x = x0 + lane - R, y = y0 + ty;
     double r = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
-    static_for<L::Q>([&](auto I) {
-        constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
-        const int ly = int(threadIdx.y) + R - cy, lx = int(threadIdx.x) + R - cx;
-        const double f = mom_pop<L, int(I), ORDER, PO>(sm[0][ly][lx], sm[1][ly][lx], sm[2][ly][lx], sm[3][ly][lx],
-                                                   sm[4][ly][lx], sm[5][ly][lx], rx);
-        r += f;
-        if constexpr (cx != 0) jx += double(cx) * f;
-        if constexpr (cy != 0) jy += double(cy) * f;
-        if constexpr (cx != 0) pxx += double(cx * cx) * f;
-        if constexpr (cx != 0 && cy != 0) pxy += double(cx * cy) * f;
-        if constexpr (cy != 0) pyy += double(cy * cy) * f;
+    static_for<NC>([&](auto KI) {
+        constexpr int K = int(KI) - R;
+        double mv[MOM_K];
+        static_for<MOM_K>([&](auto M) { mv[M] = sm[M][ty - K + R][lane]; });
+        // row sums of the class at this lane: s0 = sum f, s1 = sum c_x f,
+        // s2 = sum c_x^2 f over the populations (c_x, K) arriving here
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+        class_from_moments<L, K, ORDER, PO>(mv, rx, [&](auto CX, double f) {
+            constexpr int cx = decltype(CX)::value;
+            const double g = lane_from<cx>(f);
+            s0 += g;
+            if constexpr (cx != 0) {
+                s1 += double(cx) * g;
+                s2 += double(cx * cx) * g;
+            }
+        });
+        r += s0;
+        jx += s1;
+        pxx += s2;
+        if constexpr (K != 0) {
+            jy += double(K) * s0;
+            pxy += double(K) * s1;
+            pyy += double(K * K) * s0;
+        }
+        // one class at a time: the sums are taken here (not sunk to the end
+        // with every class's row sums kept alive), and the scheduler does not
+        // interleave classes
+        asm volatile("" : "+v"(r), "+v"(jx), "+v"(jy), "+v"(pxx), "+v"(pxy), "+v"(pyy));
+        __builtin_amdgcn_sched_barrier(0);
     });
+    if (lane < R || lane >= BX - R || x >= nx || y >= ny) return;
     const double ux = jx / r, uy = jy / r;
     const double m[MOM_K] = { r, ux, uy, pxx - r * L::cs2 - r * ux * ux, pxy - r * ux * uy,
                               pyy - r * L::cs2 - r * uy * uy };
