@@ -18,6 +18,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -38,16 +39,26 @@ def bytes_per_node(q: int, storage: str) -> int:
     return 2 * 6 * 8 if storage == "moments" else 2 * q * STORAGE_BYTES[storage]
 
 
+def _code_only(text: str) -> str:
+    """C/C++ source without comments and with whitespace collapsed (string
+    literals are kept as they are; none of the sources holds a comment
+    marker inside one)."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash(unit: str = "step2d.hip") -> str:
-    """Hash of one kernel unit's source and the headers it includes (a
-    counter summary is valid only while they are unchanged)."""
+    """Hash of the code of one kernel unit and the headers it includes (a
+    counter summary is valid only while it is unchanged; comments and
+    layout do not count)."""
     from paper_1704_04413_amd import build
 
     h = hashlib.sha256()
     for p in sorted(build._deps(unit)):
-        with open(p, "rb") as f:
+        with open(p) as f:
             h.update(os.path.basename(p).encode())
-            h.update(f.read())
+            h.update(_code_only(f.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -166,9 +177,10 @@ def summarize_trace(args) -> str:
     name = f"{args.lattice.lower()}_{'closure' if args.only_closure else args.storage}_{args.n}_kernel_trace.md"
     out = [f"# rocprofv3 kernel trace: {args.lattice} {args.storage.upper()} {args.n}x{args.n} shear layer ({what})",
            "", "Command (repo root on an MI355X):", "",
-           f"    rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o run -- python3 bench.py --steps 50 --warmup 5 "
-           f"{mode} --lattice {args.lattice} --n {args.n}{flag}",
-           "", f"Summary: `python3 bench.py --lattice {args.lattice} --n {args.n}{flag}{' --only-closure' if args.only_closure else ''} "
+           f"    rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o run -- python3 bench.py --steps {args.steps} "
+           f"--warmup {args.warmup} {mode} --lattice {args.lattice} --n {args.n}{flag}",
+           "", f"Summary: `python3 bench.py --steps {args.steps} --warmup {args.warmup} --lattice {args.lattice} "
+               f"--n {args.n}{flag}{' --only-closure' if args.only_closure else ''} "
                f"--summarize-trace <run_results.db> <bench output>`",
            "", "From the `top_kernels` view of the run's database (durations in microseconds):", "",
            "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
@@ -250,6 +262,49 @@ def summarize_requests(args) -> str:
         f"hbm_bytes_per_launch: {rbytes(rd) + wbytes(wr):.0f}",
     ]
     path = os.path.join(ROOT, "profiles", f"{args.lattice.lower()}_{args.storage}_{args.n}_requests.txt")
+    with open(path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return path
+
+
+CLOSURE_COUNTERS = ("SQ_INSTS_VALU SQ_ACTIVE_INST_VALU SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES "
+                    "SQ_WAVE_CYCLES SQ_WAIT_INST_ANY SQ_BUSY_CYCLES GRBM_GUI_ACTIVE")
+
+
+def summarize_closure_pmc(args) -> str:
+    """Instruction mix of the fused closure step against the plain step of
+    the same grid from two rocprofv3 --pmc runs with the same counters
+    (profiles/d2v37_closure_<n>_counters.txt)."""
+    cdir, pdir = args.summarize_closure_pmc
+    nodes = args.n * args.n
+    cus, xccs = 256, 8
+    rows = []
+    for label, d_, hint in (("closure", cdir, "k_stream_collide_closure"), ("plain", pdir, "k_stream_collide<")):
+        kname, d = _pmc_sums(d_, hint)
+        cyc = d["GRBM_GUI_ACTIVE"] / xccs
+        rows.append((label, kname, {
+            "valu_insts_per_node": d["SQ_INSTS_VALU"] * 64 / nodes,
+            "transcendental_insts_per_node": d["SQ_INSTS_VALU_TRANS_F32"] * 64 / nodes,
+            "mfma_insts_per_wave_of_64_nodes": d["SQ_INSTS_MFMA"] * 64 / nodes,
+            "valu_busy_percent": 100.0 * d["SQ_ACTIVE_INST_VALU"] / cus / cyc,
+            "mfma_busy_percent": 100.0 * d["SQ_VALU_MFMA_BUSY_CYCLES"] / cus / cyc / 4,
+            "wait_inst_any_percent_of_wave_cycles": 100.0 * d["SQ_WAIT_INST_ANY"] / d["SQ_WAVE_CYCLES"],
+            "gpu_cycles_per_xcc": cyc,
+        }))
+    lines = [f"# Fused closure step against the plain step: D2V37 FP64 {args.n}x{args.n} (rocprofv3 PMC)", "#",
+             "# Commands (repo root on an MI355X):",
+             f"#   rocprofv3 --pmc {CLOSURE_COUNTERS} --output-format csv -d {cdir} -o run -- python3 bench.py "
+             f"--steps 20 --warmup 2 --only-closure --lattice D2V37 --n {args.n}",
+             f"#   rocprofv3 --pmc {CLOSURE_COUNTERS} --output-format csv -d {pdir} -o run -- {PROFILE_RUN} "
+             f"--lattice D2V37 --n {args.n}",
+             f"# Summary: python3 bench.py --n {args.n} --summarize-closure-pmc {cdir} {pdir}",
+             "# Per node in the lane view (one lane per node); busy fractions over the kernel's GPU cycles.",
+             "# MFMA busy: SQ_VALU_MFMA_BUSY_CYCLES / 256 CUs / 4 SIMDs per kernel cycle."]
+    for label, kname, v in rows:
+        lines.append(f"{label}.kernel: {kname}")
+        lines += [f"{label}.{k}: {x:.1f}" for k, x in v.items()]
+    lines.append(f"kernel_source_hash: {kernel_source_hash('closure.hip')}")
+    path = os.path.join(ROOT, "profiles", f"d2v37_closure_{args.n}_counters.txt")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     return path
@@ -630,6 +685,8 @@ def main():
     ap.add_argument("--summarize-requests", nargs=4, metavar="DIR",
                     help="request-counter cross-check from --pmc csv dirs: step reads, step writes, copy reads, copy writes")
     ap.add_argument("--summarize-valu", nargs=1, metavar="DIR", help="VALU summary from one --pmc csv dir")
+    ap.add_argument("--summarize-closure-pmc", nargs=2, metavar="DIR",
+                    help="closure-step counters against the plain step: closure csv dir, plain csv dir")
     ap.add_argument("--only-batch", action="store_true",
                     help="time the 64-instance batch (FP32, autotuned) alone and print its line")
     ap.add_argument("--summarize-trace-batch", nargs=2, metavar=("DB", "BENCH_OUT"),
@@ -659,6 +716,9 @@ def main():
         return
     if args.summarize_valu:
         print(summarize_valu(args))
+        return
+    if args.summarize_closure_pmc:
+        print(summarize_closure_pmc(args))
         return
     if args.summarize_trace3d:
         print(summarize_trace3d(args))
