@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 METRIC = "MLUPS and % of HBM roofline per lattice; closure/low-precision vs plain at stated error"
 STORAGE_FLAGS = {"fp64": 0, "fp32": 0x2, "bf16": 0x4, "moments": 0x8, "fp32d": 0x2 | 0x400}
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp32d": 4}
@@ -65,6 +66,38 @@ def kernel_source_hash(unit: str = "step2d.hip") -> str:
 def kernel_unit(storage: str = "fp64", closure: bool = False) -> str:
     """The source unit of the kernel a profile of this storage covers."""
     return "closure.hip" if closure else "mom.hip" if storage == "moments" else "step2d.hip"
+
+
+def read_profile(name: str, unit: str):
+    """The key: value lines of profiles/<name>, or None if the file is missing
+    or the kernel's code has changed since it was written."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith("#"):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    return kv if kv.get("kernel_source_hash") == kernel_source_hash(unit) else None
+
+
+def moment_step_roofline(row):
+    """The moment-form step is bound by vector ALU issue, not HBM: its FP64
+    rate against the 78.6 TFLOP/s FP64 vector peak, with the VALU busy
+    fraction and instruction counts of its rocprofv3 profile (per node, so
+    they hold at any grid size)."""
+    kv = read_profile("d2v37_moments_2048_valu.txt", "mom.hip")
+    if kv is None or row is None:
+        return None
+    flops = float(kv["fp64_flops_per_node"])
+    achieved = row["MLUPS"] * 1e6 * flops / 1e12
+    return {"bound": "alu", "lattice": row["lattice"], "n": row["n"], "MLUPS": row["MLUPS"],
+            "fp64_flops_per_node": flops, "valu_insts_per_node": float(kv["valu_insts_per_node"]),
+            "achieved": round(achieved, 2), "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(achieved / FP64_PEAK_TFLOPS, 4),
+            "valu_busy_percent_2048": float(kv["valu_busy_percent"]),
+            "profile": "profiles/d2v37_moments_2048_valu.txt"}
 
 
 def read_traffic(name: str):
@@ -860,6 +893,8 @@ def main():
                  ("D2V17", 4096, "moments", False, 0), ("D2V37", 4096, "moments", False, 0)]
         out["per_lattice_hbm"] = [roofline_point(torch, b, wl, lat, n, st, steps=50, thermal=th, coll=co)
                                   for lat, n, st, th, co in cases]
+        mom = [r for r in out["per_lattice_hbm"] if r["storage"] == "moments" and r["lattice"] == "D2V37"]
+        out["roofline_moment_step"] = moment_step_roofline(mom[0] if mom else None)
     if not args.no_sweep:
         # 1024^2: buffers of 37-310 MB, inside or about the size of the 256 MiB
         # memory-side cache, so these are MLUPS only (no HBM fraction); the

@@ -114,3 +114,41 @@ def test_moments_rejected_where_populations_are_needed(orc, b):
     with pytest.raises(b.LbmError):
         b.lbm_closure_set(sim.ctx, theta, norm)
     sim.close()
+
+
+@pytest.mark.parametrize("name,n", [("D2V37", 1024), ("D2V17", 1024), ("D2V37", 2048)])
+def test_moments_full_size_sampled(orc, b, name, n):
+    """The moment form at the benchmark's grid sizes (its launch shape:
+    16-row blocks of 64 - 2R output columns, ragged at the right edge): init
+    + 2 steps, the rebuilt post-collision populations checked at 512 sampled
+    nodes (edges included) that the oracle evaluates one by one (gather the
+    neighbours' post-collision values, collide)."""
+    import torch
+
+    print(f"[case] moments {name} {n}x{n} sampled nodes", flush=True)
+    steps = 2
+    lat = orc.lattice(name)
+    u0, tau = wl.shear_layer_params(lat.cs2, n, 1e5)
+    rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+    noise = wl.uniform_noise(3, lat.Q, n, n)
+    sim = b.Simulation(name, n, n, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, flags=b.LBM_STORE_MOMENTS)
+    sim.step(steps)
+    f = sim.populations()
+    rng = np.random.default_rng(11)
+    ys = np.concatenate([[0, n - 1, 15, 16, 0], rng.integers(0, n, 507)])
+    xs = np.concatenate([[0, n - 1, 57, 58, n - 3], rng.integers(0, n, 507)])
+    got = f[:, torch.as_tensor(ys, device=f.device), torch.as_tensor(xs, device=f.device)].cpu().numpy()
+    sim.close()
+    del f
+
+    def post(ys_, xs_, t):
+        if t == 0:
+            f0 = orc.init_populations(lat, rho[ys_, xs_], ux[ys_, xs_], uy[ys_, xs_], None,
+                                      noise[:, ys_, xs_], 1e-8)
+            return orc.collide(lat, f0, tau)
+        pre = np.empty((lat.Q, len(ys_)))
+        for i, (cx, cy) in enumerate(lat.c):
+            pre[i] = post((ys_ - cy) % n, (xs_ - cx) % n, t - 1)[i]
+        return orc.collide(lat, pre, tau)
+
+    check(got, post(ys, xs, steps), 1e-13)
