@@ -34,10 +34,13 @@ STORAGE_FLAGS = {"fp64": 0, "fp32": 0x2, "bf16": 0x4, "moments": 0x8, "fp32d": 0
 STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp32d": 4}
 
 
-def bytes_per_node(q: int, storage: str) -> int:
+def bytes_per_node(q: int, storage: str, thermal: bool = False) -> int:
     """Algorithmic HBM bytes of one node update: every stored value read once
-    and written once (Q populations, or the six FP64 moments)."""
-    return 2 * 6 * 8 if storage == "moments" else 2 * q * STORAGE_BYTES[storage]
+    and written once (Q populations, or the six FP64 moments; ten for the
+    thermal moment state)."""
+    if storage == "moments":
+        return 2 * (10 if thermal else 6) * 8
+    return 2 * q * STORAGE_BYTES[storage]
 
 
 def _code_only(text: str) -> str:
@@ -551,9 +554,9 @@ def roofline_point(torch, b, wl, lattice, n, storage, steps=100, regions=5, ther
     bad = int(sim.moments(vorticity=False)["sums"][8])
     sim.close()
     med = float(np.median(ms))
-    bpl = bytes_per_node(meta["q"], storage) * n * n
+    bpl = bytes_per_node(meta["q"], storage, thermal) * n * n
     gbs = bpl / (med * 1e-3) / 1e9
-    buf = bpl // 2 if storage != "moments" else 6 * 8 * n * n
+    buf = bpl // 2
     return {"lattice": lattice, "storage": storage, "thermal": thermal,
             "collision": {0: "RR", 0x10: "PR", 0x20: "BGK"}[coll], "n": n,
             "buffer_MiB": round(buf / 2 ** 20, 1), "MLUPS": round(n * n / (med * 1e-3) / 1e6, 1),
@@ -700,6 +703,7 @@ def main():
     ap.add_argument("--lattice", default="D2V37")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--storage", default="fp64", choices=list(STORAGE_FLAGS))
+    ap.add_argument("--thermal", action="store_true", help="thermal form of the --only-headline workload (D2V37)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
@@ -821,16 +825,17 @@ def main():
         args.closure = "none"
         args.regions = 0
 
-    sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage)
+    sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage, thermal=args.thermal)
     wall, kms = time_steps(torch, sim, args.steps, args.warmup)
     med = time_regions(torch, sim, args.region_steps, args.regions) if args.regions > 0 else []
     mom = sim.moments()
-    buffer_mib = b.lbm_buffer_elems(args.lattice, args.n, args.n, STORAGE_FLAGS[args.storage]) * \
+    buffer_mib = b.lbm_buffer_elems(args.lattice, args.n, args.n,
+                                    STORAGE_FLAGS[args.storage] | (b.LBM_THERMAL if args.thermal else 0)) * \
         (8 if args.storage in ("fp64", "moments") else STORAGE_BYTES[args.storage]) / 2 ** 20
     sim.close()
     nodes = args.n * args.n
     mlups = nodes * args.steps / wall / 1e6
-    bytes_per_launch = bytes_per_node(meta["q"], args.storage) * nodes
+    bytes_per_launch = bytes_per_node(meta["q"], args.storage, args.thermal) * nodes
     kavg = kms * 1e-3
     achieved = bytes_per_launch / kavg / 1e9
     traffic = read_traffic(f"{args.lattice.lower()}_{args.storage}_{args.n}_traffic.txt")
@@ -848,7 +853,8 @@ def main():
         "dtype": "f32" if args.storage in ("fp32", "bf16") else "f64",
         "data": "synthetic",
         "config": {
-            "workload": f"{args.lattice} isothermal recursive-regularized shear layer {args.n}x{args.n}, "
+            "workload": f"{args.lattice} {'thermal' if args.thermal else 'isothermal'} recursive-regularized "
+                        f"shear layer {args.n}x{args.n}, "
                         f"{args.storage} populations, order {b.lbm_lattice_info(args.lattice)[2]}, "
                         "Re 1e5, Mach 0.1",
             "lattice": args.lattice, "nx": args.n, "ny": args.n, "storage": args.storage, "scheme": "pull",
@@ -890,10 +896,12 @@ def main():
                  ("D2V17", 3072, "fp32", False, 0), ("D2V37", 2048, "fp32", False, 0),
                  ("D2V37", 2048, "fp32d", False, 0),
                  ("D2V37", 4096, "bf16", False, 0), ("D2Q9", 4096, "moments", False, 0),
-                 ("D2V17", 4096, "moments", False, 0), ("D2V37", 4096, "moments", False, 0)]
+                 ("D2V17", 4096, "moments", False, 0), ("D2V37", 4096, "moments", False, 0),
+                 ("D2V37", 2048, "moments", True, 0)]
         out["per_lattice_hbm"] = [roofline_point(torch, b, wl, lat, n, st, steps=50, thermal=th, coll=co)
                                   for lat, n, st, th, co in cases]
-        mom = [r for r in out["per_lattice_hbm"] if r["storage"] == "moments" and r["lattice"] == "D2V37"]
+        mom = [r for r in out["per_lattice_hbm"]
+               if r["storage"] == "moments" and r["lattice"] == "D2V37" and not r["thermal"]]
         out["roofline_moment_step"] = moment_step_roofline(mom[0] if mom else None)
     if not args.no_sweep:
         # 1024^2: buffers of 37-310 MB, inside or about the size of the 256 MiB
@@ -906,7 +914,7 @@ def main():
                  ("D2V37", "fp64", True, 0), ("D2Q9", "fp32", False, 0), ("D2V17", "fp32", False, 0),
                  ("D2V37", "fp32", False, 0), ("D2V37", "fp32d", False, 0), ("D2V37", "bf16", False, 0),
                  ("D2Q9", "moments", False, 0),
-                 ("D2V17", "moments", False, 0), ("D2V37", "moments", False, 0)]
+                 ("D2V17", "moments", False, 0), ("D2V37", "moments", False, 0), ("D2V37", "moments", True, 0)]
         for lat, st, th, co in cases:
             s2, m2 = make_sim(b, wl, lat, args.n, st, thermal=th, coll=co, noise=False)
             s2.step(5)

@@ -33,12 +33,15 @@
  *   LBM_STORE_FP64 (default) keeps the plain populations f_i in double and does
  *   all arithmetic in double.  LBM_STORE_FP32 / LBM_STORE_BF16 keep the
  *   weight-shifted populations g_i = f_i - w_i in float / bfloat16 and do all
- *   arithmetic in float.  LBM_STORE_MOMENTS (isothermal recursive
- *   regularization only) keeps, per node, the six values (rho, u_x, u_y,
- *   a1^(2)_xx, a1^(2)_xy, a1^(2)_yy) of the pre-collision populations in
- *   double: with the recursion the post-collision populations are a function
- *   of these alone (Eq. GenRegCollision, Eq. MalaspinasRecursiveRelation), so
- *   a step rebuilds each pulled population from its source node's moments.
+ *   arithmetic in float.  LBM_STORE_MOMENTS (recursive regularization only)
+ *   keeps, per node, the six values (rho, u_x, u_y, a1^(2)_xx, a1^(2)_xy,
+ *   a1^(2)_yy) of the pre-collision populations in double: with the
+ *   recursion the post-collision populations are a function of these alone
+ *   (Eq. GenRegCollision, Eq. MalaspinasRecursiveRelation), so a step
+ *   rebuilds each pulled population from its source node's moments.  With
+ *   LBM_THERMAL (D2V37, App. C) the state is the ten raw moments
+ *   s_pq = sum_i f_i c_x^p c_y^q, p + q <= 3 (planes s00, s10, s01, s20, s11,
+ *   s02, s30, s21, s12, s03), which are all the thermal collision reads.
  *   The sequence of states equals that of LBM_STORE_FP64 up to rounding.
  *   LBM_STORE_FP32 | LBM_MATH_FP64 keeps the float storage of g_i and does
  *   the collision in double, so each value is rounded to float once per step
@@ -82,7 +85,7 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_THERMAL 0x1u        /* thermal/compressible form; D2V37 only          */
 #define LBM_STORE_FP32 0x2u     /* store f - w in float, float arithmetic          */
 #define LBM_STORE_BF16 0x4u     /* store f - w in bfloat16, float arithmetic       */
-#define LBM_STORE_MOMENTS 0x8u  /* store (rho, u, a1^(2)) in double; isothermal RR */
+#define LBM_STORE_MOMENTS 0x8u  /* store the collision's moments in double; RR     */
 #define LBM_COLL_PR 0x10u       /* projection-based regularization (Sec. II.E)     */
 #define LBM_COLL_BGK 0x20u      /* BGK collision (Sec. III.A)                      */
 #define LBM_EQ_INIT_ORDER2 0x100u /* initial f^(0) truncated at Hermite order 2    */

@@ -267,8 +267,8 @@ int validate(int lattice, int nx, int ny, double tau, int reg_order, uint32_t fl
         return fail(LBM_EINVAL, "LBM_MATH_FP64 goes with LBM_STORE_FP32");
     const uint32_t stores = flags & (LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS);
     if (stores & (stores - 1)) return fail(LBM_EINVAL, "two storage flags");
-    if ((flags & LBM_STORE_MOMENTS) && (flags & (LBM_THERMAL | LBM_COLL_PR | LBM_COLL_BGK | LBM_A13_PROJECTED)))
-        return fail(LBM_EINVAL, "the moment representation is isothermal recursive regularization only");
+    if ((flags & LBM_STORE_MOMENTS) && (flags & (LBM_COLL_PR | LBM_COLL_BGK)))
+        return fail(LBM_EINVAL, "the moment representation is recursive regularization only");
     if ((flags & LBM_COLL_PR) && (flags & LBM_COLL_BGK)) return fail(LBM_EINVAL, "two collision flags");
     if ((flags & LBM_THERMAL) && lattice != LBM_D2V37)
         return fail(LBM_EINVAL, "the thermal form needs the D2V37 lattice");
@@ -292,7 +292,7 @@ double neumaier(const double* x, int64_t n, int stride)
 // Bytes of one state buffer.
 int64_t store_bytes(const lbm_ctx* c)
 {
-    if (c->store == ST_MOM) return int64_t(sizeof(double)) * MOM_K * c->nx * c->ny;
+    if (c->store == ST_MOM) return int64_t(sizeof(double)) * (c->thermal ? MOM_KT : MOM_K) * c->nx * c->ny;
     const int64_t esz = (c->store == ST_F32 || c->store == ST_F32D) ? 4 : c->store == ST_BF16 ? 2 : 8;
     return esz * layout_elems(c->q, c->nx, c->ny * c->nz);
 }
@@ -358,7 +358,7 @@ int64_t lbm_buffer_elems(int lattice, int nx, int ny, uint32_t flags)
     if (!lattice_info(lattice, &li)) return fail(LBM_EINVAL, "unknown lattice");
     if (is_3d(lattice)) return fail(LBM_EINVAL, "3D lattice: use lbm_buffer_elems_3d");
     if (nx < 1 || ny < 1) return fail(LBM_EINVAL, "empty grid");
-    if (flags & LBM_STORE_MOMENTS) return int64_t(MOM_K) * nx * ny;
+    if (flags & LBM_STORE_MOMENTS) return int64_t((flags & LBM_THERMAL) ? MOM_KT : MOM_K) * nx * ny;
     return layout_elems(li.q, nx, ny);
 }
 

@@ -181,13 +181,12 @@ __device__ __forceinline__ void iso_recursion(T ux, T uy, T (&a1)[5][5])
     a1[0][4] = T(6) * uyy * yy;
 }
 
+// Steps 2-4 from the raw moments s[p][q] = sum_i v_i c_x^p c_y^q (orders up
+// to 2 for BGK, 3 for the thermal path, 4 for PR of rank 4).
 template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
-__device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k)
+__device__ __forceinline__ void coeffs_from_moments(const T (&s)[5][5], NodeCoeffs<T>& k)
 {
     constexpr T cs2 = T(L::cs2);
-    T s[5][5];
-    raw_moments<L, T>(v, s);
-
     const T s00 = s[0][0];
     const T rho = SHIFTED ? T(1) + s00 : s00;
     const T drho = SHIFTED ? s00 : s00 - T(1);
@@ -294,6 +293,15 @@ __device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k
         a1[1][3] = T(3) * uy * a1[1][2] + ux * a1[0][3] + T(3) * by * xy - T(3) * uxy * yy;
         a1[0][4] = T(4) * uy * a1[0][3] + T(6) * by * yy;
     }
+}
+
+// Steps 1-4 of one node from its populations v.
+template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
+__device__ __forceinline__ void node_coeffs(const T (&v)[L::Q], NodeCoeffs<T>& k)
+{
+    T s[5][5];
+    raw_moments<L, T>(v, s);
+    coeffs_from_moments<L, T, COLL, THERMAL, SHIFTED, A13P>(s, k);
 }
 
 // Step 5: relax and rebuild the populations,

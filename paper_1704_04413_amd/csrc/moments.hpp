@@ -13,6 +13,13 @@
 //
 // State layout: six FP64 planes [m][y][x], m = rho, ux, uy, a1_xx, a1_xy,
 // a1_yy of the pre-collision populations.
+//
+// Thermal form (D2V37, App. C): the collision reads the raw moments of the
+// pre-collision populations up to order three and nothing else (rho, u, theta
+// from orders 0-2, a1^(2) by projection, a1^(3) from the projected third
+// moments and the gradient estimates, a1^(4) by the recursion), so those ten
+// values are the state: planes m = s00, s10, s01, s20, s11, s02, s30, s21,
+// s12, s03 with s_pq = sum_i f_i c_x^p c_y^q.
 #pragma once
 
 #include "collide.hpp"
@@ -303,6 +310,51 @@ __device__ __forceinline__ void class_from_moments(const double (&m)[MOM_K], con
     }
 }
 
+// Exponents (p, q) of the raw moments of the thermal state, plane by plane.
+constexpr int TH_P[MOM_KT] = { 0, 1, 0, 2, 1, 0, 3, 2, 1, 0 };
+constexpr int TH_Q[MOM_KT] = { 0, 0, 1, 0, 1, 2, 0, 1, 2, 3 };
+
+// Thermal collision of a node from its raw moments m: the population form's
+// steps 2-4 (coeffs_from_moments), then C[a][b] = a0 + k_n a1 of rank n, the
+// factors k_n zero above the regularization order.
+template <class L, bool A13P>
+__device__ __forceinline__ void thermal_coeffs(const double (&m)[MOM_KT], const Relax& rx, double (&C)[5][5])
+{
+    double s[5][5];
+    static_for<5>([&](auto a) { static_for<5>([&](auto b) { s[a][b] = 0.0; }); });
+    static_for<MOM_KT>([&](auto M) { s[TH_P[M]][TH_Q[M]] = m[M]; });
+    NodeCoeffs<double> k;
+    coeffs_from_moments<L, double, COLL_RR, true, false, A13P>(s, k);
+    static_for<5>([&](auto A) {
+        static_for<5>([&](auto B) {
+            constexpr int r = int(A) + int(B);
+            if constexpr (L::basis(int(A), int(B))) {
+                if constexpr (r == 2)
+                    C[A][B] = k.C[A][B] + rx.k2 * k.a1[A][B];
+                else if constexpr (r == 3)
+                    C[A][B] = k.C[A][B] + rx.k3 * k.a1[A][B];
+                else if constexpr (r == 4)
+                    C[A][B] = k.C[A][B] + rx.k4 * k.a1[A][B];
+                else
+                    C[A][B] = k.C[A][B];
+            }
+        });
+    });
+}
+
+// Makes the values materialise here (an empty asm that reads and writes
+// them): code that computes them cannot be moved past this point.
+template <int N>
+__device__ __forceinline__ void pin(double (&a)[N])
+{
+    static_assert(N == 6 || N == 10, "six or ten sums");
+    if constexpr (N == 6)
+        asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]));
+    else
+        asm volatile("" : "+v"(a[0]), "+v"(a[1]), "+v"(a[2]), "+v"(a[3]), "+v"(a[4]), "+v"(a[5]), "+v"(a[6]),
+                     "+v"(a[7]), "+v"(a[8]), "+v"(a[9]));
+}
+
 // Value of v held by lane (lane - D) of the wave (D in [-3, 3]), by |D|
 // one-lane wave shifts of both halves (DPP wave_shr:1 / wave_shl:1); lanes
 // whose source is outside the wave get zero.
@@ -323,14 +375,18 @@ __device__ __forceinline__ double lane_from(double v)
     }
 }
 
-// Eight waves per SIMD: 64 VGPRs, and the 67.6 KB of staged moments of a
-// 16-row block let two blocks share a CU.
-template <class L, int ORDER, bool PO>
-__global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(8))) void k_mom_step(
+// Isothermal form: eight waves per SIMD (64 VGPRs), and the 67.6 KB of staged
+// moments of a 16-row block let two blocks share a CU.  Thermal form (TH):
+// ten staged planes, 112.6 KB, one block and four waves per SIMD.  The
+// moments gathered at a node are its raw sums s_pq (p + q <= 2, or 3 for the
+// thermal state), in the plane order of TH_P / TH_Q.
+template <class L, int ORDER, bool PO, bool TH = false, bool A13P = false>
+__global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(TH ? 4 : 8))) void k_mom_step(
     const double* __restrict__ min, double* __restrict__ mout, int nx, int ny, int bx_blocks, Relax rx)
 {
     constexpr int R = L::R, OX = BX - 2 * R, SH = MOM_ROWS + 2 * R, NC = 2 * R + 1;
-    __shared__ double sm[MOM_K][SH][BX];
+    constexpr int NV = TH ? MOM_KT : MOM_K, PMAX = TH ? 3 : 2;
+    __shared__ double sm[NV][SH][BX];
     const int x0 = int(blockIdx.x % unsigned(bx_blocks)) * OX;
     const int y0 = int(blockIdx.x / unsigned(bx_blocks)) * MOM_ROWS;
     const int64_t n = int64_t(nx) * ny;
@@ -352,59 +408,74 @@ __global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(8)
             gy = ((gy % ny) + ny) % ny;
         }
         const int64_t g = int64_t(gy) * nx + gx;
-        static_for<MOM_K>([&](auto M) { sm[M][ly][lx] = min[int64_t(M) * n + g]; });
+        static_for<NV>([&](auto M) { sm[M][ly][lx] = min[int64_t(M) * n + g]; });
     }
     __syncthreads();
     const int x = x0 + lane - R, y = y0 + ty;
-    double r = 0, jx = 0, jy = 0, pxx = 0, pxy = 0, pyy = 0;
+    double acc[NV];
+    static_for<NV>([&](auto M) { acc[M] = 0.0; });
     static_for<NC>([&](auto KI) {
         constexpr int K = int(KI) - R;
-        double mv[MOM_K];
-        static_for<MOM_K>([&](auto M) { mv[M] = sm[M][ty - K + R][lane]; });
-        // row sums of the class at this lane: s0 = sum f, s1 = sum c_x f,
-        // s2 = sum c_x^2 f over the populations (c_x, K) arriving here
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0;
-        class_from_moments<L, K, ORDER, PO>(mv, rx, [&](auto CX, double f) {
+        double mv[NV];
+        static_for<NV>([&](auto M) { mv[M] = sm[M][ty - K + R][lane]; });
+        // row sums of the class at this lane, rs[p] = sum c_x^p f over the
+        // populations (c_x, K) arriving here
+        double rs[PMAX + 1];
+        static_for<PMAX + 1>([&](auto P) { rs[P] = 0.0; });
+        auto add = [&](auto CX, double f) {
             constexpr int cx = decltype(CX)::value;
             const double g = lane_from<cx>(f);
-            s0 += g;
-            if constexpr (cx != 0) {
-                s1 += double(cx) * g;
-                s2 += double(cx * cx) * g;
-            }
-        });
-        r += s0;
-        jx += s1;
-        pxx += s2;
-        if constexpr (K != 0) {
-            jy += double(K) * s0;
-            pxy += double(K) * s1;
-            pyy += double(K * K) * s0;
+            rs[0] += g;
+            if constexpr (cx != 0)
+                static_for<PMAX>([&](auto P) {
+                    constexpr double cp = ipow(double(cx), int(P) + 1);
+                    rs[int(P) + 1] += cp * g;
+                });
+        };
+        if constexpr (TH) {
+            double C[5][5];
+            thermal_coeffs<L, A13P>(mv, rx, C);
+            class_pops<L, K>(C, add);
+        } else {
+            class_from_moments<L, K, ORDER, PO>(mv, rx, add);
         }
+        static_for<NV>([&](auto S) {
+            constexpr int p = TH_P[S], q = TH_Q[S];
+            constexpr double kq = ipow(double(K), q);
+            if constexpr (q == 0)
+                acc[S] += rs[p];
+            else if constexpr (K != 0)
+                acc[S] += kq * rs[p];
+        });
         // one class at a time: the sums are taken here (not sunk to the end
         // with every class's row sums kept alive), and the scheduler does not
         // interleave classes
-        asm volatile("" : "+v"(r), "+v"(jx), "+v"(jy), "+v"(pxx), "+v"(pxy), "+v"(pyy));
+        pin(acc);
         __builtin_amdgcn_sched_barrier(0);
     });
     if (lane < R || lane >= BX - R || x >= nx || y >= ny) return;
-    const double ux = jx / r, uy = jy / r;
-    const double m[MOM_K] = { r, ux, uy, pxx - r * L::cs2 - r * ux * ux, pxy - r * ux * uy,
-                              pyy - r * L::cs2 - r * uy * uy };
     const int64_t here = int64_t(y) * nx + x;
-    static_for<MOM_K>([&](auto M) { __builtin_nontemporal_store(m[M], mout + int64_t(M) * n + here); });
+    if constexpr (TH) {
+        static_for<NV>([&](auto M) { __builtin_nontemporal_store(acc[M], mout + int64_t(M) * n + here); });
+    } else {
+        const double r = acc[0], jx = acc[1], jy = acc[2], pxx = acc[3], pxy = acc[4], pyy = acc[5];
+        const double ux = jx / r, uy = jy / r;
+        const double m[MOM_K] = { r, ux, uy, pxx - r * L::cs2 - r * ux * ux, pxy - r * ux * uy,
+                                  pyy - r * L::cs2 - r * uy * uy };
+        static_for<MOM_K>([&](auto M) { __builtin_nontemporal_store(m[M], mout + int64_t(M) * n + here); });
+    }
 }
 
 // Initial state: the moments of f^(0) [+ f^(1)] + noise (the populations the
 // population form starts from, before its first collision).
-template <class L>
+template <class L, bool TH = false>
 __global__ __launch_bounds__(256) void k_mom_init(InitArgs a)
 {
     const int64_t n = int64_t(a.lay.nx) * a.lay.ny;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     double f[L::Q];
-    equilibrium_node<L, double, false>(a.rho[k], a.ux[k], a.uy[k], 1.0, a.eq_order, f);
+    equilibrium_node<L, double, false>(a.rho[k], a.ux[k], a.uy[k], TH ? a.theta[k] : 1.0, a.eq_order, f);
     if (a.grad) {
         const double du[2][2] = { { a.grad[k], a.grad[2 * n + k] }, { a.grad[n + k], a.grad[3 * n + k] } };
         double f1[L::Q];
@@ -412,20 +483,46 @@ __global__ __launch_bounds__(256) void k_mom_init(InitArgs a)
         static_for<L::Q>([&](auto I) { f[I] += f1[I]; });
     }
     if (a.noise) static_for<L::Q>([&](auto I) { f[I] += a.noise_amp * L::v.w[I] * a.noise[int64_t(I) * n + k]; });
-    double m[MOM_K];
-    node_state<L>(f, m);
     double* out = static_cast<double*>(a.f);
-    static_for<MOM_K>([&](auto M) { out[int64_t(M) * n + k] = m[M]; });
+    if constexpr (TH) {
+        static_for<MOM_KT>([&](auto M) {
+            double sum = 0.0;
+            static_for<L::Q>([&](auto I) {
+                constexpr double c = ipow(double(L::v.cx[I]), TH_P[M]) * ipow(double(L::v.cy[I]), TH_Q[M]);
+                sum += c * f[I];
+            });
+            out[int64_t(M) * n + k] = sum;
+        });
+    } else {
+        double m[MOM_K];
+        node_state<L>(f, m);
+        static_for<MOM_K>([&](auto M) { out[int64_t(M) * n + k] = m[M]; });
+    }
 }
 
 // Post-collision populations of node k (what the population form stores).
-template <class L, int ORDER>
+template <class L, int ORDER, bool TH = false, bool A13P = false>
 __device__ __forceinline__ void mom_node_populations(const double* __restrict__ m, int64_t n, int64_t k,
                                                      const Relax& rx, double (&v)[L::Q])
 {
-    const double r = m[k], ux = m[n + k], uy = m[2 * n + k];
-    const double axx = m[3 * n + k], axy = m[4 * n + k], ayy = m[5 * n + k];
-    static_for<L::Q>([&](auto I) { v[I] = mom_pop<L, int(I), ORDER, true>(r, ux, uy, axx, axy, ayy, rx); });
+    if constexpr (TH) {
+        double mv[MOM_KT], C[5][5];
+        static_for<MOM_KT>([&](auto M) { mv[M] = m[int64_t(M) * n + k]; });
+        thermal_coeffs<L, A13P>(mv, rx, C);
+        static_for<5>([&](auto A) {
+            static_for<5>([&](auto B) {
+                if constexpr (L::basis(int(A), int(B))) {
+                    constexpr double nrm = inv_norm<L>(int(A), int(B));
+                    C[A][B] *= nrm;
+                }
+            });
+        });
+        reconstruct<L, double>(C, v);
+    } else {
+        const double r = m[k], ux = m[n + k], uy = m[2 * n + k];
+        const double axx = m[3 * n + k], axy = m[4 * n + k], ayy = m[5 * n + k];
+        static_for<L::Q>([&](auto I) { v[I] = mom_pop<L, int(I), ORDER, true>(r, ux, uy, axx, axy, ayy, rx); });
+    }
 }
 
 } // namespace rr

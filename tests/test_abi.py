@@ -47,6 +47,8 @@ def test_buffer_elems_cover_the_grid():
         for nx, ny in ((1, 1), (3, 3), (128, 128), (1000, 7), (1024, 1024)):
             assert b.lbm_buffer_elems(name, nx, ny) >= q * nx * ny
             assert b.lbm_buffer_elems(name, nx, ny, b.LBM_STORE_MOMENTS) == 6 * nx * ny
+    # thermal moment state: the ten raw moments of order <= 3
+    assert b.lbm_buffer_elems("D2V37", 9, 5, b.LBM_STORE_MOMENTS | b.LBM_THERMAL) == 10 * 9 * 5
     with pytest.raises(b.LbmError):
         b.lbm_buffer_elems(7, 4, 4)
     with pytest.raises(b.LbmError):
@@ -82,7 +84,8 @@ class FakePtr:
     (dict(flags=b.LBM_THERMAL, grad=True), b.LBM_EINVAL),  # the f^(1) start is isothermal
     (dict(flags=b.LBM_STORE_MOMENTS | b.LBM_STORE_FP32), b.LBM_EINVAL),
     (dict(flags=b.LBM_STORE_MOMENTS | b.LBM_COLL_PR), b.LBM_EINVAL),  # moments: RR only
-    (dict(flags=b.LBM_STORE_MOMENTS | b.LBM_THERMAL), b.LBM_EINVAL),
+    (dict(flags=b.LBM_STORE_MOMENTS | b.LBM_COLL_BGK), b.LBM_EINVAL),
+    (dict(lattice=0, flags=b.LBM_STORE_MOMENTS | b.LBM_THERMAL), b.LBM_EINVAL),  # thermal needs D2V37
 ])
 def test_init_rejects_invalid_arguments(args, code):
     p = dict(lattice=2, nx=8, ny=8, tau=0.6, reg_order=4, flags=0)

@@ -33,7 +33,7 @@ def make(b, lattice, n, flags, re=3e4, seed=4):
     return b.Simulation(lattice, n, n, tau, rho, ux, uy, theta=theta, noise=noise, noise_amp=1e-8, flags=flags)
 
 
-CASES = [("D2V37", 0), ("D2V37", 0x2), ("D2V37", 0x4), ("D2Q9", 0x2), ("D2V37", 0x1), ("D2V17", 0x8)]
+CASES = [("D2V37", 0), ("D2V37", 0x2), ("D2V37", 0x4), ("D2Q9", 0x2), ("D2V37", 0x1), ("D2V17", 0x8), ("D2V37", 0x9)]
 
 
 @pytest.mark.parametrize("lattice,flags", CASES)

@@ -152,3 +152,92 @@ def test_moments_full_size_sampled(orc, b, name, n):
         return orc.collide(lat, pre, tau)
 
     check(got, post(ys, xs, steps), 1e-13)
+
+
+# ------------------------------------------------------------ thermal form
+
+
+@pytest.mark.parametrize("a13", [False, True])
+def test_thermal_moments_sod_against_oracle(orc, b, a13):
+    """Thermal D2V37 (App. C) in the moment representation, ten raw moments
+    per node: the Sod tube of the population-form test (400 x 4, tau 0.6,
+    40 steps; 4 rows take the modulo wrap of the staged block), populations
+    rebuilt from the moments against the oracle, same bound (1e-11 for
+    |f| <= 3.3), and theta against the oracle's."""
+    print(f"[case] thermal moments sod a13_projected={a13}", flush=True)
+    lat = orc.lattice("D2V37")
+    nx, ny, tau, steps = 400, 4, 0.6, 40
+    rho, ux, uy, th = wl.sod_fields(nx, ny)
+    f0 = orc.init_populations(lat, rho, ux, uy, th)
+    flags = b.LBM_STORE_MOMENTS | b.LBM_THERMAL | (b.LBM_A13_PROJECTED if a13 else 0)
+    sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=flags)
+    assert b.lbm_buffer_elems("D2V37", nx, ny, flags) == 10 * nx * ny
+    sim.step(steps)
+    got = sim.populations().cpu().numpy()
+    m = sim.moments()
+    sim.close()
+    want = orc.collide(lat, orc.step(lat, f0, tau, steps, thermal=True, a13_raw=a13), tau, thermal=True,
+                       a13_raw=a13)
+    check(got, want, 1e-11)
+    _, _, _, t = orc.moments(lat, want, thermal=True)
+    np.testing.assert_allclose(m["theta"].cpu().numpy(), t, rtol=0, atol=2e-9)
+
+
+def test_thermal_moments_shear_with_noise(orc, b):
+    """Thermal shear layer with a temperature perturbation and seeded noise on
+    a ragged 70 x 45 grid, RR at order 3 and 4."""
+    lat = orc.lattice("D2V37")
+    nx, ny = 70, 45
+    u0, tau = wl.shear_layer_params(lat.cs2, nx, 3e3)
+    rho, ux, uy = wl.shear_layer_fields(nx, ny, u0, k=20.0)
+    th = 1.0 + 0.05 * np.cos(2 * np.pi * (np.arange(ny)[:, None] + 0.5) / ny) * np.ones((1, nx))
+    noise = wl.uniform_noise(4, lat.Q, ny, nx)
+    f0 = orc.init_populations(lat, rho, ux, uy, th, noise, 1e-8)
+    for order in (3, 4):
+        print(f"[case] thermal moments shear RR{order} {nx}x{ny}", flush=True)
+        sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, noise=noise, noise_amp=1e-8,
+                           flags=b.LBM_STORE_MOMENTS | b.LBM_THERMAL, reg_order=order)
+        sim.step(9)
+        got = sim.populations().cpu().numpy()
+        sim.close()
+        want = orc.collide(lat, orc.step(lat, f0, tau, 9, thermal=True, order=order), tau, thermal=True,
+                           order=order)
+        check(got, want, 1e-12)
+
+
+def test_thermal_moments_per_order_relaxation(orc, b):
+    """Pr = 0.5 on the Sod tube: rank 3 relaxed with its own time; the state is
+    the pre-collision moments, so every rebuild uses the times in force."""
+    print("[case] thermal moments per-order relaxation", flush=True)
+    lat = orc.lattice("D2V37")
+    nx, ny, tau, tau3 = 400, 4, 0.6, 0.7
+    rho, ux, uy, th = wl.sod_fields(nx, ny)
+    sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_STORE_MOMENTS | b.LBM_THERMAL)
+    sim.set_relaxation(tau3, tau)
+    sim.step(30)
+    got = sim.populations().cpu().numpy()
+    sim.close()
+    f0 = orc.init_populations(lat, rho, ux, uy, th)
+    g = orc.step(lat, f0, tau, 30, thermal=True, tau3=tau3, tau4=tau)
+    check(got, orc.collide(lat, g, tau, thermal=True, tau3=tau3, tau4=tau), 1e-11)
+
+
+def test_thermal_moments_follow_the_population_form(orc, b):
+    """200 steps of the Sod tube on 800 x 20: fields and diagnostics of both
+    representations agree."""
+    print("[case] thermal moments vs populations 800x20 x 200", flush=True)
+    nx, ny, tau = 800, 20, 0.6
+    rho, ux, uy, th = wl.sod_fields(nx, ny)
+    a = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_STORE_MOMENTS | b.LBM_THERMAL)
+    p = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_THERMAL)
+    a.step(200)
+    p.step(200)
+    check(a.populations().cpu().numpy(), p.populations().cpu().numpy(), 1e-10, "populations vs population form")
+    ma, mp = a.moments(), p.moments()
+    for key in ("rho", "ux", "uy", "theta"):
+        check(ma[key].cpu().numpy(), mp[key].cpu().numpy(), 1e-10, key)
+    sa, sp = np.asarray(ma["sums"]), np.asarray(mp["sums"])
+    np.testing.assert_allclose(sa[[0, 3]], sp[[0, 3]], rtol=1e-12)
+    assert sa[8] == sp[8] == 0
+    a.close()
+    p.close()
