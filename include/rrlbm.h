@@ -39,9 +39,11 @@
  *   recursion the post-collision populations are a function of these alone
  *   (Eq. GenRegCollision, Eq. MalaspinasRecursiveRelation), so a step
  *   rebuilds each pulled population from its source node's moments.  With
- *   LBM_THERMAL (D2V37, App. C) the state is the ten raw moments
- *   s_pq = sum_i f_i c_x^p c_y^q, p + q <= 3 (planes s00, s10, s01, s20, s11,
- *   s02, s30, s21, s12, s03), which are all the thermal collision reads.
+ *   LBM_THERMAL (D2V37, App. C) the collision reads the populations only
+ *   through their raw moments of order <= 3, and the state is the eleven
+ *   values they give before rank 4: rho, u_x, u_y, sig = (theta - 1) c_s^2,
+ *   a1^(2)_xx, a1^(2)_xy, a1^(2)_yy, a1^(3)_xxx, a1^(3)_xxy, a1^(3)_xyy,
+ *   a1^(3)_yyy (planes in that order).
  *   The sequence of states equals that of LBM_STORE_FP64 up to rounding.
  *   LBM_STORE_FP32 | LBM_MATH_FP64 keeps the float storage of g_i and does
  *   the collision in double, so each value is rounded to float once per step

@@ -181,6 +181,37 @@ __device__ __forceinline__ void iso_recursion(T ux, T uy, T (&a1)[5][5])
     a1[0][4] = T(6) * uyy * yy;
 }
 
+// Equilibrium coefficients C[kx][ky] = rho m_kx(ux) m_ky(uy) over the basis
+// (not yet normalised; C[0][0] = rho, entries off the basis zero).
+template <class L, class T>
+__device__ __forceinline__ void eq_coeffs(T rho, T ux, T uy, T sig, T (&C)[5][5])
+{
+    T mx[5], my[5];
+    eq_factors<T>(ux, sig, mx);
+    eq_factors<T>(uy, sig, my);
+    zero_coeffs<L, T>(C);
+    static_for<5>([&](auto KX) {
+        static_for<5>([&](auto KY) {
+            if constexpr (L::basis(int(KX), int(KY)) && int(KX) + int(KY) >= 1) C[KX][KY] = rho * mx[KX] * my[KY];
+        });
+    });
+    C[0][0] = rho;
+}
+
+// Rank 4 of the thermal recursion (App. C) from a1^(2), a1^(3), u and
+// sig = (theta - 1) c_s^2.
+template <class T>
+__device__ __forceinline__ void thermal_rank4(T ux, T uy, T sig, T (&a1)[5][5])
+{
+    const T xx = a1[2][0], xy = a1[1][1], yy = a1[0][2];
+    const T bx = sig - ux * ux, by = sig - uy * uy, uxy = ux * uy;
+    a1[4][0] = T(4) * ux * a1[3][0] + T(6) * bx * xx;
+    a1[3][1] = T(3) * ux * a1[2][1] + uy * a1[3][0] + T(3) * bx * xy - T(3) * uxy * xx;
+    a1[2][2] = T(2) * (ux * a1[1][2] + uy * a1[2][1]) + bx * yy + by * xx - T(4) * uxy * xy;
+    a1[1][3] = T(3) * uy * a1[1][2] + ux * a1[0][3] + T(3) * by * xy - T(3) * uxy * yy;
+    a1[0][4] = T(4) * uy * a1[0][3] + T(6) * by * yy;
+}
+
 // Steps 2-4 from the raw moments s[p][q] = sum_i v_i c_x^p c_y^q (orders up
 // to 2 for BGK, 3 for the thermal path, 4 for PR of rank 4).
 template <class L, class T, int COLL, bool THERMAL, bool SHIFTED, bool A13P>
@@ -210,18 +241,7 @@ __device__ __forceinline__ void coeffs_from_moments(const T (&s)[5][5], NodeCoef
         sig = cs2 * thm1;
     }
     k.sig = sig;
-    T mx[5], my[5];
-    eq_factors<T>(ux, sig, mx);
-    eq_factors<T>(uy, sig, my);
-
-    zero_coeffs<L, T>(k.C);
-    // equilibrium part (a1^(0) = a1^(1) = 0)
-    static_for<5>([&](auto KX) {
-        static_for<5>([&](auto KY) {
-            if constexpr (L::basis(int(KX), int(KY)) && int(KX) + int(KY) >= 1)
-                k.C[KX][KY] = rho * mx[KX] * my[KY];
-        });
-    });
+    eq_coeffs<L, T>(rho, ux, uy, sig, k.C);
     k.C[0][0] = SHIFTED ? drho : rho;
 
     auto& C = k.C;
@@ -286,12 +306,7 @@ __device__ __forceinline__ void coeffs_from_moments(const T (&s)[5][5], NodeCoef
             a1[1][2] = T(2) * uy * xy + ux * yy - gx;
             a1[0][3] = T(3) * (uy * yy - gy);
         }
-        const T bx = sig - ux * ux, by = sig - uy * uy, uxy = ux * uy;
-        a1[4][0] = T(4) * ux * a1[3][0] + T(6) * bx * xx;
-        a1[3][1] = T(3) * ux * a1[2][1] + uy * a1[3][0] + T(3) * bx * xy - T(3) * uxy * xx;
-        a1[2][2] = T(2) * (ux * a1[1][2] + uy * a1[2][1]) + bx * yy + by * xx - T(4) * uxy * xy;
-        a1[1][3] = T(3) * uy * a1[1][2] + ux * a1[0][3] + T(3) * by * xy - T(3) * uxy * yy;
-        a1[0][4] = T(4) * uy * a1[0][3] + T(6) * by * yy;
+        thermal_rank4<T>(ux, uy, sig, a1);
     }
 }
 

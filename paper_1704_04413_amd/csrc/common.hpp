@@ -88,7 +88,7 @@ struct InstDesc {
 };
 
 constexpr int MOM_K = 6;    // values per node of the moment representation
-constexpr int MOM_KT = 10;  // values per node of the thermal moment representation
+constexpr int MOM_KT = 11;  // values per node of the thermal moment representation
 constexpr int MOM_NS = 8;   // per-block partial sums of the 2D moments kernel
 constexpr int VORT_NS = 2;  // per-block partial sums of the vorticity kernel
 constexpr int MOM3_NS = 8;  // per-block partial sums of the 3D moments kernel

@@ -61,7 +61,7 @@ hipError_t launch(const lbm_ctx* c, int what, const void* fin, void* fout, const
     const double* m = static_cast<const double*>(c->buf[c->cur]);
     const dim3 grid(unsigned((n + 255) / 256)), block(256);
     switch (what) {
-    case 0: k_mom_init<L, TH><<<grid, block, 0, c->stream>>>(*ia); break;
+    case 0: k_mom_init<L, TH, A13P><<<grid, block, 0, c->stream>>>(*ia); break;
     case 1: k_mom_populations<L, ORDER, TH, A13P><<<grid, block, 0, c->stream>>>(m, n, rx, out); break;
     case 2:
         k_mom_moments<L, ORDER, TH, A13P>

@@ -14,12 +14,14 @@
 // State layout: six FP64 planes [m][y][x], m = rho, ux, uy, a1_xx, a1_xy,
 // a1_yy of the pre-collision populations.
 //
-// Thermal form (D2V37, App. C): the collision reads the raw moments of the
-// pre-collision populations up to order three and nothing else (rho, u, theta
-// from orders 0-2, a1^(2) by projection, a1^(3) from the projected third
-// moments and the gradient estimates, a1^(4) by the recursion), so those ten
-// values are the state: planes m = s00, s10, s01, s20, s11, s02, s30, s21,
-// s12, s03 with s_pq = sum_i f_i c_x^p c_y^q.
+// Thermal form (D2V37, App. C): the collision reads the pre-collision
+// populations only through their raw moments of order up to three (rho, u,
+// theta from orders 0-2, a1^(2) by projection, a1^(3) from the projected
+// third moments and the gradient estimates, a1^(4) by the recursion).  The
+// state is what that gives before rank 4: planes m = rho, ux, uy,
+// sig = (theta - 1) c_s^2, a1_xx, a1_xy, a1_yy, a1_xxx, a1_xxy, a1_xyy,
+// a1_yyy, computed once per node from its gathered raw moments; every pull
+// then rebuilds only the equilibrium and rank 4.
 #pragma once
 
 #include "collide.hpp"
@@ -310,33 +312,50 @@ __device__ __forceinline__ void class_from_moments(const double (&m)[MOM_K], con
     }
 }
 
-// Exponents (p, q) of the raw moments of the thermal state, plane by plane.
-constexpr int TH_P[MOM_KT] = { 0, 1, 0, 2, 1, 0, 3, 2, 1, 0 };
-constexpr int TH_Q[MOM_KT] = { 0, 0, 1, 0, 1, 2, 0, 1, 2, 3 };
+// Exponents (p, q) of the raw moments a thermal step gathers (p + q <= 3);
+// the first six are the isothermal step's.
+constexpr int TH_NS = 10;
+constexpr int TH_P[TH_NS] = { 0, 1, 0, 2, 1, 0, 3, 2, 1, 0 };
+constexpr int TH_Q[TH_NS] = { 0, 0, 1, 0, 1, 2, 0, 1, 2, 3 };
 
-// Thermal collision of a node from its raw moments m: the population form's
-// steps 2-4 (coeffs_from_moments), then C[a][b] = a0 + k_n a1 of rank n, the
-// factors k_n zero above the regularization order.
+// Thermal state of a node from its raw moments: the population form's steps
+// 2-4 (coeffs_from_moments), kept up to rank 3.
 template <class L, bool A13P>
-__device__ __forceinline__ void thermal_coeffs(const double (&m)[MOM_KT], const Relax& rx, double (&C)[5][5])
+__device__ __forceinline__ void thermal_state(const double (&sums)[TH_NS], double (&m)[MOM_KT])
 {
     double s[5][5];
     static_for<5>([&](auto a) { static_for<5>([&](auto b) { s[a][b] = 0.0; }); });
-    static_for<MOM_KT>([&](auto M) { s[TH_P[M]][TH_Q[M]] = m[M]; });
+    static_for<TH_NS>([&](auto M) { s[TH_P[M]][TH_Q[M]] = sums[M]; });
     NodeCoeffs<double> k;
     coeffs_from_moments<L, double, COLL_RR, true, false, A13P>(s, k);
+    const double out[MOM_KT] = { k.rho,      k.ux,       k.uy,       k.sig,      k.a1[2][0], k.a1[1][1],
+                                 k.a1[0][2], k.a1[3][0], k.a1[2][1], k.a1[1][2], k.a1[0][3] };
+    static_for<MOM_KT>([&](auto M) { m[M] = out[M]; });
+}
+
+// Coefficients C[a][b] = a0 + k_n a1 of rank n of a node in the thermal
+// state m: the equilibrium with theta, a1^(4) by the thermal recursion, the
+// factors k_n zero above the regularization order.
+template <class L>
+__device__ __forceinline__ void thermal_coeffs(const double (&m)[MOM_KT], const Relax& rx, double (&C)[5][5])
+{
+    const double ux = m[1], uy = m[2], sig = m[3];
+    eq_coeffs<L, double>(m[0], ux, uy, sig, C);
+    double a1[5][5];
+    a1[2][0] = m[4];
+    a1[1][1] = m[5];
+    a1[0][2] = m[6];
+    a1[3][0] = m[7];
+    a1[2][1] = m[8];
+    a1[1][2] = m[9];
+    a1[0][3] = m[10];
+    thermal_rank4<double>(ux, uy, sig, a1);
     static_for<5>([&](auto A) {
         static_for<5>([&](auto B) {
             constexpr int r = int(A) + int(B);
-            if constexpr (L::basis(int(A), int(B))) {
-                if constexpr (r == 2)
-                    C[A][B] = k.C[A][B] + rx.k2 * k.a1[A][B];
-                else if constexpr (r == 3)
-                    C[A][B] = k.C[A][B] + rx.k3 * k.a1[A][B];
-                else if constexpr (r == 4)
-                    C[A][B] = k.C[A][B] + rx.k4 * k.a1[A][B];
-                else
-                    C[A][B] = k.C[A][B];
+            if constexpr (L::basis(int(A), int(B)) && r >= 2) {
+                const double kr = r == 2 ? rx.k2 : r == 3 ? rx.k3 : rx.k4;
+                C[A][B] += kr * a1[A][B];
             }
         });
     });
@@ -377,15 +396,15 @@ __device__ __forceinline__ double lane_from(double v)
 
 // Isothermal form: eight waves per SIMD (64 VGPRs), and the 67.6 KB of staged
 // moments of a 16-row block let two blocks share a CU.  Thermal form (TH):
-// ten staged planes, 112.6 KB, one block and four waves per SIMD.  The
+// eleven staged planes, 123.9 KB, one block and four waves per SIMD.  The
 // moments gathered at a node are its raw sums s_pq (p + q <= 2, or 3 for the
-// thermal state), in the plane order of TH_P / TH_Q.
+// thermal state), in the order of TH_P / TH_Q.
 template <class L, int ORDER, bool PO, bool TH = false, bool A13P = false>
 __global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(TH ? 4 : 8))) void k_mom_step(
     const double* __restrict__ min, double* __restrict__ mout, int nx, int ny, int bx_blocks, Relax rx)
 {
     constexpr int R = L::R, OX = BX - 2 * R, SH = MOM_ROWS + 2 * R, NC = 2 * R + 1;
-    constexpr int NV = TH ? MOM_KT : MOM_K, PMAX = TH ? 3 : 2;
+    constexpr int NV = TH ? MOM_KT : MOM_K, NA = TH ? TH_NS : MOM_K, PMAX = TH ? 3 : 2;
     __shared__ double sm[NV][SH][BX];
     const int x0 = int(blockIdx.x % unsigned(bx_blocks)) * OX;
     const int y0 = int(blockIdx.x / unsigned(bx_blocks)) * MOM_ROWS;
@@ -412,8 +431,8 @@ __global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(TH
     }
     __syncthreads();
     const int x = x0 + lane - R, y = y0 + ty;
-    double acc[NV];
-    static_for<NV>([&](auto M) { acc[M] = 0.0; });
+    double acc[NA];
+    static_for<NA>([&](auto M) { acc[M] = 0.0; });
     static_for<NC>([&](auto KI) {
         constexpr int K = int(KI) - R;
         double mv[NV];
@@ -434,12 +453,12 @@ __global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(TH
         };
         if constexpr (TH) {
             double C[5][5];
-            thermal_coeffs<L, A13P>(mv, rx, C);
+            thermal_coeffs<L>(mv, rx, C);
             class_pops<L, K>(C, add);
         } else {
             class_from_moments<L, K, ORDER, PO>(mv, rx, add);
         }
-        static_for<NV>([&](auto S) {
+        static_for<NA>([&](auto S) {
             constexpr int p = TH_P[S], q = TH_Q[S];
             constexpr double kq = ipow(double(K), q);
             if constexpr (q == 0)
@@ -456,7 +475,9 @@ __global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(TH
     if (lane < R || lane >= BX - R || x >= nx || y >= ny) return;
     const int64_t here = int64_t(y) * nx + x;
     if constexpr (TH) {
-        static_for<NV>([&](auto M) { __builtin_nontemporal_store(acc[M], mout + int64_t(M) * n + here); });
+        double m[MOM_KT];
+        thermal_state<L, A13P>(acc, m);
+        static_for<MOM_KT>([&](auto M) { __builtin_nontemporal_store(m[M], mout + int64_t(M) * n + here); });
     } else {
         const double r = acc[0], jx = acc[1], jy = acc[2], pxx = acc[3], pxy = acc[4], pyy = acc[5];
         const double ux = jx / r, uy = jy / r;
@@ -468,7 +489,7 @@ __global__ __launch_bounds__(BX* MOM_ROWS) __attribute__((amdgpu_waves_per_eu(TH
 
 // Initial state: the moments of f^(0) [+ f^(1)] + noise (the populations the
 // population form starts from, before its first collision).
-template <class L, bool TH = false>
+template <class L, bool TH = false, bool A13P = false>
 __global__ __launch_bounds__(256) void k_mom_init(InitArgs a)
 {
     const int64_t n = int64_t(a.lay.nx) * a.lay.ny;
@@ -485,14 +506,17 @@ __global__ __launch_bounds__(256) void k_mom_init(InitArgs a)
     if (a.noise) static_for<L::Q>([&](auto I) { f[I] += a.noise_amp * L::v.w[I] * a.noise[int64_t(I) * n + k]; });
     double* out = static_cast<double*>(a.f);
     if constexpr (TH) {
-        static_for<MOM_KT>([&](auto M) {
+        double sums[TH_NS], m[MOM_KT];
+        static_for<TH_NS>([&](auto M) {
             double sum = 0.0;
             static_for<L::Q>([&](auto I) {
                 constexpr double c = ipow(double(L::v.cx[I]), TH_P[M]) * ipow(double(L::v.cy[I]), TH_Q[M]);
                 sum += c * f[I];
             });
-            out[int64_t(M) * n + k] = sum;
+            sums[M] = sum;
         });
+        thermal_state<L, A13P>(sums, m);
+        static_for<MOM_KT>([&](auto M) { out[int64_t(M) * n + k] = m[M]; });
     } else {
         double m[MOM_K];
         node_state<L>(f, m);
@@ -508,7 +532,7 @@ __device__ __forceinline__ void mom_node_populations(const double* __restrict__ 
     if constexpr (TH) {
         double mv[MOM_KT], C[5][5];
         static_for<MOM_KT>([&](auto M) { mv[M] = m[int64_t(M) * n + k]; });
-        thermal_coeffs<L, A13P>(mv, rx, C);
+        thermal_coeffs<L>(mv, rx, C);
         static_for<5>([&](auto A) {
             static_for<5>([&](auto B) {
                 if constexpr (L::basis(int(A), int(B))) {

@@ -47,8 +47,8 @@ def test_buffer_elems_cover_the_grid():
         for nx, ny in ((1, 1), (3, 3), (128, 128), (1000, 7), (1024, 1024)):
             assert b.lbm_buffer_elems(name, nx, ny) >= q * nx * ny
             assert b.lbm_buffer_elems(name, nx, ny, b.LBM_STORE_MOMENTS) == 6 * nx * ny
-    # thermal moment state: the ten raw moments of order <= 3
-    assert b.lbm_buffer_elems("D2V37", 9, 5, b.LBM_STORE_MOMENTS | b.LBM_THERMAL) == 10 * 9 * 5
+    # thermal moment state: rho, u, theta, a1^(2), a1^(3)
+    assert b.lbm_buffer_elems("D2V37", 9, 5, b.LBM_STORE_MOMENTS | b.LBM_THERMAL) == 11 * 9 * 5
     with pytest.raises(b.LbmError):
         b.lbm_buffer_elems(7, 4, 4)
     with pytest.raises(b.LbmError):

@@ -159,8 +159,8 @@ def test_moments_full_size_sampled(orc, b, name, n):
 
 @pytest.mark.parametrize("a13", [False, True])
 def test_thermal_moments_sod_against_oracle(orc, b, a13):
-    """Thermal D2V37 (App. C) in the moment representation, ten raw moments
-    per node: the Sod tube of the population-form test (400 x 4, tau 0.6,
+    """Thermal D2V37 (App. C) in the moment representation (rho, u, theta,
+    a1^(2), a1^(3) per node): the Sod tube of the population-form test (400 x 4, tau 0.6,
     40 steps; 4 rows take the modulo wrap of the staged block), populations
     rebuilt from the moments against the oracle, same bound (1e-11 for
     |f| <= 3.3), and theta against the oracle's."""
@@ -171,7 +171,7 @@ def test_thermal_moments_sod_against_oracle(orc, b, a13):
     f0 = orc.init_populations(lat, rho, ux, uy, th)
     flags = b.LBM_STORE_MOMENTS | b.LBM_THERMAL | (b.LBM_A13_PROJECTED if a13 else 0)
     sim = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=flags)
-    assert b.lbm_buffer_elems("D2V37", nx, ny, flags) == 10 * nx * ny
+    assert b.lbm_buffer_elems("D2V37", nx, ny, flags) == 11 * nx * ny
     sim.step(steps)
     got = sim.populations().cpu().numpy()
     m = sim.moments()
@@ -223,16 +223,20 @@ def test_thermal_moments_per_order_relaxation(orc, b):
 
 
 def test_thermal_moments_follow_the_population_form(orc, b):
-    """200 steps of the Sod tube on 800 x 20: fields and diagnostics of both
-    representations agree."""
-    print("[case] thermal moments vs populations 800x20 x 200", flush=True)
+    """100 steps of the Sod tube on 800 x 20: fields and diagnostics of both
+    representations agree.  The two sum in different orders, so they differ
+    by rounding each step; the oracle run from an f^0 perturbed by 1e-16
+    relative moves by 4.8e-13 at step 100 (|f| <= 3.3) and by 2.3e-8 at step
+    200, after the waves of the two interfaces have met, hence 100 steps and
+    a bound of 1e-11."""
+    print("[case] thermal moments vs populations 800x20 x 100", flush=True)
     nx, ny, tau = 800, 20, 0.6
     rho, ux, uy, th = wl.sod_fields(nx, ny)
     a = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_STORE_MOMENTS | b.LBM_THERMAL)
     p = b.Simulation("D2V37", nx, ny, tau, rho, ux, uy, theta=th, flags=b.LBM_THERMAL)
-    a.step(200)
-    p.step(200)
-    check(a.populations().cpu().numpy(), p.populations().cpu().numpy(), 1e-10, "populations vs population form")
+    a.step(100)
+    p.step(100)
+    check(a.populations().cpu().numpy(), p.populations().cpu().numpy(), 1e-11, "populations vs population form")
     ma, mp = a.moments(), p.moments()
     for key in ("rho", "ux", "uy", "theta"):
         check(ma[key].cpu().numpy(), mp[key].cpu().numpy(), 1e-10, key)
