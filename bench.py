@@ -36,10 +36,10 @@ STORAGE_BYTES = {"fp64": 8, "fp32": 4, "bf16": 2, "fp32d": 4}
 
 def bytes_per_node(q: int, storage: str, thermal: bool = False) -> int:
     """Algorithmic HBM bytes of one node update: every stored value read once
-    and written once (Q populations, or the six FP64 moments; ten for the
+    and written once (Q populations, or the six FP64 moments; eleven for the
     thermal moment state)."""
     if storage == "moments":
-        return 2 * (10 if thermal else 6) * 8
+        return 2 * (11 if thermal else 6) * 8
     return 2 * q * STORAGE_BYTES[storage]
 
 
@@ -147,14 +147,36 @@ def _busiest(d):
     return name, float(np.mean(d[name]))
 
 
+def _step_kernel(d, scheme):
+    """(name, mean per dispatch, dispatches) of the step kernel: the busiest
+    kernel, or for the single-buffer scheme its two kernels (one per
+    placement of the state, alternating) taken together."""
+    if scheme == "aa":
+        names = sorted(k for k in d if "k_stream_collide_aa" in k)
+        vals = [v for k in names for v in d[k]]
+        return " + ".join(names), float(np.mean(vals)), len(vals)
+    name, mean = _busiest(d)
+    return name, mean, len(d[name])
+
+
+def _scheme_tag(scheme):
+    return "_aa" if scheme == "aa" else ""
+
+
+def _run_flags(args):
+    """The bench.py options that select the profiled workload's storage and
+    scheme (the moment representation has one scheme)."""
+    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    return flag if args.storage == "moments" else flag + f" --scheme {args.scheme}"
+
+
 def summarize_pmc(args) -> str:
     """Writes profiles/<lattice>_<storage>_<n>_traffic.txt from the four PMC runs
     (step FETCH_SIZE, step WRITE_SIZE, copy FETCH_SIZE, copy WRITE_SIZE)."""
     fetch_dir, write_dir, cfetch_dir, cwrite_dir = args.summarize_pmc
-    kname, fetch = _busiest(_pmc_per_kernel(fetch_dir, "FETCH_SIZE"))
-    kname2, write = _busiest(_pmc_per_kernel(write_dir, "WRITE_SIZE"))
+    kname, fetch, ndisp = _step_kernel(_pmc_per_kernel(fetch_dir, "FETCH_SIZE"), args.scheme)
+    kname2, write, _ = _step_kernel(_pmc_per_kernel(write_dir, "WRITE_SIZE"), args.scheme)
     assert kname == kname2, (kname, kname2)
-    ndisp = len(_pmc_per_kernel(fetch_dir, "FETCH_SIZE")[kname])
     cname, cfetch = _busiest(_pmc_per_kernel(cfetch_dir, "FETCH_SIZE"))
     _, cwrite = _busiest(_pmc_per_kernel(cwrite_dir, "WRITE_SIZE"))
     copy_kib = float(1 << 20)  # 1 GiB read and written by the calibration copy
@@ -163,10 +185,11 @@ def summarize_pmc(args) -> str:
     alg = bytes_per_node(q, args.storage) * args.n * args.n
     alg_formula = ("2*6*8" if args.storage == "moments" else f"2*{q}*{STORAGE_BYTES[args.storage]}") + f"*{args.n}^2"
     rd, wr = fetch * fs * 1024, write * ws * 1024
-    name = f"{args.lattice.lower()}_{args.storage}_{args.n}_traffic.txt"
-    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    name = f"{args.lattice.lower()}_{args.storage}_{args.n}{_scheme_tag(args.scheme)}_traffic.txt"
+    flag = _run_flags(args)
+    what = "single-buffer in-place (AA)" if args.scheme == "aa" else "pull"
     lines = [
-        f"# HBM traffic of the {args.lattice} {args.storage.upper()} {args.n}x{args.n} pull stream-collide step (rocprofv3 PMC)",
+        f"# HBM traffic of the {args.lattice} {args.storage.upper()} {args.n}x{args.n} {what} stream-collide step (rocprofv3 PMC)",
         "#",
         "# Commands (repo root on an MI355X; one counter per run):",
         f"#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d {fetch_dir} -o run -- {PROFILE_RUN} --lattice {args.lattice} --n {args.n}{flag}",
@@ -207,10 +230,12 @@ def summarize_trace(args) -> str:
     line = [ln for ln in open(bench_json) if ln.startswith("{")][-1]
     live = json.loads(line)
     roof = live["roofline"]
-    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    flag = "" if args.only_closure else _run_flags(args)
     mode = "--only-closure" if args.only_closure else "--only-headline"
-    what = "fused closure step" if args.only_closure else "pull stream-collide"
-    name = f"{args.lattice.lower()}_{'closure' if args.only_closure else args.storage}_{args.n}_kernel_trace.md"
+    what = ("fused closure step" if args.only_closure else
+            "single-buffer in-place (AA) stream-collide" if args.scheme == "aa" else "pull stream-collide")
+    name = (f"{args.lattice.lower()}_{'closure' if args.only_closure else args.storage}_{args.n}"
+            f"{_scheme_tag(args.scheme)}_kernel_trace.md")
     out = [f"# rocprofv3 kernel trace: {args.lattice} {args.storage.upper()} {args.n}x{args.n} shear layer ({what})",
            "", "Command (repo root on an MI355X):", "",
            f"    rocprofv3 --kernel-trace --stats -d gpurun_out/prof -o run -- python3 bench.py --steps {args.steps} "
@@ -222,6 +247,11 @@ def summarize_trace(args) -> str:
            "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
     for n, c, tot, avg, pct in rows:
         out.append(f"| `{n}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
+    if args.scheme == "aa":
+        aa = [(c, tot) for n, c, tot, avg, pct in rows if "k_stream_collide_aa" in n]
+        calls, tot = sum(c for c, _ in aa), sum(t for _, t in aa)
+        out += ["", f"The two AA kernels (one per placement of the state, alternating) together: {calls} calls, "
+                    f"average {tot / calls:.2f} us per launch (the initial state's collision is one of them)."]
     out += ["", f"Live HIP-event timing of the step kernel inside the same run ({live['steps']} timed steps): "
                 f"average {roof['kernel_ms_avg'] * 1e3:.2f} us per launch (events at both ends of the region).",
             "", f"Algorithmic bytes per launch: {roof['bytes_per_launch']} B -> {roof['achieved']:.1f} GB/s = "
@@ -233,9 +263,10 @@ def summarize_trace(args) -> str:
     return path
 
 
-def _pmc_sums(csv_dir: str, kernel_hint: str):
+def _pmc_sums(csv_dir: str, kernel_hint: str, scheme: str = "pull"):
     """{counter: mean value per dispatch} for the busiest kernel whose name
-    contains kernel_hint, from one rocprofv3 --pmc csv run."""
+    contains kernel_hint (for the single-buffer scheme: its two step kernels
+    together), from one rocprofv3 --pmc csv run."""
     import csv
 
     per = {}
@@ -246,6 +277,13 @@ def _pmc_sums(csv_dir: str, kernel_hint: str):
                     per.setdefault((row["Kernel_Name"], row["Counter_Name"]), []).append(float(row["Counter_Value"]))
     if not per:
         raise SystemExit(f"no dispatch of a kernel matching {kernel_hint!r} in {csv_dir}")
+    if scheme == "aa":
+        names = sorted({k for k, _ in per if "k_stream_collide_aa" in k})
+        merged = {}
+        for (k, c), v in per.items():
+            if k in names:
+                merged.setdefault(c, []).extend(v)
+        return " + ".join(names), {c: float(np.mean(v)) for c, v in merged.items()}
     kname = max({k for k, _ in per}, key=lambda k: sum(len(v) for (kk, _), v in per.items() if kk == k))
     return kname, {c: float(np.mean(v)) for (k, c), v in per.items() if k == kname}
 
@@ -256,8 +294,8 @@ def summarize_requests(args) -> str:
     32 (W - W64) for writes, for the step kernel and for a 1 GiB device copy
     (profiles/<lattice>_<storage>_<n>_requests.txt)."""
     rd_dir, wr_dir, crd_dir, cwr_dir = args.summarize_requests
-    kname, rd = _pmc_sums(rd_dir, "k_stream_collide")
-    _, wr = _pmc_sums(wr_dir, "k_stream_collide")
+    kname, rd = _pmc_sums(rd_dir, "k_stream_collide", args.scheme)
+    _, wr = _pmc_sums(wr_dir, "k_stream_collide", args.scheme)
     cname, crd = _pmc_sums(crd_dir, "")
     _, cwr = _pmc_sums(cwr_dir, "")
 
@@ -270,7 +308,7 @@ def summarize_requests(args) -> str:
     q = {"D2Q9": 9, "D2V17": 17, "D2V37": 37}[args.lattice]
     alg = bytes_per_node(q, args.storage) * args.n * args.n
     gib = float(1 << 30)
-    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    flag = _run_flags(args)
     rdc = "TCC_EA0_RDREQ_sum TCC_EA0_RDREQ_128B_sum TCC_EA0_RDREQ_64B_sum TCC_EA0_RDREQ_32B_sum"
     wrc = "TCC_EA0_WRREQ_sum TCC_EA0_WRREQ_64B_sum"
     lines = [
@@ -297,7 +335,8 @@ def summarize_requests(args) -> str:
         f"write_bytes_per_launch: {wbytes(wr):.0f}",
         f"hbm_bytes_per_launch: {rbytes(rd) + wbytes(wr):.0f}",
     ]
-    path = os.path.join(ROOT, "profiles", f"{args.lattice.lower()}_{args.storage}_{args.n}_requests.txt")
+    path = os.path.join(ROOT, "profiles",
+                        f"{args.lattice.lower()}_{args.storage}_{args.n}{_scheme_tag(args.scheme)}_requests.txt")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     return path
@@ -332,7 +371,7 @@ def summarize_closure_pmc(args) -> str:
              f"#   rocprofv3 --pmc {CLOSURE_COUNTERS} --output-format csv -d {cdir} -o run -- python3 bench.py "
              f"--steps 20 --warmup 2 --only-closure --lattice D2V37 --n {args.n}",
              f"#   rocprofv3 --pmc {CLOSURE_COUNTERS} --output-format csv -d {pdir} -o run -- {PROFILE_RUN} "
-             f"--lattice D2V37 --n {args.n}",
+             f"--lattice D2V37 --n {args.n} --scheme pull",
              f"# Summary: python3 bench.py --n {args.n} --summarize-closure-pmc {cdir} {pdir}",
              "# Per node in the lane view (one lane per node); busy fractions over the kernel's GPU cycles.",
              "# MFMA busy: SQ_VALU_MFMA_BUSY_CYCLES / 256 CUs / 4 SIMDs per kernel cycle."]
@@ -350,7 +389,7 @@ def summarize_valu(args) -> str:
     """VALU instruction mix and busy fraction of the step kernel from one
     rocprofv3 --pmc run (profiles/<lattice>_<storage>_<n>_valu.txt)."""
     (vdir,) = args.summarize_valu
-    kname, d = _pmc_sums(vdir, "k_mom_step" if args.storage == "moments" else "k_stream_collide")
+    kname, d = _pmc_sums(vdir, "k_mom_step" if args.storage == "moments" else "k_stream_collide", args.scheme)
     nodes = args.n * args.n
     f64 = d["SQ_INSTS_VALU_FMA_F64"] + d["SQ_INSTS_VALU_MUL_F64"] + d["SQ_INSTS_VALU_ADD_F64"]
     flops = 64 * (2 * d["SQ_INSTS_VALU_FMA_F64"] + d["SQ_INSTS_VALU_MUL_F64"] + d["SQ_INSTS_VALU_ADD_F64"])
@@ -359,7 +398,7 @@ def summarize_valu(args) -> str:
     # comes summed over the 8 XCCs: per XCC (the kernel's duration in cycles) is 1/8
     busy = 100.0 * d["SQ_ACTIVE_INST_VALU"] / cus / (d["GRBM_GUI_ACTIVE"] / xccs)
     counters = "SQ_INSTS_VALU SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 SQ_INSTS_VALU_ADD_F64 SQ_ACTIVE_INST_VALU GRBM_GUI_ACTIVE"
-    flag = "" if args.storage == "fp64" else f" --storage {args.storage}"
+    flag = _run_flags(args)
     lines = [
         f"# VALU profile: {args.lattice} {args.storage} {args.n}x{args.n} step (rocprofv3 PMC)",
         "#",
@@ -375,7 +414,8 @@ def summarize_valu(args) -> str:
         f"fp64_flops_per_node: {flops / nodes:.1f}",
         f"valu_busy_percent: {busy:.2f}",
     ]
-    path = os.path.join(ROOT, "profiles", f"{args.lattice.lower()}_{args.storage}_{args.n}_valu.txt")
+    path = os.path.join(ROOT, "profiles",
+                        f"{args.lattice.lower()}_{args.storage}_{args.n}{_scheme_tag(args.scheme)}_valu.txt")
     with open(path, "w") as f:
         f.write("\n".join(lines) + "\n")
     return path
@@ -464,13 +504,15 @@ def summarize_trace_batch(args) -> str:
     return path
 
 
-def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0, noise=True, coll=0):
+def make_sim(b, wl, lattice, n, storage, re=1e5, thermal=False, seed=0, noise=True, coll=0, scheme="pull"):
     """The shear-layer workload (noise=False skips the 1e-8 w_i noise, which
-    changes nothing in the timing of a large grid)."""
+    changes nothing in the timing of a large grid); scheme "aa": one buffer,
+    in-place steps."""
     q, reach, n_eq, cs2 = b.lbm_lattice_info(lattice)
     u0, tau = wl.shear_layer_params(cs2, n, re)
     rho, ux, uy = wl.shear_layer_fields(n, n, u0)
     flags = STORAGE_FLAGS[storage] | (b.LBM_THERMAL if thermal else 0) | coll
+    flags |= b.LBM_SCHEME_AA if scheme == "aa" else 0
     theta = np.ones_like(rho) if thermal else None
     nz = wl.uniform_noise(seed, q, n, n) if noise else None
     sim = b.Simulation(lattice, n, n, tau, rho, ux, uy, theta=theta, noise=nz, noise_amp=1e-8 if noise else 0.0,
@@ -545,10 +587,10 @@ def time_regions(torch, sim, steps, regions=5):
     return out
 
 
-def roofline_point(torch, b, wl, lattice, n, storage, steps=100, regions=5, thermal=False, coll=0):
+def roofline_point(torch, b, wl, lattice, n, storage, steps=100, regions=5, thermal=False, coll=0, scheme="pull"):
     """Median-of-regions step time of one workload and its fraction of the
     8 TB/s HBM peak (algorithmic bytes 2 Q sizeof per node)."""
-    sim, meta = make_sim(b, wl, lattice, n, storage, thermal=thermal, noise=False, coll=coll)
+    sim, meta = make_sim(b, wl, lattice, n, storage, thermal=thermal, noise=False, coll=coll, scheme=scheme)
     sim.step(5)
     ms = time_regions(torch, sim, steps, regions)
     bad = int(sim.moments(vorticity=False)["sums"][8])
@@ -558,10 +600,31 @@ def roofline_point(torch, b, wl, lattice, n, storage, steps=100, regions=5, ther
     gbs = bpl / (med * 1e-3) / 1e9
     buf = bpl // 2
     return {"lattice": lattice, "storage": storage, "thermal": thermal,
-            "collision": {0: "RR", 0x10: "PR", 0x20: "BGK"}[coll], "n": n,
+            "collision": {0: "RR", 0x10: "PR", 0x20: "BGK"}[coll], "scheme": scheme, "n": n,
             "buffer_MiB": round(buf / 2 ** 20, 1), "MLUPS": round(n * n / (med * 1e-3) / 1e6, 1),
             "kernel_ms_median": round(med, 5), "kernel_ms_regions": [round(x, 5) for x in ms],
             "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": bad}
+
+
+# Sizes where one state buffer fits the 256 MiB memory-side cache but two do
+# not (the band the single-buffer scheme is for), and two above it.
+AA_CASES = [("D2V37", 768, "fp64"), ("D2V17", 1024, "fp64"), ("D2V37", 1024, "fp32"), ("D2Q9", 2048, "fp64"),
+            ("D2V37", 1024, "fp64"), ("D2V37", 2048, "fp64")]
+
+
+def aa_suite(torch, b, wl, steps=50):
+    """The pull step against the single-buffer (AA) step on the same workload
+    (an even number of steps per timed region, so both AA kernels count
+    alike); frac_hbm is algorithmic bytes per second over the HBM peak."""
+    rows = []
+    for lat, n, st in AA_CASES:
+        pull = roofline_point(torch, b, wl, lat, n, st, steps=steps)
+        aa = roofline_point(torch, b, wl, lat, n, st, steps=steps, scheme="aa")
+        rows.append({"lattice": lat, "n": n, "storage": st, "buffer_MiB": aa["buffer_MiB"],
+                     "pull_MLUPS": pull["MLUPS"], "aa_MLUPS": aa["MLUPS"], "pull_frac_hbm": pull["frac_hbm"],
+                     "aa_frac_hbm": aa["frac_hbm"], "aa_over_pull": round(aa["MLUPS"] / pull["MLUPS"], 3),
+                     "nonfinite": pull["nonfinite"] + aa["nonfinite"]})
+    return rows
 
 
 def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
@@ -704,6 +767,12 @@ def main():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--storage", default="fp64", choices=list(STORAGE_FLAGS))
     ap.add_argument("--thermal", action="store_true", help="thermal form of the --only-headline workload (D2V37)")
+    ap.add_argument("--scheme", choices=["pull", "aa"],
+                    help="single-buffer in-place (AA) step or two-buffer pull step for the headline workload "
+                         "(the same states bit for bit; default: AA, the faster at the headline size, for "
+                         "population storage; the moment representation has the pull step only)")
+    ap.add_argument("--no-aa", action="store_true", help="skip the pull-against-AA lines")
+    ap.add_argument("--only-aa", action="store_true", help="time the pull-against-AA lines alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
@@ -741,6 +810,10 @@ def main():
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "BENCH_OUT"),
                     help="write the kernel-trace summary from a rocprofv3 database and that run's output")
     args = ap.parse_args()
+    if args.scheme is None:
+        args.scheme = "pull" if args.storage == "moments" else "aa"
+    if args.scheme == "aa" and args.storage == "moments":
+        ap.error("the moment representation has the pull step only")
 
     if args.summarize_pmc:
         print(summarize_pmc(args))
@@ -795,6 +868,10 @@ def main():
         print(json.dumps({"batched": batched_suite(torch, b, wl, steps=args.steps)}), flush=True)
         return
 
+    if args.only_aa:
+        print(json.dumps({"scheme_aa": aa_suite(torch, b, wl)}), flush=True)
+        return
+
     if args.only_closure:
         # the fused closure step with a random network (every node inside a wide
         # normalisation range): its cost does not depend on the weights
@@ -820,12 +897,12 @@ def main():
         return
 
     if args.only_headline:
-        args.no_sweep = args.no_batch = args.no_3d = args.no_studies = args.no_cpu_baseline = True
+        args.no_sweep = args.no_batch = args.no_3d = args.no_studies = args.no_cpu_baseline = args.no_aa = True
         args.no_hbm_points = True
         args.closure = "none"
         args.regions = 0
 
-    sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage, thermal=args.thermal)
+    sim, meta = make_sim(b, wl, args.lattice, args.n, args.storage, thermal=args.thermal, scheme=args.scheme)
     wall, kms = time_steps(torch, sim, args.steps, args.warmup)
     med = time_regions(torch, sim, args.region_steps, args.regions) if args.regions > 0 else []
     mom = sim.moments()
@@ -838,7 +915,7 @@ def main():
     bytes_per_launch = bytes_per_node(meta["q"], args.storage, args.thermal) * nodes
     kavg = kms * 1e-3
     achieved = bytes_per_launch / kavg / 1e9
-    traffic = read_traffic(f"{args.lattice.lower()}_{args.storage}_{args.n}_traffic.txt")
+    traffic = read_traffic(f"{args.lattice.lower()}_{args.storage}_{args.n}{_scheme_tag(args.scheme)}_traffic.txt")
     out = {
         "metric": METRIC,
         "value": round(mlups, 2),
@@ -857,7 +934,7 @@ def main():
                         f"shear layer {args.n}x{args.n}, "
                         f"{args.storage} populations, order {b.lbm_lattice_info(args.lattice)[2]}, "
                         "Re 1e5, Mach 0.1",
-            "lattice": args.lattice, "nx": args.n, "ny": args.n, "storage": args.storage, "scheme": "pull",
+            "lattice": args.lattice, "nx": args.n, "ny": args.n, "storage": args.storage, "scheme": args.scheme,
             "tau": meta["tau"],
         },
         "roofline": {
@@ -870,9 +947,12 @@ def main():
             "bytes_per_launch": bytes_per_launch,
             "kernel_ms_avg": round(kms, 5),
             "buffer_MiB": round(buffer_mib, 1),
-            "memory": ("cache-assisted: the state buffer is within the 256-320 MiB band where the step keeps "
-                       "what it writes in the 256 MiB memory-side cache (the out-of-cache point is "
-                       "roofline_out_of_cache)") if 256 < buffer_mib <= 320 else
+            "memory": (("cache-assisted: the one state buffer of the in-place steps is a little larger than "
+                        "the 256 MiB memory-side cache, which still serves part of each step's traffic (the "
+                        "out-of-cache point is roofline_out_of_cache)") if args.scheme == "aa" else
+                       ("cache-assisted: the state buffer is within the 256-320 MiB band where the step keeps "
+                        "what it writes in the 256 MiB memory-side cache (the out-of-cache point is "
+                        "roofline_out_of_cache)")) if 256 < buffer_mib <= 320 else
                       ("cache-resident" if buffer_mib <= 256 else "out of cache"),
         },
         "nonfinite_nodes": int(mom["sums"][8]),
@@ -932,6 +1012,8 @@ def main():
         out["per_lattice"] = sweep
         out["cost_ratios_1024"] = ratios
         out["copy_GBs"] = round(copy_bandwidth(torch), 1)
+    if not args.no_aa:
+        out["scheme_aa"] = aa_suite(torch, b, wl)
     if not args.no_3d:
         out["lattices_3d"] = suite_3d(torch, b, wl, n=args.n3)
     if not args.no_batch:

@@ -49,12 +49,33 @@
  *   the collision in double, so each value is rounded to float once per step
  *   (at the store); batches and the closure do not take it.
  *
+ * Scheme (population storage only)
+ *   By default a step gathers from one buffer into the other (f_a, f_b
+ *   alternate).  LBM_SCHEME_AA keeps the state in f_a alone and updates it in
+ *   place (the AA pattern): after an even number of steps the post-collision
+ *   value f_i(x) sits in plane opp(i) at x (opp(i): the velocity -c_i), after
+ *   an odd number in plane i at x + c_i (periodic); a step from an even count
+ *   reads plane opp(i) at x - c_i and writes plane i at x + c_i, one from an
+ *   odd count reads and writes node x's own planes.  Each node's update reads
+ *   and then writes the same slots, so steps are race-free.  The states (and
+ *   what lbm_populations, lbm_moments and the checkpoints give) are those of
+ *   the two-buffer scheme bit for bit; a checkpoint holds f_a as it sits, so
+ *   it loads only into an LBM_SCHEME_AA context.  It halves the state memory
+ *   and the working set: faster where one buffer fits the 256 MiB
+ *   memory-side cache but two do not, slower where the step streams from
+ *   HBM (the shifted writes of every other step).  Not with
+ *   LBM_STORE_MOMENTS, batches or the closure.
+ *
  * Environment (read when a context is created; none changes any result)
  *   RRLBM_CACHE_POLICY=0/1/2  forces the cache policy of the step: 0 ordinary
  *     loads and non-temporal stores, 1 ordinary loads and stores with the tile
  *     order reversed every other step, 2 non-temporal loads and ordinary
  *     stores.  By default the policy follows the size of one state buffer
  *     (1 up to 128 MiB, 2 from 256 to 320 MiB, 0 otherwise; 3D: RR and BGK).
+ *     With LBM_SCHEME_AA: 1 (the default at every size) ordinary stores,
+ *     0 non-temporal stores in order, 2 non-temporal stores in the steps
+ *     that write a node's own slots and ordinary ones in the others; with 1
+ *     and 2 the tile order is reversed every other step.
  *   RRLBM_XCD_REMAP=0  keeps the hardware's round-robin order of blocks over
  *     the 8 XCDs instead of giving each XCD a contiguous band of tiles.
  *   RRLBM_BATCH_SPLIT=1/2  (read by lbm_batch_create) gives each lattice of a
@@ -93,6 +114,7 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_EQ_INIT_ORDER2 0x100u /* initial f^(0) truncated at Hermite order 2    */
 #define LBM_A13_PROJECTED 0x200u  /* thermal RR: keep the projected a1^(3)         */
 #define LBM_MATH_FP64 0x400u      /* with LBM_STORE_FP32: double arithmetic        */
+#define LBM_SCHEME_AA 0x800u      /* one population buffer, in-place steps          */
 
 /* Error codes. */
 #define LBM_OK 0
@@ -130,7 +152,8 @@ int64_t lbm_buffer_elems(int lattice, int nx, int ny, uint32_t flags);
  *   flags      LBM_* flags above.  LBM_THERMAL requires LBM_D2V37.
  *   f_a, f_b   two device buffers of lbm_buffer_elems() elements of the
  *              storage type (double, float or bfloat16), caller-owned; they
- *              must stay valid until lbm_destroy.
+ *              must stay valid until lbm_destroy.  With LBM_SCHEME_AA only
+ *              f_a is used and f_b must be NULL.
  *   rho,ux,uy  device FP64 fields of the initial state.
  *   theta      device FP64 field of theta = T/T_0 (thermal), or NULL (= 1).
  *   grad       device FP64 array [4][y][x] of the velocity gradients
@@ -149,7 +172,8 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
              const double* theta, const double* grad, const double* noise, double noise_amp, void* stream);
 
 /* Advances nsteps (>= 0) time steps: each is one fused launch that gathers
- * f_i(x - c_i) (periodic pull), regularizes, relaxes and stores.  Returns
+ * f_i(x - c_i) (periodic pull), regularizes, relaxes and stores (in place
+ * with LBM_SCHEME_AA).  Returns
  * LBM_EDEVICE if a launch fails.  A blow-up is not an error (lbm_moments
  * counts non-finite nodes). */
 int lbm_step(lbm_ctx* ctx, int nsteps);

@@ -27,6 +27,7 @@ LBM_COLL_BGK = 0x20
 LBM_EQ_INIT_ORDER2 = 0x100
 LBM_A13_PROJECTED = 0x200
 LBM_MATH_FP64 = 0x400
+LBM_SCHEME_AA = 0x800
 LBM_NSUMS = 10
 LBM_NSUMS_3D = 8
 
@@ -337,7 +338,8 @@ def lbm_closure_fallbacks(ctx) -> int:
 # ---------------------------------------------------------------- helper
 
 class Simulation:
-    """Owns the two population buffers (torch tensors) and one context."""
+    """Owns the population buffers (torch tensors: two, or one with
+    LBM_SCHEME_AA) and one context."""
 
     def __init__(self, lattice, nx, ny, tau, rho, ux, uy, theta=None, noise=None, noise_amp=0.0,
                  reg_order=None, flags=0, device="cuda:0", stream=None, grad=None):
@@ -353,7 +355,7 @@ class Simulation:
         dtype = (torch.float32 if flags & LBM_STORE_FP32 else
                  torch.bfloat16 if flags & LBM_STORE_BF16 else torch.float64)
         n = lbm_buffer_elems(self.lattice, nx, ny, flags)
-        self.bufs = [torch.empty(n, dtype=dtype, device=self.device) for _ in range(2)]
+        self.bufs = [torch.empty(n, dtype=dtype, device=self.device) for _ in range(1 if flags & LBM_SCHEME_AA else 2)]
 
         def dev(a):
             if a is None:
@@ -362,7 +364,8 @@ class Simulation:
             return t.to(self.device, torch.float64).contiguous()
 
         fields = [dev(a) for a in (rho, ux, uy, theta, grad, noise)]
-        self.ctx = lbm_init(self.lattice, nx, ny, tau, self.reg_order, flags, self.bufs[0], self.bufs[1],
+        f_b = self.bufs[1] if len(self.bufs) > 1 else None
+        self.ctx = lbm_init(self.lattice, nx, ny, tau, self.reg_order, flags, self.bufs[0], f_b,
                             *fields, noise_amp=noise_amp, stream=self.stream)
         self._keep = fields  # inputs must outlive the asynchronous init
 

@@ -228,13 +228,18 @@ bool lattice_info(int lattice, LatInfo* out)
 // the step at 768^2, 1024^2 and 1536^2 for every lattice and storage:
 // POL_CACHE wins up to 128 MiB (by up to 20 points of HBM peak), POL_KEEP from
 // 256 to 320 MiB (D2V37 FP64 1024^2, 310 MB: 75.7% against 71.5%), POL_STREAM
-// elsewhere.  RRLBM_CACHE_POLICY=0/1/2 forces one.
-int choose_policy(int64_t buffer_bytes)
+// elsewhere.  The in-place (AA) step takes POL_CACHE at every size: its
+// ordinary stores beat non-temporal ones on every lattice and storage
+// measured from 166 MiB to 1.2 GB (D2V37 FP64 2048^2: 68.2% against 57.4%;
+// D2V17 FP64 2048^2: 78.2 against 58.5%) but one (D2V37 FP64 1024^2: 80.7
+// against 81.8%).  RRLBM_CACHE_POLICY=0/1/2 forces one.
+int choose_policy(int64_t buffer_bytes, bool aa = false)
 {
     if (const char* e = std::getenv("RRLBM_CACHE_POLICY")) {
         const int p = std::atoi(e);
         if (p >= POL_STREAM && p <= POL_KEEP) return p;
     }
+    if (aa) return POL_CACHE;
     const int64_t MiB = int64_t(1) << 20;
     if (buffer_bytes <= 128 * MiB) return POL_CACHE;
     if (buffer_bytes > 256 * MiB && buffer_bytes <= 320 * MiB) return POL_KEEP;
@@ -261,7 +266,8 @@ int validate(int lattice, int nx, int ny, double tau, int reg_order, uint32_t fl
     if (layout_elems(li->q, nx, ny) >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "grid too large");
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_ETAU, "tau must be finite and > 1/2");
     const uint32_t known = LBM_THERMAL | LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS | LBM_COLL_PR |
-                           LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_A13_PROJECTED | LBM_MATH_FP64;
+                           LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_A13_PROJECTED | LBM_MATH_FP64 |
+                           LBM_SCHEME_AA;
     if (flags & ~known) return fail(LBM_EINVAL, "unknown flag bits");
     if ((flags & LBM_MATH_FP64) && !(flags & LBM_STORE_FP32))
         return fail(LBM_EINVAL, "LBM_MATH_FP64 goes with LBM_STORE_FP32");
@@ -270,6 +276,8 @@ int validate(int lattice, int nx, int ny, double tau, int reg_order, uint32_t fl
     if ((flags & LBM_STORE_MOMENTS) && (flags & (LBM_COLL_PR | LBM_COLL_BGK)))
         return fail(LBM_EINVAL, "the moment representation is recursive regularization only");
     if ((flags & LBM_COLL_PR) && (flags & LBM_COLL_BGK)) return fail(LBM_EINVAL, "two collision flags");
+    if ((flags & LBM_SCHEME_AA) && (flags & LBM_STORE_MOMENTS))
+        return fail(LBM_EINVAL, "LBM_SCHEME_AA goes with population storage");
     if ((flags & LBM_THERMAL) && lattice != LBM_D2V37)
         return fail(LBM_EINVAL, "the thermal form needs the D2V37 lattice");
     if (!(flags & LBM_COLL_BGK) && (reg_order < 2 || reg_order > li->n_eq))
@@ -370,7 +378,11 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     LatInfo li;
     int e = validate(lattice, nx, ny, tau, reg_order, flags, &li);
     if (e) return e;
-    if (!f_a || !f_b || f_a == f_b) return fail(LBM_EINVAL, "two distinct population buffers are needed");
+    if (flags & LBM_SCHEME_AA) {
+        if (!f_a || f_b) return fail(LBM_EINVAL, "LBM_SCHEME_AA takes f_a and a NULL f_b");
+    } else if (!f_a || !f_b || f_a == f_b) {
+        return fail(LBM_EINVAL, "two distinct population buffers are needed");
+    }
     if (!rho || !ux || !uy) return fail(LBM_EINVAL, "rho, ux and uy are required");
     if ((flags & LBM_THERMAL) == 0 && theta)
         return fail(LBM_EINVAL, "theta given for an isothermal run");
@@ -395,9 +407,10 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     c->coll = (flags & LBM_COLL_PR) ? COLL_PR : (flags & LBM_COLL_BGK) ? COLL_BGK : COLL_RR;
     c->thermal = (flags & LBM_THERMAL) != 0;
     c->a13p = (flags & LBM_A13_PROJECTED) != 0;
+    c->aa = (flags & LBM_SCHEME_AA) != 0;
     c->q = li.q;
     c->lay = make_layout(li.q, nx, ny);
-    c->pol = choose_policy(store_bytes(c));
+    c->pol = choose_policy(store_bytes(c), c->aa);
     // tuning knob: RRLBM_XCD_REMAP=0 keeps the hardware's round-robin block order
     if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     c->buf[0] = f_a;
@@ -415,6 +428,12 @@ int lbm_init(lbm_ctx** out, int lattice, int nx, int ny, double tau, int reg_ord
     if (c->store == ST_MOM) {
         const InitArgs ia{ f_a, c->lay, rho, ux, uy, theta, grad, noise, noise_amp, eq_order, tau };
         he = mom_launch_any(c, 0, nullptr, nullptr, &ia); // the moments are the state: no collision here
+    } else if (c->aa) {
+        // f^(0) [+ f^(1)] + noise into f_a, collided in place into the
+        // placement of an even step count
+        const InitArgs ia{ f_a, c->lay, rho, ux, uy, theta, grad, noise, noise_amp, eq_order, tau };
+        he = ops2d(c->lattice, c->store).init(c, ia);
+        if (he == hipSuccess) he = ops2d(c->lattice, c->store).step_aa(c, false, 0u);
     } else {
         // f^(0) [+ f^(1)] + noise into f_b, collided node by node into f_a: post-collision state, cur = 0
         const InitArgs ia{ f_b, c->lay, rho, ux, uy, theta, grad, noise, noise_amp, eq_order, tau };
@@ -434,9 +453,14 @@ int lbm_step(lbm_ctx* c, int nsteps)
     if (!c) return fail(LBM_EINVAL, "ctx is NULL");
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
     for (int s = 0; s < nsteps; ++s) {
-        hipError_t he = launch_step(c, c->buf[c->cur], c->buf[1 - c->cur], true);
+        hipError_t he;
+        if (c->aa) {
+            he = ops2d(c->lattice, c->store).step_aa(c, (c->steps & 1) == 0, uint32_t(c->steps + 1));
+        } else {
+            he = launch_step(c, c->buf[c->cur], c->buf[1 - c->cur], true);
+            c->cur = 1 - c->cur;
+        }
         if (he != hipSuccess) return fail(LBM_EDEVICE, std::string("step launch: ") + hipGetErrorString(he));
-        c->cur = 1 - c->cur;
         ++c->steps;
     }
     return LBM_OK;
@@ -903,6 +927,7 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, i
             return fail(LBM_EINVAL, "batch members must use the isothermal recursive regularization");
         if (c->store == ST_MOM || c->store == ST_F32D)
             return fail(LBM_EINVAL, "batch members must store FP64, FP32 or BF16 populations with arithmetic of the same width");
+        if (c->aa) return fail(LBM_EINVAL, "batch members must use the two-buffer scheme");
         if (c->store != ctxs[0]->store) return fail(LBM_EINVAL, "batch members must share the storage type");
         if (c->stream != ctxs[0]->stream) return fail(LBM_EINVAL, "batch members must share the stream");
         for (int j = 0; j < i; ++j)

@@ -81,8 +81,9 @@ extern "C" {
 int lbm_closure_samples(lbm_ctx* c, int factor, float* x, float* r)
 {
     if (!c || !x || !r) return fail(LBM_EINVAL, "ctx, x or r is NULL");
-    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal || c->store == ST_MOM || c->store == ST_F32D)
-        return fail(LBM_EINVAL, "closure samples need an isothermal RR D2V37 context storing FP64, FP32 or BF16 populations");
+    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal || c->store == ST_MOM || c->store == ST_F32D ||
+        c->aa)
+        return fail(LBM_EINVAL, "closure samples need an isothermal RR D2V37 context storing FP64, FP32 or BF16 populations in two buffers");
     if (factor < 1 || factor > 8 || c->nx % factor || c->ny % factor)
         return fail(LBM_EINVAL, "factor must be in [1, 8] and divide nx and ny");
     const double sf = (1.0 - 0.5 / c->tau) / (1.0 - 1.0 / c->tau);
@@ -244,8 +245,9 @@ int lbm_closure_set(lbm_ctx* c, const float* theta, const float* norm)
         return LBM_OK;
     }
     if (!norm) return fail(LBM_EINVAL, "norm is NULL");
-    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal || c->store == ST_MOM || c->store == ST_F32D)
-        return fail(LBM_EINVAL, "the closure needs an isothermal RR D2V37 context storing FP64, FP32 or BF16 populations");
+    if (c->lattice != LBM_D2V37 || c->coll != COLL_RR || c->thermal || c->store == ST_MOM || c->store == ST_F32D ||
+        c->aa)
+        return fail(LBM_EINVAL, "the closure needs an isothermal RR D2V37 context storing FP64, FP32 or BF16 populations in two buffers");
     if (!c->cl_frags) {
         HIP_TRY(hipMalloc(&c->cl_frags, sizeof(MlpInfer)));
         HIP_TRY(hipMalloc(&c->cl_norm, sizeof(float) * NORM_N));

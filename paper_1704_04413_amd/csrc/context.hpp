@@ -30,6 +30,7 @@ struct lbm_ctx {
     uint32_t flags = 0;
     int store = rr::ST_F64, coll = rr::COLL_RR;
     bool thermal = false, a13p = false;
+    bool aa = false; // LBM_SCHEME_AA: the state lives in buf[0] alone, cur stays 0
     int q = 0;
     rr::Layout lay{};
     int xcd_remap = 1;
@@ -78,10 +79,17 @@ inline StepArgs step_args(const lbm_ctx* c, const void* fin, void* fout, bool pu
                      (c->pol == POL_CACHE && pull && (c->steps & 1)) ? 1 : 0 };
 }
 
+// Where the current state sits (RD of state_index): 0 two-buffer; with the
+// single buffer 1 after an even number of steps, 2 after an odd number.
+inline int state_placement(const lbm_ctx* c) { return !c->aa ? 0 : (c->steps & 1) ? 2 : 1; }
+
 // One 2D (lattice, storage) pair: the kernels of step2d.hip compiled for it.
 struct Ops2D {
     // one step fin -> fout (pull), or the local collision of the initial state
     hipError_t (*step)(const lbm_ctx* c, const void* fin, void* fout, bool pull);
+    // one in-place step of the single-buffer scheme on buf[0] (shifted: the
+    // placement after an even number of steps), the state written keyed `seq`
+    hipError_t (*step_aa)(const lbm_ctx* c, bool shifted, uint32_t seq);
     hipError_t (*init)(const lbm_ctx* c, const InitArgs& a);
     hipError_t (*populations)(const lbm_ctx* c, const void* src, double* out);
     // fields (any may be NULL) and per-block sums into `partial` (nblk blocks of MOM_NS)

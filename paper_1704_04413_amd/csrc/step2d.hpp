@@ -30,6 +30,10 @@ namespace rr {
 #ifndef RRLBM_WAVES_PER_EU
 #define RRLBM_WAVES_PER_EU 4
 #endif
+// The same for the in-place (AA) step kernel.
+#ifndef RRLBM_AA_WAVES_PER_EU
+#define RRLBM_AA_WAVES_PER_EU 4
+#endif
 
 // The hardware hands consecutive workgroup ids to the 8 XCDs in turn; with
 // the remap, XCD k works on the k-th contiguous eighth of the tiles, so
@@ -101,6 +105,91 @@ void k_stream_collide(StepArgs a)
     node_update<L, S, COLL, THERMAL, A13P, PULL, POL == POL_STREAM, POL == POL_KEEP>(
         static_cast<const typename S::elem*>(a.fin), static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx,
         a.seq);
+}
+
+// ------------------------------------------------ single-buffer (AA) step
+
+// Hides v's value from the optimizer (no instruction is emitted).
+__device__ __forceinline__ void opaque(int& v) { asm volatile("" : "+v"(v)); }
+
+// One node of the in-place step on one buffer f (the AA pattern).  The state
+// alternates between two placements of the post-collision values (see
+// state_index).  !SHIFTED (the state after an odd number of steps, or the
+// initial populations): the node finds its incoming f_i(x - c_i) in its own
+// slot i and leaves its outgoing value i in its own slot opp(i).  SHIFTED
+// (after an even number): value i comes from slot opp(i) of the node x - c_i
+// and goes to slot i of the node x + c_i.  Either way a thread writes exactly
+// the slots it has read, after reading all of them, so threads never touch
+// each other's slots within one launch.  The collision, the node key and the
+// dither stream are those of the pull step, so both schemes give the same
+// states bit for bit.
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool SHIFTED, bool NT>
+__device__ __forceinline__ void node_update_aa(typename S::elem* f, const Layout& lay, int x, int y,
+                                               const Relax& rx, uint32_t seq)
+{
+    using T = typename S::math;
+    constexpr int R = L::R;
+    const int nx = lay.nx, ny = lay.ny;
+    const uint32_t node = uint32_t(y) * uint32_t(nx) + uint32_t(x);
+
+    // periodic x + d and row(y + d) for d in [-R, R]
+    int xs[2 * R + 1], ys[2 * R + 1];
+    auto neighbours = [&](int x0, int y0) {
+        static_for<2 * R + 1>([&](auto D) {
+            constexpr int d = int(D) - R;
+            int xx = x0 + d, yy = y0 + d;
+            if constexpr (d < 0) {
+                xx += (xx < 0) ? nx : 0;
+                yy += (yy < 0) ? ny : 0;
+            } else if constexpr (d > 0) {
+                xx -= (xx >= nx) ? nx : 0;
+                yy -= (yy >= ny) ? ny : 0;
+            }
+            xs[D] = xx;
+            ys[D] = lay.row(yy);
+        });
+    };
+    if constexpr (SHIFTED) neighbours(x, y);
+
+    T v[L::Q];
+    static_for<L::Q>([&](auto I) {
+        constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
+        constexpr int o = opp_index<L>(int(I));
+        const int idx = SHIFTED ? ys[R - cy] + xs[R - cx] + o * lay.te : lay.row(y) + x + int(I) * lay.te;
+        v[I] = S::load(f + idx);
+    });
+
+    collide_node<L, T, COLL, THERMAL, S::shifted, A13P, S::conserve_in_double>(v, rx);
+
+    // The stores go to the addresses the loads used; hiding x and y makes the
+    // compiler rebuild them here rather than hold all Q across the collision
+    // (which spills).
+    opaque(x);
+    opaque(y);
+    if constexpr (SHIFTED) neighbours(x, y);
+    const int here = lay.row(y) + x;
+
+    store_node_at<L, S, T, NT>(
+        f,
+        [&](auto I) {
+            constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
+            constexpr int o = opp_index<L>(int(I));
+            return SHIFTED ? ys[R + cy] + xs[R + cx] + int(I) * lay.te : here + o * lay.te;
+        },
+        v, node, seq);
+}
+
+// a.fin == a.fout: the one state buffer.
+template <class L, class S, int COLL, bool THERMAL, bool A13P, bool SHIFTED, bool NT>
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_AA_WAVES_PER_EU)))
+void k_stream_collide_aa(StepArgs a)
+{
+    const int bid = block_index(a);
+    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
+    const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
+    if (x >= a.lay.nx || y >= a.lay.ny) return;
+    node_update_aa<L, S, COLL, THERMAL, A13P, SHIFTED, NT>(static_cast<typename S::elem*>(a.fout), a.lay, x, y,
+                                                            a.rx, a.seq);
 }
 
 // ---------------------------------------------------------- batch kernel
@@ -220,7 +309,8 @@ __device__ __forceinline__ void node_diag(const double (&v)[L::Q], int thermal, 
 
 // rho, u, theta per node (FP64 arithmetic whatever the storage) and block sums
 // of [rho, rho ux, rho uy, sum f|c|^2/2, |u|^2, |u|^4, non-finite, theta].
-template <class L, class S>
+// RD: where the state sits (state_index).
+template <class L, class S, int RD = 0>
 __global__ __launch_bounds__(256) void k_moments(const void* fsrc, Layout lay, int thermal, double* rho_o,
                                                  double* ux_o, double* uy_o, double* th_o, double* partial)
 {
@@ -228,11 +318,11 @@ __global__ __launch_bounds__(256) void k_moments(const void* fsrc, Layout lay, i
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double val[MOM_NS] = { 0, 0, 0, 0, 0, 0, 0, 0 };
     if (k < n) {
-        const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
+        const int x = int(k % lay.nx), y = int(k / lay.nx);
         const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
         double v[L::Q];
         static_for<L::Q>([&](auto I) {
-            v[I] = double(S::load(f + here + int(I) * lay.te));
+            v[I] = double(S::load(f + state_index<L, RD, int(I)>(lay, x, y)));
             if (S::shifted) v[I] += L::v.w[I];
         });
         node_diag<L>(v, thermal, k, rho_o, ux_o, uy_o, th_o, val);

@@ -120,40 +120,78 @@ struct Dither {
     }
 };
 
-// Writes the Q post-collision values of one node (stochastic rounding where
-// the storage asks for it).
-template <class L, class S, class T, bool NT = true>
-__device__ __forceinline__ void store_node(typename S::elem* __restrict__ fout, int here, int te, const T (&v)[L::Q],
-                                           uint32_t node, uint32_t seq)
+// Writes the Q post-collision values of one node, value i to fout + at(i)
+// (stochastic rounding where the storage asks for it, the random bits drawn
+// in the order of i whatever the addresses).
+template <class L, class S, class T, bool NT, class At>
+__device__ __forceinline__ void store_node_at(typename S::elem* fout, At&& at, const T (&v)[L::Q], uint32_t node,
+                                              uint32_t seq)
 {
     // NT: non-temporal stores, for state buffers larger than the memory-side
     // cache; ordinary stores leave the written state there for the next step
     if constexpr (S::dithered) {
         Dither dz(node, seq);
         if constexpr (NT)
-            static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + here + int(I) * te, v[I], dz.next16()); });
+            static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + at(I), v[I], dz.next16()); });
         else
-            static_for<L::Q>([&](auto I) { S::store_sr(fout + here + int(I) * te, v[I], dz.next16()); });
+            static_for<L::Q>([&](auto I) { S::store_sr(fout + at(I), v[I], dz.next16()); });
     } else {
         if constexpr (NT)
-            static_for<L::Q>([&](auto I) { S::store_nt(fout + here + int(I) * te, v[I]); });
+            static_for<L::Q>([&](auto I) { S::store_nt(fout + at(I), v[I]); });
         else
-            static_for<L::Q>([&](auto I) { S::store(fout + here + int(I) * te, v[I]); });
+            static_for<L::Q>([&](auto I) { S::store(fout + at(I), v[I]); });
+    }
+}
+
+// The same into the node's own slots (plane i at `here`).
+template <class L, class S, class T, bool NT = true>
+__device__ __forceinline__ void store_node(typename S::elem* __restrict__ fout, int here, int te, const T (&v)[L::Q],
+                                           uint32_t node, uint32_t seq)
+{
+    store_node_at<L, S, T, NT>(fout, [&](auto I) { return here + int(I) * te; }, v, node, seq);
+}
+
+// Where value i of the post-collision state of node (x, y) is held.  RD 0:
+// the two-buffer state, plane i at the node.  The single-buffer AA state
+// after an even number of steps (RD 1): plane opp(i) at the node; after an
+// odd number (RD 2): plane i at the node x + c_i (periodic).
+template <class L>
+constexpr int opp_index(int i)
+{
+    return vel_index<L>(-L::v.cx[i], -L::v.cy[i]);
+}
+
+template <class L, int RD, int I>
+__device__ __forceinline__ int state_index(const Layout& lay, int x, int y)
+{
+    if constexpr (RD == 0) {
+        return lay.row(y) + x + I * lay.te;
+    } else if constexpr (RD == 1) {
+        return lay.row(y) + x + opp_index<L>(I) * lay.te;
+    } else {
+        constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
+        int xx = x + cx, yy = y + cy;
+        xx += xx < 0 ? lay.nx : 0;
+        xx -= xx >= lay.nx ? lay.nx : 0;
+        yy += yy < 0 ? lay.ny : 0;
+        yy -= yy >= lay.ny ? lay.ny : 0;
+        return lay.row(yy) + xx + I * lay.te;
     }
 }
 
 // ------------------------------------------------------ dump / reductions
 
-template <class L, class S>
+// The state as FP64 populations [i][y][x]; RD: where it sits (state_index).
+template <class L, class S, int RD = 0>
 __global__ __launch_bounds__(256) void k_populations(const void* fsrc, Layout lay, double* out)
 {
     const int64_t n = int64_t(lay.nx) * lay.ny;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
-    const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
+    const int x = int(k % lay.nx), y = int(k / lay.nx);
     const typename S::elem* f = static_cast<const typename S::elem*>(fsrc);
     static_for<L::Q>([&](auto I) {
-        double v = double(S::load(f + here + int(I) * lay.te));
+        double v = double(S::load(f + state_index<L, RD, int(I)>(lay, x, y)));
         if (S::shifted) v += L::v.w[I];
         out[int64_t(I) * n + k] = v;
     });

@@ -86,6 +86,10 @@ class FakePtr:
     (dict(flags=b.LBM_STORE_MOMENTS | b.LBM_COLL_PR), b.LBM_EINVAL),  # moments: RR only
     (dict(flags=b.LBM_STORE_MOMENTS | b.LBM_COLL_BGK), b.LBM_EINVAL),
     (dict(lattice=0, flags=b.LBM_STORE_MOMENTS | b.LBM_THERMAL), b.LBM_EINVAL),  # thermal needs D2V37
+    (dict(flags=b.LBM_SCHEME_AA), b.LBM_EINVAL),                     # one buffer: f_b must be NULL
+    (dict(flags=b.LBM_SCHEME_AA, no_fb=True, no_fa=True), b.LBM_EINVAL),
+    (dict(flags=b.LBM_SCHEME_AA | b.LBM_STORE_MOMENTS, no_fb=True), b.LBM_EINVAL),  # populations only
+    (dict(no_fb=True), b.LBM_EINVAL),                                # two buffers without the flag
 ])
 def test_init_rejects_invalid_arguments(args, code):
     p = dict(lattice=2, nx=8, ny=8, tau=0.6, reg_order=4, flags=0)
@@ -93,6 +97,10 @@ def test_init_rejects_invalid_arguments(args, code):
     fa, fb = FakePtr(0x1000), FakePtr(0x2000)
     if args.get("same_buffers"):
         fb = fa
+    if args.get("no_fb"):
+        fb = None
+    if args.get("no_fa"):
+        fa = None
     rho = None if args.get("no_rho") else FakePtr(0x3000)
     with pytest.raises(b.LbmError) as e:
         b.lbm_init(p["lattice"], p["nx"], p["ny"], p["tau"], p["reg_order"], p["flags"], fa, fb, rho,
@@ -180,6 +188,10 @@ def test_init_3d_rejects_invalid_arguments(args, code):
     fa, fb = FakePtr(0x1000), FakePtr(0x2000)
     if args.get("same_buffers"):
         fb = fa
+    if args.get("no_fb"):
+        fb = None
+    if args.get("no_fa"):
+        fa = None
     uz = None if args.get("no_uz") else FakePtr(0x6000)
     with pytest.raises(b.LbmError) as e:
         b.lbm_init_3d(p["lattice"], p["nx"], p["ny"], p["nz"], p["tau"], p["reg_order"], p["flags"], fa, fb,
