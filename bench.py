@@ -811,9 +811,10 @@ def main():
                     help="write the kernel-trace summary from a rocprofv3 database and that run's output")
     args = ap.parse_args()
     if args.scheme is None:
-        args.scheme = "pull" if args.storage == "moments" else "aa"
-    if args.scheme == "aa" and args.storage == "moments":
-        ap.error("the moment representation has the pull step only")
+        # the moment representation and the closure have the pull step only
+        args.scheme = "pull" if args.storage == "moments" or args.only_closure else "aa"
+    if args.scheme == "aa" and (args.storage == "moments" or args.only_closure):
+        ap.error("the moment representation and the closure have the pull step only")
 
     if args.summarize_pmc:
         print(summarize_pmc(args))

@@ -170,11 +170,10 @@ __device__ __forceinline__ void node_update_aa(typename S::elem* f, const Layout
     const int here = lay.row(y) + x;
 
     store_node_at<L, S, T, NT>(
-        f,
         [&](auto I) {
             constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
             constexpr int o = opp_index<L>(int(I));
-            return SHIFTED ? ys[R + cy] + xs[R + cx] + int(I) * lay.te : here + o * lay.te;
+            return f + (SHIFTED ? ys[R + cy] + xs[R + cx] + int(I) * lay.te : here + o * lay.te);
         },
         v, node, seq);
 }

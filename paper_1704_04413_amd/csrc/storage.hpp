@@ -120,26 +120,25 @@ struct Dither {
     }
 };
 
-// Writes the Q post-collision values of one node, value i to fout + at(i)
-// (stochastic rounding where the storage asks for it, the random bits drawn
-// in the order of i whatever the addresses).
+// Writes the Q post-collision values of one node, value i to the element
+// at(i) points to (stochastic rounding where the storage asks for it, the
+// random bits drawn in the order of i whatever the addresses).
 template <class L, class S, class T, bool NT, class At>
-__device__ __forceinline__ void store_node_at(typename S::elem* fout, At&& at, const T (&v)[L::Q], uint32_t node,
-                                              uint32_t seq)
+__device__ __forceinline__ void store_node_at(At&& at, const T (&v)[L::Q], uint32_t node, uint32_t seq)
 {
     // NT: non-temporal stores, for state buffers larger than the memory-side
     // cache; ordinary stores leave the written state there for the next step
     if constexpr (S::dithered) {
         Dither dz(node, seq);
         if constexpr (NT)
-            static_for<L::Q>([&](auto I) { S::store_nt_sr(fout + at(I), v[I], dz.next16()); });
+            static_for<L::Q>([&](auto I) { S::store_nt_sr(at(I), v[I], dz.next16()); });
         else
-            static_for<L::Q>([&](auto I) { S::store_sr(fout + at(I), v[I], dz.next16()); });
+            static_for<L::Q>([&](auto I) { S::store_sr(at(I), v[I], dz.next16()); });
     } else {
         if constexpr (NT)
-            static_for<L::Q>([&](auto I) { S::store_nt(fout + at(I), v[I]); });
+            static_for<L::Q>([&](auto I) { S::store_nt(at(I), v[I]); });
         else
-            static_for<L::Q>([&](auto I) { S::store(fout + at(I), v[I]); });
+            static_for<L::Q>([&](auto I) { S::store(at(I), v[I]); });
     }
 }
 
@@ -148,7 +147,9 @@ template <class L, class S, class T, bool NT = true>
 __device__ __forceinline__ void store_node(typename S::elem* __restrict__ fout, int here, int te, const T (&v)[L::Q],
                                            uint32_t node, uint32_t seq)
 {
-    store_node_at<L, S, T, NT>(fout, [&](auto I) { return here + int(I) * te; }, v, node, seq);
+    // the node's base pointer once, then one uniform plane offset per value
+    typename S::elem* const base = fout + here;
+    store_node_at<L, S, T, NT>([&](auto I) { return base + int(I) * te; }, v, node, seq);
 }
 
 // Where value i of the post-collision state of node (x, y) is held.  RD 0:
