@@ -438,17 +438,20 @@ def summarize_trace3d(args) -> str:
     out = [f"# rocprofv3 kernel trace: 3D lattices (Table II), {n}^3 extruded shear layer, FP64", "",
            "Command (repo root on an MI355X):", "", f"    {cmd}", "",
            f"Summary: `python3 bench.py --summarize-trace3d <run_results.db> <bench output>`", "",
-           "From the `top_kernels` view (durations in microseconds; the step kernel of each lattice and "
-           "collision is one template instance, `k_stream_collide3<L, MODE>` with MODE 0 RR, 2 BGK):", "",
+           "From the `top_kernels` view (durations in microseconds; the pull step of each lattice and "
+           "collision is one template instance, `k_stream_collide3<L, MODE, POL>` with MODE 0 RR, 2 BGK; the "
+           "single-buffer step two, `k_stream_collide3_aa<L, MODE, SHIFTED, NT>`, alternating):", "",
            "| kernel | calls | total us | average us | % |", "|---|---|---|---|---|"]
     for name, c, tot, avg, pct in rows:
         out.append(f"| `{name[:110]}` | {c} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
     out += ["", "Live HIP-event timing inside the same run (average step-kernel duration, algorithmic "
-                "bytes 2 Q 8 per node, fraction of the 8 TB/s HBM3E peak):", "",
-            "| lattice | collision | us per step | GB/s | % of peak |", "|---|---|---|---|---|"]
+                "bytes 2 Q 8 per node, fraction of the 8 TB/s HBM3E peak), pull step and single-buffer step:", "",
+            "| lattice | collision | pull us per step | GB/s | % of peak | AA us per step | GB/s | % of peak |",
+            "|---|---|---|---|---|---|---|---|"]
     for r in cases:
         out.append(f"| {r['lattice']} | {r['collision']} | {r['kernel_ms_avg'] * 1e3:.1f} | {r['kernel_GBs']:.0f} | "
-                   f"{r['frac_hbm'] * 100:.1f} |")
+                   f"{r['frac_hbm'] * 100:.1f} | {r['aa_kernel_ms_avg'] * 1e3:.1f} | {r['aa_kernel_GBs']:.0f} | "
+                   f"{r['aa_frac_hbm'] * 100:.1f} |")
     out += ["", f"kernel_source_hash: {kernel_source_hash('step3d.hip')}"]
     path = os.path.join(ROOT, "profiles", f"lattices3d_{n}_kernel_trace.md")
     with open(path, "w") as f:
@@ -539,15 +542,21 @@ def suite_3d(torch, b, wl, n=128, steps=30, warmup=3, only=None):
         if only is not None and (lat, coll) != only:
             continue
         flags = b.LBM_COLL_BGK if coll == "BGK" else 0
-        sim, meta = make_sim3(b, wl, lat, n, flags=flags)
-        wall, kms = time_steps(torch, sim, steps, warmup)
-        bad = int(sim.moments()["sums"][7])
-        sim.close()
         nodes = n ** 3
-        gbs = bytes_per_node(meta["q"], "fp64") * nodes / (kms * 1e-3) / 1e9
-        rows.append({"lattice": lat, "collision": coll, "n": n, "order": b.lbm_lattice_info(lat)[2] if coll == "RR"
-                     else None, "MLUPS": round(nodes * steps / wall / 1e6, 1), "kernel_ms_avg": round(kms, 4),
-                     "kernel_GBs": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "nonfinite": bad})
+        row = {"lattice": lat, "collision": coll, "n": n,
+               "order": b.lbm_lattice_info(lat)[2] if coll == "RR" else None}
+        # the pull step, then the single-buffer step on the same workload
+        for tag, fl in (("", flags), ("aa_", flags | b.LBM_SCHEME_AA)):
+            sim, meta = make_sim3(b, wl, lat, n, flags=fl)
+            wall, kms = time_steps(torch, sim, steps, warmup)
+            bad = int(sim.moments()["sums"][7])
+            sim.close()
+            gbs = bytes_per_node(meta["q"], "fp64") * nodes / (kms * 1e-3) / 1e9
+            row.update({f"{tag}MLUPS": round(nodes * steps / wall / 1e6, 1), f"{tag}kernel_ms_avg": round(kms, 4),
+                        f"{tag}kernel_GBs": round(gbs, 1), f"{tag}frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
+                        f"{tag}nonfinite": bad})
+        row["aa_over_pull"] = round(row["aa_MLUPS"] / row["MLUPS"], 3)
+        rows.append(row)
     return rows
 
 

@@ -52,19 +52,20 @@
  * Scheme (population storage only)
  *   By default a step gathers from one buffer into the other (f_a, f_b
  *   alternate).  LBM_SCHEME_AA keeps the state in f_a alone and updates it in
- *   place (the AA pattern): after an even number of steps the post-collision
- *   value f_i(x) sits in plane opp(i) at x (opp(i): the velocity -c_i), after
- *   an odd number in plane i at x + c_i (periodic); a step from an even count
- *   reads plane opp(i) at x - c_i and writes plane i at x + c_i, one from an
- *   odd count reads and writes node x's own planes.  Each node's update reads
- *   and then writes the same slots, so steps are race-free.  The states (and
- *   what lbm_populations, lbm_moments and the checkpoints give) are those of
- *   the two-buffer scheme bit for bit; a checkpoint holds f_a as it sits, so
- *   it loads only into an LBM_SCHEME_AA context.  It halves the state memory
- *   and the working set: faster where one buffer fits the 256 MiB
- *   memory-side cache but two do not, slower where the step streams from
- *   HBM (the shifted writes of every other step).  Not with
- *   LBM_STORE_MOMENTS, batches or the closure.
+ *   place (the AA pattern; 2D and 3D contexts): after an even number of
+ *   steps the post-collision value f_i(x) sits in plane opp(i) at x (opp(i):
+ *   the velocity -c_i), after an odd number in plane i at x + c_i
+ *   (periodic); a step from an even count reads plane opp(i) at x - c_i and
+ *   writes plane i at x + c_i, one from an odd count reads and writes node
+ *   x's own planes.  Each node's update reads and then writes the same
+ *   slots, so steps are race-free.  The states (and what lbm_populations,
+ *   lbm_moments, lbm_moments_3d and the checkpoints give) are those of the
+ *   two-buffer scheme bit for bit; a checkpoint holds f_a as it sits, so it
+ *   loads only into an LBM_SCHEME_AA context.  It halves the state memory
+ *   and the working set, which the 256 MiB memory-side cache then serves
+ *   better: on D2V37 FP64 it is 32% faster at 768^2 and 8% at 1024^2, on
+ *   D2V17 FP64 14% at 2048^2, and 3% slower at D2V37 FP64 2048^2 (1.2 GB).
+ *   Not with LBM_STORE_MOMENTS, batches or the closure.
  *
  * Environment (read when a context is created; none changes any result)
  *   RRLBM_CACHE_POLICY=0/1/2  forces the cache policy of the step: 0 ordinary
@@ -72,10 +73,11 @@
  *     order reversed every other step, 2 non-temporal loads and ordinary
  *     stores.  By default the policy follows the size of one state buffer
  *     (1 up to 128 MiB, 2 from 256 to 320 MiB, 0 otherwise; 3D: RR and BGK).
- *     With LBM_SCHEME_AA: 1 (the default at every size) ordinary stores,
- *     0 non-temporal stores in order, 2 non-temporal stores in the steps
- *     that write a node's own slots and ordinary ones in the others; with 1
- *     and 2 the tile order is reversed every other step.
+ *     With LBM_SCHEME_AA on 2D contexts: 1 (the default at every size)
+ *     ordinary stores, 0 non-temporal stores in order, 2 non-temporal stores
+ *     in the steps that write a node's own slots and ordinary ones in the
+ *     others; with 1 and 2 the tile order is reversed every other step.  3D
+ *     contexts with LBM_SCHEME_AA always take 1.
  *   RRLBM_XCD_REMAP=0  keeps the hardware's round-robin order of blocks over
  *     the 8 XCDs instead of giving each XCD a contiguous band of tiles.
  *   RRLBM_BATCH_SPLIT=1/2  (read by lbm_batch_create) gives each lattice of a
@@ -289,9 +291,12 @@ int64_t lbm_buffer_elems_3d(int lattice, int nx, int ny, int nz, uint32_t flags)
  *   nx, ny, nz each >= the lattice reach; lbm_buffer_elems_3d() < 2^31.
  *   tau        discrete relaxation time (> 1/2), nu = c_s^2 (tau - 1/2).
  *   reg_order  2 <= N <= n_eq (3, 6, 3, 4); ignored with LBM_COLL_BGK.
- *   flags      LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2 only.
+ *   flags      LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2, LBM_SCHEME_AA
+ *              only.
  *   f_a, f_b   two distinct device buffers of lbm_buffer_elems_3d() doubles,
- *              owned by the caller for the context's lifetime.
+ *              owned by the caller for the context's lifetime; with
+ *              LBM_SCHEME_AA (the single-buffer scheme of the 2D contexts,
+ *              with c_i and opp(i) in 3D) only f_a, and f_b must be NULL.
  *   rho, ux, uy, uz  device fields; noise device [q][z][y][x] or NULL.
  * Same errors as lbm_init. */
 int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, int reg_order, uint32_t flags,

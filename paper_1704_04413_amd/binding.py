@@ -415,8 +415,8 @@ class Simulation:
 
 
 class Simulation3D(Simulation):
-    """A 3D context (Table II lattices, FP64 populations) and its buffers;
-    fields are [z][y][x] arrays."""
+    """A 3D context (Table II lattices, FP64 populations) and its buffers
+    (two, or one with LBM_SCHEME_AA); fields are [z][y][x] arrays."""
 
     def __init__(self, lattice, nx, ny, nz, tau, rho, ux, uy, uz, noise=None, noise_amp=0.0, reg_order=None,
                  flags=0, device="cuda:0", stream=None):
@@ -430,7 +430,8 @@ class Simulation3D(Simulation):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         n = lbm_buffer_elems_3d(self.lattice, nx, ny, nz, flags)
-        self.bufs = [torch.empty(n, dtype=torch.float64, device=self.device) for _ in range(2)]
+        self.bufs = [torch.empty(n, dtype=torch.float64, device=self.device)
+                     for _ in range(1 if flags & LBM_SCHEME_AA else 2)]
 
         def dev(a):
             if a is None:
@@ -439,7 +440,8 @@ class Simulation3D(Simulation):
             return t.to(self.device, torch.float64).contiguous()
 
         fields = [dev(a) for a in (rho, ux, uy, uz, noise)]
-        self.ctx = lbm_init_3d(self.lattice, nx, ny, nz, tau, self.reg_order, flags, self.bufs[0], self.bufs[1],
+        f_b = self.bufs[1] if len(self.bufs) > 1 else None
+        self.ctx = lbm_init_3d(self.lattice, nx, ny, nz, tau, self.reg_order, flags, self.bufs[0], f_b,
                                *fields, noise_amp=noise_amp, stream=self.stream)
         self._keep = fields
 

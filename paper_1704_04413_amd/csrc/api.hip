@@ -454,7 +454,9 @@ int lbm_step(lbm_ctx* c, int nsteps)
     if (nsteps < 0) return fail(LBM_EINVAL, "nsteps < 0");
     for (int s = 0; s < nsteps; ++s) {
         hipError_t he;
-        if (c->aa) {
+        if (c->aa && c->dim == 3) {
+            he = ops3d(c->lattice).step_aa(c, (c->steps & 1) == 0);
+        } else if (c->aa) {
             he = ops2d(c->lattice, c->store).step_aa(c, (c->steps & 1) == 0, uint32_t(c->steps + 1));
         } else {
             he = launch_step(c, c->buf[c->cur], c->buf[1 - c->cur], true);
@@ -658,12 +660,17 @@ int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, 
     if (int64_t(ny) * nz >= (int64_t(1) << 31) || layout_elems(li.q, nx, ny * nz) >= (int64_t(1) << 31))
         return fail(LBM_EINVAL, "grid too large");
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_ETAU, "tau must be finite and > 1/2");
-    const uint32_t known = LBM_COLL_PR | LBM_COLL_BGK | LBM_EQ_INIT_ORDER2;
-    if (flags & ~known) return fail(LBM_EINVAL, "3D lattices take LBM_COLL_PR, LBM_COLL_BGK and LBM_EQ_INIT_ORDER2 only");
+    const uint32_t known = LBM_COLL_PR | LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_SCHEME_AA;
+    if (flags & ~known)
+        return fail(LBM_EINVAL, "3D lattices take LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2 and LBM_SCHEME_AA only");
     if ((flags & LBM_COLL_PR) && (flags & LBM_COLL_BGK)) return fail(LBM_EINVAL, "two collision flags");
     if (!(flags & LBM_COLL_BGK) && (reg_order < 2 || reg_order > li.n_eq))
         return fail(LBM_EINVAL, "regularization order must be in [2, " + std::to_string(li.n_eq) + "]");
-    if (!f_a || !f_b || f_a == f_b) return fail(LBM_EINVAL, "two distinct population buffers are needed");
+    if (flags & LBM_SCHEME_AA) {
+        if (!f_a || f_b) return fail(LBM_EINVAL, "LBM_SCHEME_AA takes f_a and a NULL f_b");
+    } else if (!f_a || !f_b || f_a == f_b) {
+        return fail(LBM_EINVAL, "two distinct population buffers are needed");
+    }
     if (!rho || !ux || !uy || !uz) return fail(LBM_EINVAL, "rho, ux, uy and uz are required");
     if (!std::isfinite(noise_amp)) return fail(LBM_EINVAL, "noise_amp not finite");
 
@@ -681,19 +688,27 @@ int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, 
     c->flags = flags;
     c->store = ST_F64;
     c->coll = (flags & LBM_COLL_PR) ? COLL_PR : (flags & LBM_COLL_BGK) ? COLL_BGK : COLL_RR;
+    c->aa = (flags & LBM_SCHEME_AA) != 0;
     c->q = li.q;
     c->lay = make_layout(li.q, nx, ny * nz);
-    c->pol = choose_policy(int64_t(sizeof(double)) * layout_elems(li.q, nx, ny * nz));
+    c->pol = choose_policy(int64_t(sizeof(double)) * layout_elems(li.q, nx, ny * nz), c->aa);
     if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     c->buf[0] = f_a;
     c->buf[1] = f_b;
     c->stream = static_cast<hipStream_t>(stream);
     const int64_t n = int64_t(nx) * ny * nz;
     c->nblk = (n + 255) / 256;
-    // f^(0) goes to f_b shifted by -c_i; one pull launch then collides it into f_a
-    hipError_t he = ops3d(lattice).init(c, f_b, rho, ux, uy, uz, noise, noise_amp,
-                                        (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq);
-    if (he == hipSuccess) he = launch_step(c, f_b, f_a, true); // post-collision state in f_a, cur = 0
+    const int eq_order = (flags & LBM_EQ_INIT_ORDER2) ? 2 : li.n_eq;
+    hipError_t he;
+    if (c->aa) {
+        // f^(0) into f_a, collided in place into the placement of an even step count
+        he = ops3d(lattice).init(c, f_a, rho, ux, uy, uz, noise, noise_amp, eq_order);
+        if (he == hipSuccess) he = ops3d(lattice).step_aa(c, false);
+    } else {
+        // f^(0) goes to f_b shifted by -c_i; one pull launch then collides it into f_a
+        he = ops3d(lattice).init(c, f_b, rho, ux, uy, uz, noise, noise_amp, eq_order);
+        if (he == hipSuccess) he = launch_step(c, f_b, f_a, true); // post-collision state in f_a, cur = 0
+    }
     if (he != hipSuccess) {
         delete c;
         return fail(LBM_EDEVICE, std::string("init launch: ") + hipGetErrorString(he));

@@ -269,6 +269,17 @@ __device__ __forceinline__ void collide3(double (&v)[L::Q], const Relax& rx, int
 // POL: cache policy as in the 2D step (POL_STREAM ordinary loads and
 // non-temporal stores, POL_CACHE ordinary loads and stores, POL_KEEP
 // non-temporal loads and ordinary stores).
+__device__ __forceinline__ int block_index3(const Step3Args& a)
+{
+    int bid = int(blockIdx.x);
+    if (a.xcd_remap) {
+        // the hardware deals blocks to the 8 XCDs round-robin
+        const int q = a.nblocks / 8, r = a.nblocks % 8, xcd = bid % 8, local = bid / 8;
+        bid = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
+    }
+    return a.reverse ? a.nblocks - 1 - bid : bid;
+}
+
 template <class L, int MODE, int POL>
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU_3D)))
 void k_stream_collide3(Step3Args a)
@@ -276,13 +287,7 @@ void k_stream_collide3(Step3Args a)
     static_assert(BX == 64, "one wave per row segment");
     constexpr int R = L::R;
     const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
-    int bid = int(blockIdx.x);
-    if (a.xcd_remap) {
-        // the hardware deals blocks to the 8 XCDs round-robin
-        const int q = a.nblocks / 8, r = a.nblocks % 8, xcd = bid % 8, local = bid / 8;
-        bid = xcd < r ? xcd * (q + 1) + local : r * (q + 1) + (xcd - r) * q + local;
-    }
-    if (a.reverse) bid = a.nblocks - 1 - bid;
+    const int bid = block_index3(a);
     const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y)); // uniform within a wave
     const int row = (bid / a.bx_blocks) * BY + ty;
     const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
@@ -331,6 +336,93 @@ void k_stream_collide3(Step3Args a)
     });
 }
 
+// The index of -c_i.
+template <class L>
+constexpr int opp_index3(int i)
+{
+    for (int j = 0; j < L::Q; ++j)
+        if (L::v.cx[j] == -L::v.cx[i] && L::v.cy[j] == -L::v.cy[i] && L::v.cz[j] == -L::v.cz[i]) return j;
+    return -1;
+}
+
+// Hides a wave-uniform value from the optimizer (no instruction is emitted).
+__device__ __forceinline__ void opaque_s(int& v) { asm volatile("" : "+s"(v)); }
+__device__ __forceinline__ void opaque_v(int& v) { asm volatile("" : "+v"(v)); }
+
+// The in-place step on one buffer (the AA pattern), as in 2D: !SHIFTED (the
+// state after an odd number of steps, or the initial populations) reads
+// value i from the node's own plane i and writes it to its own plane opp(i);
+// SHIFTED (after an even number) reads plane opp(i) of the node x - c_i and
+// writes plane i of the node x + c_i.  Each thread writes exactly the slots
+// it has read, after reading all of them.  Addressing as in the pull kernel
+// (wave-uniform row bases, per-lane byte offsets of x).
+template <class L, int MODE, bool SHIFTED, bool NT>
+__global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU_3D)))
+void k_stream_collide3_aa(Step3Args a)
+{
+    static_assert(BX == 64, "one wave per row segment");
+    constexpr int R = L::R;
+    const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
+    const int bid = block_index3(a);
+    const int ty = __builtin_amdgcn_readfirstlane(int(threadIdx.y)); // uniform within a wave
+    int row = (bid / a.bx_blocks) * BY + ty;
+    int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
+    if (row >= ny * nz || x >= nx) return;
+
+    // byte offset of x + d and rows y + d, z + d (periodic), d in [-R, R]
+    uint32_t xb[2 * R + 1];
+    int ys[2 * R + 1], zs[2 * R + 1];
+    auto neighbours = [&](int x0, int row0) {
+        const int y0 = row0 % ny, z0 = row0 / ny;
+        static_for<2 * R + 1>([&](auto D) {
+            constexpr int d = int(D) - R;
+            int xx = x0 + d, yy = y0 + d, zz = z0 + d;
+            if constexpr (d < 0) {
+                xx += (xx < 0) ? nx : 0;
+                yy += (yy < 0) ? ny : 0;
+                zz += (zz < 0) ? nz : 0;
+            } else if constexpr (d > 0) {
+                xx -= (xx >= nx) ? nx : 0;
+                yy -= (yy >= ny) ? ny : 0;
+                zz -= (zz >= nz) ? nz : 0;
+            }
+            xb[D] = uint32_t(xx) * uint32_t(sizeof(double));
+            ys[D] = yy;
+            zs[D] = zz;
+        });
+    };
+    char* f = static_cast<char*>(a.fout);
+    const int64_t plane = int64_t(a.lay.te) * int64_t(sizeof(double));
+    auto slot = [&](int dz, int dy, uint32_t xoff, int i) {
+        const int64_t r = int64_t(a.lay.row(zs[dz + R] * ny + ys[dy + R])) * int64_t(sizeof(double));
+        return reinterpret_cast<double*>(f + r + int64_t(i) * plane + xoff);
+    };
+    neighbours(x, row);
+    double v[L::Q];
+    static_for<L::Q>([&](auto I) {
+        constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
+        constexpr int o = opp_index3<L>(int(I)); // a compile-time constant, not a run-time search
+        if constexpr (SHIFTED)
+            v[I] = *slot(-cz, -cy, xb[R - cx], o);
+        else
+            v[I] = *slot(0, 0, xb[R], int(I));
+    });
+    // The stores go to the addresses the loads used; hiding the node makes
+    // the compiler rebuild them rather than hold all Q across the collision.
+    opaque_s(row);
+    opaque_v(x);
+    neighbours(x, row);
+    collide3<L, MODE>(v, a.rx, a.order, [&](auto I, double val) {
+        constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
+        constexpr int o = opp_index3<L>(int(I));
+        double* p = SHIFTED ? slot(cz, cy, xb[R + cx], int(I)) : slot(0, 0, xb[R], o);
+        if constexpr (NT)
+            __builtin_nontemporal_store(val, p);
+        else
+            *p = val;
+    });
+}
+
 struct Init3Args {
     void* f;
     Layout lay;
@@ -340,11 +432,12 @@ struct Init3Args {
     int eq_order;
 };
 
-// f^(0) over the basis up to rank eq_order plus noise_amp w_i noise_i,
-// written for the first pull: value i of node x goes to node x - c_i, so
+// f^(0) over the basis up to rank eq_order plus noise_amp w_i noise_i.
+// SHIFT: written for the first pull, value i of node x to node x - c_i, so
 // that one step kernel launch gathers f^(0) back at every node and collides
-// it (the kept state is post-collision).
-template <class L>
+// it (the kept state is post-collision); !SHIFT: value i in the node's own
+// plane i, for the in-place local kernel.
+template <class L, bool SHIFT = true>
 __global__ __launch_bounds__(256) void k_init3(Init3Args a)
 {
     const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
@@ -360,7 +453,7 @@ __global__ __launch_bounds__(256) void k_init3(Init3Args a)
         [&](auto I, double val) {
             constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
             if (a.noise) val += a.noise_amp * L::v.w[I] * a.noise[int64_t(I) * n + k];
-            int xd = x - cx, yd = y - cy, zd = z - cz; // |c| <= reach <= each dimension
+            int xd = SHIFT ? x - cx : x, yd = SHIFT ? y - cy : y, zd = SHIFT ? z - cz : z; // |c| <= reach
             xd += xd < 0 ? nx : (xd >= nx ? -nx : 0);
             yd += yd < 0 ? ny : (yd >= ny ? -ny : 0);
             zd += zd < 0 ? nz : (zd >= nz ? -nz : 0);
@@ -371,7 +464,39 @@ __global__ __launch_bounds__(256) void k_init3(Init3Args a)
 
 // rho, u per node and block sums of [rho, rho ux, rho uy, rho uz,
 // sum f |c|^2 / 2, |u|^2, |u|^4, non-finite].
-template <class L>
+// Where value I of node (x, y, z) is held: RD 0 the two-buffer state
+// (plane I at the node); the single-buffer state after an even number of
+// steps (RD 1): plane opp(I) at the node; after an odd number (RD 2): plane
+// I at the node x + c_I (periodic).
+template <class L, int RD, int I>
+__device__ __forceinline__ int state_index3(const Layout& lay, int ny, int nz, int x, int y, int z)
+{
+    if constexpr (RD == 0) {
+        return lay.row(z * ny + y) + x + I * lay.te;
+    } else if constexpr (RD == 1) {
+        return lay.row(z * ny + y) + x + opp_index3<L>(I) * lay.te;
+    } else {
+        constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
+        int xx = x + cx, yy = y + cy, zz = z + cz;
+        xx += xx < 0 ? lay.nx : (xx >= lay.nx ? -lay.nx : 0);
+        yy += yy < 0 ? ny : (yy >= ny ? -ny : 0);
+        zz += zz < 0 ? nz : (zz >= nz ? -nz : 0);
+        return lay.row(zz * ny + yy) + xx + I * lay.te;
+    }
+}
+
+// The state as populations [i][z][y][x].
+template <class L, int RD>
+__global__ __launch_bounds__(256) void k_populations3(const double* f, Layout lay, int ny, int nz, double* out)
+{
+    const int64_t n = int64_t(lay.nx) * ny * nz;
+    const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (k >= n) return;
+    const int x = int(k % lay.nx), row = int(k / lay.nx), y = row % ny, z = row / ny;
+    static_for<L::Q>([&](auto I) { out[int64_t(I) * n + k] = f[state_index3<L, RD, int(I)>(lay, ny, nz, x, y, z)]; });
+}
+
+template <class L, int RD = 0>
 __global__ __launch_bounds__(256) void k_moments3(const double* f, Layout lay, int ny, int nz, double* rho_o,
                                                   double* ux_o, double* uy_o, double* uz_o, double* partial)
 {
@@ -379,11 +504,11 @@ __global__ __launch_bounds__(256) void k_moments3(const double* f, Layout lay, i
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     double val[MOM3_NS] = { 0, 0, 0, 0, 0, 0, 0, 0 };
     if (k < n) {
-        const int here = lay.row(int(k / lay.nx)) + int(k % lay.nx);
+        const int x = int(k % lay.nx), row = int(k / lay.nx), y = row % ny, z = row / ny;
         double r = 0, jx = 0, jy = 0, jz = 0, e2 = 0;
         static_for<L::Q>([&](auto I) {
             constexpr double cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
-            const double v = f[here + int(I) * lay.te];
+            const double v = f[state_index3<L, RD, int(I)>(lay, ny, nz, x, y, z)];
             r += v;
             jx += cx * v;
             jy += cy * v;

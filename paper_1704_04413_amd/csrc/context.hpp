@@ -101,6 +101,11 @@ const Ops2D& ops2d(int lattice, int store);
 // One 3D lattice: the kernels of step3d.hip compiled for it.
 struct Ops3D {
     hipError_t (*step)(const lbm_ctx* c, const void* fin, void* fout);
+    // one in-place step of the single-buffer scheme on buf[0] (shifted: the
+    // placement after an even number of steps, or the initial collision when not)
+    hipError_t (*step_aa)(const lbm_ctx* c, bool shifted);
+    // the initial populations into dst: shifted for the first pull, or in
+    // place for the single-buffer scheme
     hipError_t (*init)(const lbm_ctx* c, void* dst, const double* rho, const double* ux, const double* uy,
                        const double* uz, const double* noise, double noise_amp, int eq_order);
     hipError_t (*populations)(const lbm_ctx* c, const void* src, double* out);

@@ -1,7 +1,9 @@
 // The 3D step for one lattice of Table II, chosen at compile time: this file
-// is compiled once per lattice (RR_LAT3 = LBM_D3Q19, LBM_D3Q27, LBM_D3V39 or
-// LBM_D3Q103).  It provides the pull step for every collision and cache
-// policy, the initial state, the population dump and the diagnostics.
+// is compiled twice per lattice (RR_LAT3 = LBM_D3Q19, LBM_D3Q27, LBM_D3V39 or
+// LBM_D3Q103), so that the two halves build in parallel.  With RR_AA3 = 0 it
+// provides the pull step for every collision and cache policy, the initial
+// state, the population dump and the diagnostics; with RR_AA3 = 1 the
+// in-place single-buffer step for every collision.
 #include "context.hpp"
 #include "storage.hpp"
 #include "collide3d.hpp"
@@ -9,8 +11,18 @@
 #if !defined(RR_LAT3)
 #error "compile with -DRR_LAT3=<3D lattice id>"
 #endif
+#if !defined(RR_AA3)
+#define RR_AA3 0
+#endif
+
+#define RR_STEP3_AA_NAME_(l) step3d_aa_##l
+#define RR_STEP3_AA_NAME(l) RR_STEP3_AA_NAME_(l)
 
 namespace rr {
+
+// one in-place step of the single-buffer scheme (the RR_AA3 = 1 unit)
+hipError_t RR_STEP3_AA_NAME(RR_LAT3)(const lbm_ctx* c, bool shifted);
+
 namespace {
 
 #if RR_LAT3 == 3
@@ -24,6 +36,8 @@ using Lat = D3Q103;
 #else
 #error "RR_LAT3 must be a 3D lattice"
 #endif
+
+#if RR_AA3 == 0
 
 template <int MODE>
 hipError_t step_t(const lbm_ctx* c, const void* fin, void* fout)
@@ -62,32 +76,84 @@ hipError_t init(const lbm_ctx* c, void* dst, const double* rho, const double* ux
                 const double* uz, const double* noise, double noise_amp, int eq_order)
 {
     const Init3Args ia{ dst, c->lay, c->ny, c->nz, rho, ux, uy, uz, noise, noise_amp, eq_order };
-    k_init3<Lat><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
+    // the single-buffer scheme collides the initial populations in place
+    if (c->aa)
+        k_init3<Lat, false><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
+    else
+        k_init3<Lat, true><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
     return hipGetLastError();
 }
 
 hipError_t populations(const lbm_ctx* c, const void* src, double* out)
 {
     const int64_t n = int64_t(c->nx) * c->ny * c->nz;
-    k_populations<Lat, StoreF64><<<dim3(unsigned((n + 255) / 256)), dim3(256), 0, c->stream>>>(src, c->lay, out);
+    const dim3 grid(unsigned((n + 255) / 256)), block(256);
+    const double* f = static_cast<const double*>(src);
+    switch (state_placement(c)) {
+    case 1: k_populations3<Lat, 1><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out); break;
+    case 2: k_populations3<Lat, 2><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out); break;
+    default: k_populations3<Lat, 0><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out);
+    }
     return hipGetLastError();
 }
 
 hipError_t moments(const lbm_ctx* c, double* r, double* ux, double* uy, double* uz, double* partial)
 {
-    k_moments3<Lat><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(
-        static_cast<const double*>(c->buf[c->cur]), c->lay, c->ny, c->nz, r, ux, uy, uz, partial);
+    const dim3 grid(unsigned(c->nblk)), block(256);
+    const double* f = static_cast<const double*>(c->buf[c->cur]);
+    switch (state_placement(c)) {
+    case 1: k_moments3<Lat, 1><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial); break;
+    case 2: k_moments3<Lat, 2><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial); break;
+    default: k_moments3<Lat, 0><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial);
+    }
     return hipGetLastError();
 }
 
+#else // RR_AA3 == 1
+
+template <int MODE>
+hipError_t step_aa_t(const lbm_ctx* c, bool shifted)
+{
+    const int rows = c->ny * c->nz;
+    const int bxn = (c->nx + BX - 1) / BX, byn = (rows + BY - 1) / BY;
+    // ordinary stores with the tile order reversed every other step (the 2D
+    // scheme's default policy; the others are not built for 3D, each kernel
+    // of the largest lattice costing half a minute of build)
+    Step3Args a{ c->buf[0], c->buf[0], c->lay, c->ny, c->nz, bxn, bxn * byn, c->xcd_remap, relax_of(c), c->order,
+                 (c->steps & 1) ? 1 : 0 };
+    const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
+    if (shifted)
+        k_stream_collide3_aa<Lat, MODE, true, false><<<grid, block, 0, c->stream>>>(a);
+    else
+        k_stream_collide3_aa<Lat, MODE, false, false><<<grid, block, 0, c->stream>>>(a);
+    return hipGetLastError();
+}
+
+#endif
+
 } // namespace
+
+#if RR_AA3 == 0
 
 #define RR_OPS3D_NAME_(l) ops3d_##l
 #define RR_OPS3D_NAME(l) RR_OPS3D_NAME_(l)
 const Ops3D& RR_OPS3D_NAME(RR_LAT3)()
 {
-    static const Ops3D ops{ step, init, populations, moments };
+    static const Ops3D ops{ step, RR_STEP3_AA_NAME(RR_LAT3), init, populations, moments };
     return ops;
 }
+
+#else
+
+hipError_t RR_STEP3_AA_NAME(RR_LAT3)(const lbm_ctx* c, bool shifted)
+{
+    switch (c->coll) {
+    case COLL_PR: return step_aa_t<C3_PR>(c, shifted);
+    case COLL_BGK: return step_aa_t<C3_BGK>(c, shifted);
+    default: return step_aa_t<C3_RR>(c, shifted);
+    }
+}
+
+#endif
 
 } // namespace rr

@@ -181,6 +181,9 @@ def test_3d_buffer_elems():
     (dict(flags=b.LBM_COLL_PR | b.LBM_COLL_BGK), b.LBM_EINVAL),
     (dict(same_buffers=True), b.LBM_EINVAL),
     (dict(no_uz=True), b.LBM_EINVAL),
+    (dict(flags=b.LBM_SCHEME_AA), b.LBM_EINVAL),                      # one buffer: f_b must be NULL
+    (dict(flags=b.LBM_SCHEME_AA, no_fb=True, no_fa=True), b.LBM_EINVAL),
+    (dict(no_fb=True), b.LBM_EINVAL),                                 # two buffers without the flag
 ])
 def test_init_3d_rejects_invalid_arguments(args, code):
     p = dict(lattice=b.LBM_D3V39, nx=8, ny=8, nz=8, tau=0.6, reg_order=3, flags=0)

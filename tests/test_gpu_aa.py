@@ -10,8 +10,11 @@ buffer (the slot depends on the parity of the step count), so:
     arithmetic, same node keys and step numbers for the BF16 dither), with
     every cache policy, on ragged grids and on grids as small as the
     stencil reach (where the periodic wraps alias);
-  - checkpoints taken after even and odd step counts resume bit for bit.
+  - checkpoints taken after even and odd step counts resume bit for bit;
+  - the same on the 3D lattices of Table II (RR, PR and BGK).
 """
+import math
+
 import numpy as np
 import pytest
 
@@ -195,3 +198,108 @@ def test_aa_rejected_by_batches_and_closure(b):
         b.lbm_closure_samples(sim.ctx, 2, x, x)
     assert e.value.code == b.LBM_EINVAL
     sim.close()
+
+
+# ---------------------------------------------------------------- 3D lattices
+
+NAMES_3D = ["D3Q19", "D3Q27", "D3V39", "D3Q103"]
+COLLS_3D = {"RR": (0, 0), "PR": (1, 0x10), "BGK": (2, 0x20)}
+
+
+def fields_3d(b, name, dims, seed=0, mach=0.1):
+    nx, ny, nz = dims
+    q, _, _, cs2 = b.lbm_lattice_info(name)
+    rho, ux, uy, uz = wl.shear_layer_fields_3d(nx, ny, nz, mach * math.sqrt(cs2), k=20.0, delta=0.1)
+    return rho, ux, uy, uz, wl.uniform_noise_3d(seed, q, nz, ny, nx)
+
+
+def run_3d(b, name, dims, tau, fields, flags, steps, relax=None, order=None):
+    rho, ux, uy, uz, noise = fields
+    sim = b.Simulation3D(name, *dims, tau, rho, ux, uy, uz, noise=noise, noise_amp=1e-6, flags=flags,
+                         reg_order=order)
+    assert len(sim.bufs) == (1 if flags & AA else 2)
+    if relax:
+        sim.set_relaxation(*relax)
+    sim.step(steps)
+    mom = sim.moments()
+    out = dict(f=sim.populations().cpu().numpy(), sums=np.asarray(mom["sums"]),
+               **{k: mom[k].cpu().numpy() for k in ("rho", "ux", "uy", "uz")})
+    assert sim.steps == steps
+    sim.close()
+    return out
+
+
+def assert_same_3d(got, want):
+    for k in ("f", "rho", "ux", "uy", "uz", "sums"):
+        np.testing.assert_array_equal(got[k], want[k], err_msg=k)
+
+
+@pytest.mark.parametrize("name", NAMES_3D)
+@pytest.mark.parametrize("steps", [5, 6])
+def test_aa_3d_matches_oracle(b, name, steps):
+    """70 x 5 x 3: two 64-wide x blocks with a ragged tail, 15 rows (not a
+    multiple of the 4-row tile)."""
+    from oracle import o3d
+
+    o3d.build()
+    dims, tau = (70, 5, 3), 0.52
+    say(f"AA 3D RR {name} {dims} steps={steps} against the oracle")
+    lat = o3d.lattice(name)
+    rho, ux, uy, uz, noise = fields_3d(b, name, dims)
+    f0 = o3d.equilibrium(lat, rho, ux, uy, uz) + 1e-6 * lat.w[:, None, None, None] * noise
+    got = run_3d(b, name, dims, tau, (rho, ux, uy, uz, noise), AA, steps)
+    want = o3d.collide(lat, o3d.step(lat, f0, tau, steps), tau)
+    err = float(np.abs(got["f"] - want).max())
+    print(f"[parity] max |gpu - oracle| = {err:.3e} (bound 1e-12)", flush=True)
+    assert err <= 1e-12, err
+
+
+@pytest.mark.parametrize("name", NAMES_3D)
+@pytest.mark.parametrize("coll", ["RR", "PR", "BGK"])
+def test_aa_3d_equals_pull_bitwise(b, name, coll):
+    dims = (66, 6, 5)
+    say(f"AA vs pull 3D {name} {coll} {dims}")
+    fields = fields_3d(b, name, dims, seed=3)
+    flags = COLLS_3D[coll][1]
+    relax = (0.62, 0.9) if coll != "BGK" else None
+    for s in (4, 5):
+        assert_same_3d(run_3d(b, name, dims, 0.6, fields, flags | AA, s, relax=relax),
+                       run_3d(b, name, dims, 0.6, fields, flags, s, relax=relax))
+
+
+@pytest.mark.parametrize("policy", ["0", "1", "2"])
+def test_aa_3d_policies(b, policy, monkeypatch):
+    dims = (66, 6, 5)
+    say(f"AA 3D D3Q27 policy {policy}")
+    fields = fields_3d(b, "D3Q27", dims, seed=4)
+    want = run_3d(b, "D3Q27", dims, 0.6, fields, 0, 7)
+    monkeypatch.setenv("RRLBM_CACHE_POLICY", policy)
+    assert_same_3d(run_3d(b, "D3Q27", dims, 0.6, fields, AA, 7), want)
+
+
+@pytest.mark.parametrize("name,dims", [("D3Q19", (1, 1, 1)), ("D3Q27", (2, 1, 3)), ("D3V39", (3, 3, 3)),
+                                       ("D3Q103", (3, 4, 3))])
+def test_aa_3d_minimum_grids(b, name, dims):
+    say(f"AA 3D minimum grid {name} {dims}")
+    fields = fields_3d(b, name, dims, seed=5)
+    for s in (6, 7):
+        assert_same_3d(run_3d(b, name, dims, 0.7, fields, AA, s), run_3d(b, name, dims, 0.7, fields, 0, s))
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_aa_3d_checkpoint_resume(b, k):
+    name, dims, total = "D3Q19", (12, 12, 12), 5
+    say(f"AA 3D checkpoint {name} {k}+{total - k} steps")
+    fields = fields_3d(b, name, dims, seed=6)
+    rho, ux, uy, uz, noise = fields
+    want = run_3d(b, name, dims, 0.7, fields, AA, total)["f"]
+    first = b.Simulation3D(name, *dims, 0.7, rho, ux, uy, uz, noise=noise, noise_amp=1e-6, flags=AA)
+    first.step(k)
+    buf = first.save()
+    first.close()
+    second = b.Simulation3D(name, *dims, 0.7, rho, ux, uy, uz, flags=AA)
+    second.load(buf)
+    assert second.steps == k
+    second.step(total - k)
+    np.testing.assert_array_equal(second.populations().cpu().numpy(), want)
+    second.close()
