@@ -474,7 +474,8 @@ __device__ __forceinline__ int state_index3(const Layout& lay, int ny, int nz, i
     if constexpr (RD == 0) {
         return lay.row(z * ny + y) + x + I * lay.te;
     } else if constexpr (RD == 1) {
-        return lay.row(z * ny + y) + x + opp_index3<L>(I) * lay.te;
+        constexpr int o = opp_index3<L>(I); // folded at compile time
+        return lay.row(z * ny + y) + x + o * lay.te;
     } else {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
         int xx = x + cx, yy = y + cy, zz = z + cz;

@@ -168,7 +168,8 @@ __device__ __forceinline__ int state_index(const Layout& lay, int x, int y)
     if constexpr (RD == 0) {
         return lay.row(y) + x + I * lay.te;
     } else if constexpr (RD == 1) {
-        return lay.row(y) + x + opp_index<L>(I) * lay.te;
+        constexpr int o = opp_index<L>(I); // folded at compile time
+        return lay.row(y) + x + o * lay.te;
     } else {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I];
         int xx = x + cx, yy = y + cy;

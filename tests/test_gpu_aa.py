@@ -303,3 +303,24 @@ def test_aa_3d_checkpoint_resume(b, k):
     second.step(total - k)
     np.testing.assert_array_equal(second.populations().cpu().numpy(), want)
     second.close()
+
+
+@pytest.mark.parametrize("steps", [4, 5])
+def test_aa_noalloc_moments(b, steps):
+    """The allocation-free diagnostics read the single-buffer state through
+    the same placement as lbm_moments, at both parities."""
+    import torch
+
+    name, n = "D2V37", 90
+    say(f"AA noalloc moments {name} {n}x{n} steps={steps}")
+    tau, (rho, ux, uy, _, noise) = fields_for(b, name, n, n, 0)
+    sim = b.Simulation(name, n, n, tau, rho, ux, uy, noise=noise, noise_amp=1e-8, flags=AA)
+    sim.step(steps)
+    mk = lambda: torch.empty((n, n), dtype=torch.float64, device="cuda")
+    want, got = [mk() for _ in range(5)], [mk() for _ in range(5)]
+    s_want = b.lbm_moments(sim.ctx, *want, sums=True)
+    s_got = b.lbm_moments_noalloc(sim.ctx, *got, sums=True)
+    for w, g in zip(want, got):
+        assert torch.equal(w, g)
+    np.testing.assert_array_equal(s_got, s_want)
+    sim.close()
