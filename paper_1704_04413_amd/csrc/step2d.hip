@@ -39,11 +39,12 @@ using Sto = StoreF32D;
 template <int COLL, bool TH, bool A13P>
 hipError_t step_t(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
-    const StepArgs a = step_args(c, fin, fout, pull);
-    const dim3 grid(unsigned(a.nblocks)), block(BX, BY);
     if constexpr (Lat::id == LBM_D2V37 && COLL == COLL_RR && !TH) {
         if (pull && c->closure) return closure_step(c, fin, fout);
     }
+    using B = StepBlock<Lat, Sto, false>;
+    const StepArgs a = step_blocks<B>(step_args(c, fin, fout, pull));
+    const dim3 grid(unsigned(a.nblocks)), block(B::x, B::y);
     if (!pull)
         k_stream_collide<Lat, Sto, COLL, TH, A13P, false, POL_STREAM><<<grid, block, 0, c->stream>>>(a);
     else if (c->pol == POL_CACHE)
@@ -78,14 +79,15 @@ hipError_t step(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 template <int COLL, bool TH, bool A13P>
 hipError_t step_aa_t(const lbm_ctx* c, bool shifted, uint32_t seq)
 {
-    StepArgs a = step_args(c, c->buf[0], c->buf[0], true);
+    using B = StepBlock<Lat, Sto, true>;
+    StepArgs a = step_blocks<B>(step_args(c, c->buf[0], c->buf[0], true));
     a.seq = seq;
     // POL_STREAM: non-temporal stores, tiles in order.  POL_CACHE: ordinary
     // stores; POL_KEEP: non-temporal stores where they fill whole lines (the
     // node's own slots) and ordinary ones where they are shifted; with both,
     // the tile order is reversed every other step.
     a.reverse = (c->pol != POL_STREAM && (c->steps & 1)) ? 1 : 0;
-    const dim3 grid(unsigned(a.nblocks)), block(BX, BY);
+    const dim3 grid(unsigned(a.nblocks)), block(B::x, B::y);
     const bool nt = c->pol == POL_STREAM || (c->pol == POL_KEEP && !shifted);
     if (shifted && nt)
         k_stream_collide_aa<Lat, Sto, COLL, TH, A13P, true, true><<<grid, block, 0, c->stream>>>(a);

@@ -35,6 +35,28 @@ namespace rr {
 #define RRLBM_AA_WAVES_PER_EU 4
 #endif
 
+// Block of the 2D step kernels (pull and in-place): four waves side by side
+// along x on one row, 256 consecutive nodes, or one wave per row of a 4-row
+// tile (64 x 4).  The wide block measured faster on every lattice and storage
+// but the D2Q9 FP64 pull step (% of the HBM peak, 64 x 4 -> 256 x 1: D2V37
+// FP64 1024^2 pull 75.9 -> 79.2, in place 80.6 -> 84.3; D2V37 FP32 2048^2
+// pull 68.3 -> 72.8; D2Q9 FP64 4096^2 pull 74.3 -> 71.7).  The closure and
+// batch kernels keep 64 x 4.
+template <class L, class S, bool INPLACE>
+struct StepBlock {
+    static constexpr bool tall = !INPLACE && L::Q == 9 && sizeof(typename S::elem) == 8;
+    static constexpr int x = tall ? BX : 4 * BX, y = tall ? BY : 1;
+};
+
+// The launch shape of a 2D step over the whole grid in blocks of B.
+template <class B>
+inline StepArgs step_blocks(StepArgs a)
+{
+    a.bx_blocks = (a.lay.nx + B::x - 1) / B::x;
+    a.nblocks = a.bx_blocks * ((a.lay.ny + B::y - 1) / B::y);
+    return a;
+}
+
 // The hardware hands consecutive workgroup ids to the 8 XCDs in turn; with
 // the remap, XCD k works on the k-th contiguous eighth of the tiles, so
 // neighbouring tiles share that XCD's L2.
@@ -98,9 +120,10 @@ template <class L, class S, int COLL, bool THERMAL, bool A13P, bool PULL, int PO
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU)))
 void k_stream_collide(StepArgs a)
 {
+    using B = StepBlock<L, S, false>;
     const int bid = block_index(a);
-    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
-    const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
+    const int x = (bid % a.bx_blocks) * B::x + int(threadIdx.x);
+    const int y = (bid / a.bx_blocks) * B::y + int(threadIdx.y);
     if (x >= a.lay.nx || y >= a.lay.ny) return;
     node_update<L, S, COLL, THERMAL, A13P, PULL, POL == POL_STREAM, POL == POL_KEEP>(
         static_cast<const typename S::elem*>(a.fin), static_cast<typename S::elem*>(a.fout), a.lay, x, y, a.rx,
@@ -183,9 +206,10 @@ template <class L, class S, int COLL, bool THERMAL, bool A13P, bool SHIFTED, boo
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_AA_WAVES_PER_EU)))
 void k_stream_collide_aa(StepArgs a)
 {
+    using B = StepBlock<L, S, true>;
     const int bid = block_index(a);
-    const int x = (bid % a.bx_blocks) * BX + int(threadIdx.x);
-    const int y = (bid / a.bx_blocks) * BY + int(threadIdx.y);
+    const int x = (bid % a.bx_blocks) * B::x + int(threadIdx.x);
+    const int y = (bid / a.bx_blocks) * B::y + int(threadIdx.y);
     if (x >= a.lay.nx || y >= a.lay.ny) return;
     node_update_aa<L, S, COLL, THERMAL, A13P, SHIFTED, NT>(static_cast<typename S::elem*>(a.fout), a.lay, x, y,
                                                             a.rx, a.seq);
