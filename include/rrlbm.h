@@ -63,9 +63,10 @@
  *   two-buffer scheme bit for bit; a checkpoint holds f_a as it sits, so it
  *   loads only into an LBM_SCHEME_AA context.  It halves the state memory
  *   and the working set, which the 256 MiB memory-side cache then serves
- *   better: on D2V37 FP64 it is 31% faster at 768^2 and 6-8% at 1024^2,
- *   on D2V17 FP64 14% at 2048^2, on D3Q19 and D3Q27 13-15% at 128^3, and
- *   3-4% slower at D2V37 FP64 2048^2 (1.2 GB), 14% at D3Q103 128^3.
+ *   better: on D2V37 FP64 it is 32% faster at 768^2 and 6% at 1024^2, on
+ *   D2V17 FP64 14% at 2048^2, on D3Q19 and D3Q27 13-15% at 128^3; it is
+ *   level with the two-buffer step at D2V37 FP64 2048^2 (1.2 GB) and 14%
+ *   slower at D3Q103 128^3.
  *   Not with LBM_STORE_MOMENTS, batches or the closure.
  *
  * Environment (read when a context is created; none changes any result)
