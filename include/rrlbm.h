@@ -317,7 +317,7 @@ int lbm_moments_3d(lbm_ctx* ctx, double* rho, double* ux, double* uy, double* uz
 
 /* ---- Batched stepping ----------------------------------------------------
  * Many independent contexts (any lattice and grid size) advanced together:
- * one persistent launch per step walks a work list of 4-row tiles that spans
+ * one persistent launch per step walks a work list of tiles that spans
  * every member, and lbm_batch_step replays a HIP graph holding two such
  * launches (the two buffer parities).  Members keep working with
  * lbm_moments / lbm_populations / lbm_destroy; the batch never owns them. */
@@ -326,8 +326,9 @@ typedef struct lbm_batch lbm_batch;
 /* ctxs: host array of n (1..4096) contexts from lbm_init.  All members must
  * use the same storage flag, the recursive-regularized isothermal collision
  * (no LBM_COLL_PR, LBM_COLL_BGK or LBM_THERMAL) and the same stream (the
- * batch launches on it).  tile_x (64, 128 or 256) is the width of one work
- * item in nodes; blocks_per_cu (1..16) sets the persistent grid to that many
+ * batch launches on it).  tile_x (64, 128, 256, 512 or 1024) is the width of
+ * one work item in nodes (items of 64 and 128 are four rows high, wider ones
+ * one row); blocks_per_cu (1..16) sets the persistent grid to that many
  * blocks per compute unit.  Captures the graph; *out is set on success. */
 int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, int blocks_per_cu);
 

@@ -872,7 +872,8 @@ int batch_prepare(lbm_batch* b)
             d.rx = relax_of(c);
             d.seq = uint32_t(c->steps + 1);
             b->begin.push_back(int(total));
-            total += int64_t(d.bx_blocks) * ((c->ny + BY - 1) / BY);
+            const int rows = b->tile_x >= batch_wide_tile ? 1 : BY; // item height
+            total += int64_t(d.bx_blocks) * ((c->ny + rows - 1) / rows);
         }
         if (total >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "batch work list too long");
         b->begin.push_back(int(total));
@@ -932,7 +933,8 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, i
 {
     if (!out || !ctxs) return fail(LBM_EINVAL, "out or ctxs is NULL");
     if (n < 1 || n > 4096) return fail(LBM_EINVAL, "batch size must be in [1, 4096]");
-    if (tile_x != 64 && tile_x != 128 && tile_x != 256) return fail(LBM_EINVAL, "tile_x must be 64, 128 or 256");
+    if (tile_x != 64 && tile_x != 128 && tile_x != 256 && tile_x != 512 && tile_x != 1024)
+        return fail(LBM_EINVAL, "tile_x must be 64, 128, 256, 512 or 1024");
     if (blocks_per_cu < 1 || blocks_per_cu > 16) return fail(LBM_EINVAL, "blocks_per_cu must be in [1, 16]");
     for (int i = 0; i < n; ++i) {
         const lbm_ctx* c = ctxs[i];
@@ -1006,7 +1008,7 @@ int lbm_batch_autotune(lbm_batch* b, int steps_per_trial, char* report, int repo
     if (!b) return fail(LBM_EINVAL, "batch is NULL");
     if (steps_per_trial < 2) return fail(LBM_EINVAL, "steps_per_trial must be >= 2");
     const int steps = steps_per_trial & ~1;
-    static const int tiles[3] = { 64, 128, 256 };
+    static const int tiles[5] = { 64, 128, 256, 512, 1024 };
     static const int bpcs[4] = { 2, 4, 8, 16 };
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));

@@ -27,7 +27,18 @@ using BatchSto = StoreBF16;
 hipError_t RR_BATCH_NAME(RR_STORE)(int lattice, const InstDesc* desc, const int* begin, int n, int total, int parity,
                                    int tile_x, int grid, hipStream_t st)
 {
-    const dim3 g = dim3(unsigned(grid)), blk = dim3(BX, BY);
+    const dim3 g = dim3(unsigned(grid));
+    if (tile_x >= batch_wide_tile) {
+        const dim3 blk = dim3(BX * BY, 1);
+        switch (lattice) {
+        case LBM_D2Q9: k_batch<BatchSto, 0, true><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+        case LBM_D2V17: k_batch<BatchSto, 1, true><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+        case LBM_D2V37: k_batch<BatchSto, 2, true><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+        default: k_batch<BatchSto, -1, true><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
+        }
+        return hipGetLastError();
+    }
+    const dim3 blk = dim3(BX, BY);
     switch (lattice) {
     case LBM_D2Q9: k_batch<BatchSto, 0><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;
     case LBM_D2V17: k_batch<BatchSto, 1><<<g, blk, 0, st>>>(desc, begin, n, total, parity, tile_x); break;

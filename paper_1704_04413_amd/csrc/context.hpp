@@ -83,6 +83,10 @@ inline StepArgs step_args(const lbm_ctx* c, const void* fin, void* fout, bool pu
 // single buffer 1 after an even number of steps, 2 after an odd number.
 inline int state_placement(const lbm_ctx* c) { return !c->aa ? 0 : (c->steps & 1) ? 2 : 1; }
 
+// Batch work items at least this wide are one row high (walked by 256-wide
+// blocks); narrower ones are four rows high (64 x 4 blocks).
+constexpr int batch_wide_tile = 256;
+
 // One 2D (lattice, storage) pair: the kernels of step2d.hip compiled for it.
 struct Ops2D {
     // one step fin -> fout (pull), or the local collision of the initial state

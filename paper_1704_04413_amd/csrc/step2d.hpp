@@ -219,14 +219,17 @@ void k_stream_collide_aa(StepArgs a)
 
 // Persistent kernel: blocks stride over the work list (member, tile); item w
 // belongs to the member i with begin[i] <= w < begin[i+1].  Each item is a
-// tile_x by 4 patch of one member, walked 64 columns at a time.  `parity`
-// selects the buffer direction of this step for every member.
+// tile_x by 4 patch of one member walked 64 columns at a time by a 64 x 4
+// block, or (WIDE, tile_x >= 256) a tile_x by 1 strip walked 256 columns at a
+// time by four waves along the row, the shape of the single steps' blocks.
+// `parity` selects the buffer direction of this step for every member.
 // LAT: the one lattice of every member of this work list (its own register
 // budget), or -1 for a list that mixes lattices (one switch per work item).
-template <class S, int LAT>
+template <class S, int LAT, bool WIDE = false>
 __global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ desc, const int* __restrict__ begin,
                                                   int n, int total, int parity, int tile_x)
 {
+    constexpr int ROWS = WIDE ? 1 : BY, W = BX * BY / ROWS;
     using E = typename S::elem;
     for (int w = int(blockIdx.x); w < total; w += int(gridDim.x)) {
         int lo = 0, hi = n - 1;
@@ -241,11 +244,11 @@ __global__ __launch_bounds__(BX* BY) void k_batch(const InstDesc* __restrict__ d
         const InstDesc& d = desc[i];
         const int local = w - begin[i];
         const int x0 = (local % d.bx_blocks) * tile_x;
-        const int y = (local / d.bx_blocks) * BY + int(threadIdx.y);
+        const int y = (local / d.bx_blocks) * ROWS + int(threadIdx.y);
         const int src = d.flip ^ parity;
         const E* fin = static_cast<const E*>(d.buf[src]);
         E* fout = static_cast<E*>(d.buf[src ^ 1]);
-        for (int sub = 0; sub < tile_x; sub += BX) {
+        for (int sub = 0; sub < tile_x; sub += W) {
             const int x = x0 + sub + int(threadIdx.x);
             if (x < d.lay.nx && y < d.lay.ny) {
                 const uint32_t seq = d.seq + uint32_t(parity);

@@ -136,9 +136,8 @@ def test_aa_minimum_grids(b, name, nx, ny):
 @pytest.mark.parametrize("name,n,flags", [("D2V37", 768, 0), ("D2V37", 1024, 0), ("D2V37", 1024, 0x2),
                                           ("D2V17", 1024, 0)])
 def test_aa_full_size_bitwise(b, name, n, flags):
-    """The sizes where one buffer fits the memory-side cache (ordinary
-    stores) and where it does not (D2V37 FP64 1024^2: non-temporal stores),
-    compared whole on the GPU."""
+    """Sizes where one buffer fits the memory-side cache and where it does
+    not (D2V37 FP64 1024^2, 296 MiB), compared whole on the GPU."""
     import torch
 
     say(f"AA vs pull full size {name} {n}x{n} flags={flags:#x}")

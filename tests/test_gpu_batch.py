@@ -46,7 +46,7 @@ def check(got, want, atol):
 
 
 @pytest.mark.parametrize("split", SPLIT_MODES)
-@pytest.mark.parametrize("tile_x,bpc", [(64, 4), (128, 2), (256, 16)])
+@pytest.mark.parametrize("tile_x,bpc", [(64, 4), (128, 2), (256, 16), (512, 4), (1024, 2)])
 def test_batch_fp64_against_oracle(orc, b, tile_x, bpc, split, monkeypatch):
     monkeypatch.setenv("RRLBM_BATCH_SPLIT", split)
     print(f"[case] batch fp64 tile_x={tile_x} bpc={bpc} split={split}", flush=True)
@@ -122,13 +122,13 @@ def test_batch_autotune(orc, b):
     ref = [make(orc, b, name, nx, ny, seed, b.LBM_STORE_FP32)[0] for seed, (name, nx, ny) in enumerate(MEMBERS)]
     batch = b.lbm_batch_create([s.ctx for s in made], 64, 4)
     rows = b.lbm_batch_autotune(batch, 4)
-    assert len(rows) == 12 and all(ms > 0 for _, _, ms in rows)
+    assert len(rows) == 20 and all(ms > 0 for _, _, ms in rows)
     best = min(rows, key=lambda r: r[2])
     assert b.lbm_batch_config(batch) == (best[0], best[1])
     b.lbm_batch_step(batch, 3)
     b.lbm_batch_destroy(batch)
     n = made[0].steps
-    assert n == 12 * 6 + 3
+    assert n == 20 * 6 + 3
     for x, y in zip(made, ref):
         y.step(n)
         check(x.populations().cpu().numpy(), y.populations().cpu().numpy(), 1e-7)
