@@ -463,7 +463,8 @@ def summarize_trace_batch(args) -> str:
     """Writes profiles/batch64_fp32_kernel_trace.md from the rocpd database of
     a --kernel-trace --stats run of `bench.py --only-batch` and that run's JSON
     line.  The timed steps are the last `steps` dispatches of each persistent
-    batch kernel (the autotuner's trials come before them)."""
+    batch kernel of the chosen tile shape (the autotuner's trials come before
+    them)."""
     import sqlite3
 
     db, bench_json = args.summarize_trace_batch
@@ -474,7 +475,9 @@ def summarize_trace_batch(args) -> str:
     k = live["steps"]
     disp = con.execute("select name, duration, grid_x, workgroup_x, workgroup_y, vgpr_count, accum_vgpr_count, "
                        "sgpr_count, scratch_size from kernels where name like '%k_batch<%' order by start").fetchall()
-    names = sorted({d[0] for d in disp})
+    # the timed launches use the chosen tile's kernels: one-row (WIDE) ones for tiles of 256 and more
+    wide = live["tile_x"] >= 256
+    names = sorted({d[0] for d in disp if (", true>" in d[0]) == wide})
     cmd = f"rocprofv3 --kernel-trace --stats -d gpurun_out/profb -o run -- python3 bench.py --only-batch --steps {k}"
     out = [f"# rocprofv3 kernel trace: batch of {live['workload']}", "",
            "Command (repo root on an MI355X):", "", f"    {cmd}", "",
