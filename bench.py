@@ -452,6 +452,16 @@ def summarize_trace3d(args) -> str:
         out.append(f"| {r['lattice']} | {r['collision']} | {r['kernel_ms_avg'] * 1e3:.1f} | {r['kernel_GBs']:.0f} | "
                    f"{r['frac_hbm'] * 100:.1f} | {r['aa_kernel_ms_avg'] * 1e3:.1f} | {r['aa_kernel_GBs']:.0f} | "
                    f"{r['aa_frac_hbm'] * 100:.1f} |")
+    f32 = [r for r in cases if "fp32_kernel_ms_avg" in r]
+    if f32:
+        out += ["", "FP32 storage with FP64 arithmetic (algorithmic bytes 2 Q 4 per node), same run:", "",
+                "| lattice | collision | pull us per step | GB/s | % of peak | AA us per step | GB/s | % of peak |",
+                "|---|---|---|---|---|---|---|---|"]
+        for r in f32:
+            out.append(f"| {r['lattice']} | {r['collision']} | {r['fp32_kernel_ms_avg'] * 1e3:.1f} | "
+                       f"{r['fp32_kernel_GBs']:.0f} | {r['fp32_frac_hbm'] * 100:.1f} | "
+                       f"{r['fp32_aa_kernel_ms_avg'] * 1e3:.1f} | {r['fp32_aa_kernel_GBs']:.0f} | "
+                       f"{r['fp32_aa_frac_hbm'] * 100:.1f} |")
     out += ["", f"kernel_source_hash: {kernel_source_hash('step3d.hip')}"]
     path = os.path.join(ROOT, "profiles", f"lattices3d_{n}_kernel_trace.md")
     with open(path, "w") as f:
@@ -548,13 +558,18 @@ def suite_3d(torch, b, wl, n=128, steps=30, warmup=3, only=None):
         nodes = n ** 3
         row = {"lattice": lat, "collision": coll, "n": n,
                "order": b.lbm_lattice_info(lat)[2] if coll == "RR" else None}
-        # the pull step, then the single-buffer step on the same workload
-        for tag, fl in (("", flags), ("aa_", flags | b.LBM_SCHEME_AA)):
+        # the pull step, then the single-buffer step on the same workload, in
+        # FP64 and (RR) in FP32 storage with FP64 arithmetic
+        f32 = b.LBM_STORE_FP32 | b.LBM_MATH_FP64
+        runs = [("", flags, "fp64"), ("aa_", flags | b.LBM_SCHEME_AA, "fp64")]
+        if coll == "RR":
+            runs += [("fp32_", f32, "fp32d"), ("fp32_aa_", f32 | b.LBM_SCHEME_AA, "fp32d")]
+        for tag, fl, st in runs:
             sim, meta = make_sim3(b, wl, lat, n, flags=fl)
             wall, kms = time_steps(torch, sim, steps, warmup)
             bad = int(sim.moments()["sums"][7])
             sim.close()
-            gbs = bytes_per_node(meta["q"], "fp64") * nodes / (kms * 1e-3) / 1e9
+            gbs = bytes_per_node(meta["q"], st) * nodes / (kms * 1e-3) / 1e9
             row.update({f"{tag}MLUPS": round(nodes * steps / wall / 1e6, 1), f"{tag}kernel_ms_avg": round(kms, 4),
                         f"{tag}kernel_GBs": round(gbs, 1), f"{tag}frac_hbm": round(gbs / HBM_PEAK_GBS, 4),
                         f"{tag}nonfinite": bad})

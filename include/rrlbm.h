@@ -102,7 +102,7 @@ typedef struct lbm_ctx lbm_ctx;
 #define LBM_D2Q9 0  /* E^9_{2,5},  c_s^2 = 1/3, basis 1,x,y,xx,xy,yy,xxy,xyy,xxyy */
 #define LBM_D2V17 1 /* E^17_{2,7}, all Hermite tensors of rank <= 3           */
 #define LBM_D2V37 2 /* E^37_{2,9}, all Hermite tensors of rank <= 4           */
-/* 3D lattices (Table II); isothermal, FP64 populations, lbm_*_3d entry points. */
+/* 3D lattices (Table II); isothermal, FP64 (or FP32 with FP64 arithmetic) populations, lbm_*_3d entry points. */
 #define LBM_D3Q19 3 /* E^19_{3,5}, c_s^2 = 1/3, ranks <= 2 and the six xxy-type rank-3 tensors */
 #define LBM_D3Q27 4 /* E^27_{3,5}, c_s^2 = 1/3, the 27 products with each exponent <= 2 */
 #define LBM_D3V39 5 /* E^39_{3,7}, c_s^2 = 2/3, all Hermite tensors of rank <= 3 */
@@ -270,7 +270,10 @@ const char* lbm_last_error(void);
 /* ---- 3D lattices (Table II) ---------------------------------------------
  * Isothermal recursive regularization (the 3D forms of the recursion in
  * App. C, Eq. MalaspinasRecursiveRelation at theta = 1), projection-based
- * regularization or BGK on D3Q19, D3Q27, D3V39 and D3Q103, FP64 populations.  Grids
+ * regularization or BGK on D3Q19, D3Q27, D3V39 and D3Q103, FP64 populations, or
+ * (LBM_STORE_FP32 | LBM_MATH_FP64) the 2D form's weight-shifted floats
+ * g = f - w with every operation in double, rounded once per value at the
+ * store.  Grids
  * are periodic nx by ny by nz; fields are [z][y][x] (nx*ny*nz doubles) and
  * populations exchanged with the caller are [i][z][y][x].  The layout is the
  * 2D one over the ny*nz rows r = z*ny + y.  A 3D context works with
@@ -281,8 +284,9 @@ const char* lbm_last_error(void);
  * host arrays of q entries (any may be NULL).  LBM_EINVAL for a 2D id. */
 int lbm_lattice_velocities_3d(int lattice, int* cx, int* cy, int* cz, double* w);
 
-/* Doubles one state buffer holds: q * nx * (ny*nz rounded up to a multiple of
- * 4).  flags must carry no LBM_STORE_* bit.  Negative on error. */
+/* Elements (double, or float with LBM_STORE_FP32) one state buffer holds:
+ * q * nx * (ny*nz rounded up to a multiple of 4).  flags must carry no
+ * LBM_STORE_BF16 or LBM_STORE_MOMENTS bit.  Negative on error. */
 int64_t lbm_buffer_elems_3d(int lattice, int nx, int ny, int nz, uint32_t flags);
 
 /* Creates a 3D context and writes the initial state, the equilibrium of
@@ -293,9 +297,9 @@ int64_t lbm_buffer_elems_3d(int lattice, int nx, int ny, int nz, uint32_t flags)
  *   nx, ny, nz each >= the lattice reach; lbm_buffer_elems_3d() < 2^31.
  *   tau        discrete relaxation time (> 1/2), nu = c_s^2 (tau - 1/2).
  *   reg_order  2 <= N <= n_eq (3, 6, 3, 4); ignored with LBM_COLL_BGK.
- *   flags      LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2, LBM_SCHEME_AA
- *              only.
- *   f_a, f_b   two distinct device buffers of lbm_buffer_elems_3d() doubles,
+ *   flags      LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2, LBM_SCHEME_AA,
+ *              and LBM_STORE_FP32 together with LBM_MATH_FP64, only.
+ *   f_a, f_b   two distinct device buffers of lbm_buffer_elems_3d() elements,
  *              owned by the caller for the context's lifetime; with
  *              LBM_SCHEME_AA (the single-buffer scheme of the 2D contexts,
  *              with c_i and opp(i) in 3D) only f_a, and f_b must be NULL.

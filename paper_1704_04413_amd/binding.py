@@ -415,8 +415,9 @@ class Simulation:
 
 
 class Simulation3D(Simulation):
-    """A 3D context (Table II lattices, FP64 populations) and its buffers
-    (two, or one with LBM_SCHEME_AA); fields are [z][y][x] arrays."""
+    """A 3D context (Table II lattices, FP64 populations or FP32 with
+    LBM_STORE_FP32 | LBM_MATH_FP64) and its buffers (two, or one with
+    LBM_SCHEME_AA); fields are [z][y][x] arrays."""
 
     def __init__(self, lattice, nx, ny, nz, tau, rho, ux, uy, uz, noise=None, noise_amp=0.0, reg_order=None,
                  flags=0, device="cuda:0", stream=None):
@@ -430,7 +431,8 @@ class Simulation3D(Simulation):
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         n = lbm_buffer_elems_3d(self.lattice, nx, ny, nz, flags)
-        self.bufs = [torch.empty(n, dtype=torch.float64, device=self.device)
+        dtype = torch.float32 if flags & LBM_STORE_FP32 else torch.float64
+        self.bufs = [torch.empty(n, dtype=dtype, device=self.device)
                      for _ in range(1 if flags & LBM_SCHEME_AA else 2)]
 
         def dev(a):

@@ -34,8 +34,9 @@ FLAGS = [
 # parallel build ends soonest
 UNITS = (
     [(f"step2d_{lat}_{st}", "step2d.hip", {"RR_LAT": lat, "RR_STORE": st}) for lat in (2, 1, 0) for st in (0, 1, 2, 3)]
-    + [(f"step3d_{lat}{'_aa' if aa else ''}", "step3d.hip", {"RR_LAT3": lat, "RR_AA3": aa})
-       for lat in (6, 5, 4, 3) for aa in (0, 1)]
+    + [(f"step3d_{lat}{'_aa' if aa else ''}{'_f32' if st else ''}", "step3d.hip",
+        {"RR_LAT3": lat, "RR_AA3": aa, "RR_STORE3": st})
+       for lat in (6, 5, 4, 3) for aa in (0, 1) for st in (0, 3)]
     + [("closure", "closure.hip", {})]
     + [(f"batch_{st}", "batch.hip", {"RR_STORE": st}) for st in (0, 1, 2)]
     + [(f"mom_{lat}", "mom.hip", {"RR_LAT": lat}) for lat in (2, 1, 0)]

@@ -44,10 +44,14 @@ const Ops2D& ops2d_2_2();
 const Ops2D& ops2d_0_3();
 const Ops2D& ops2d_1_3();
 const Ops2D& ops2d_2_3();
-const Ops3D& ops3d_3();
-const Ops3D& ops3d_4();
-const Ops3D& ops3d_5();
-const Ops3D& ops3d_6();
+const Ops3D& ops3d_3_0();
+const Ops3D& ops3d_4_0();
+const Ops3D& ops3d_5_0();
+const Ops3D& ops3d_6_0();
+const Ops3D& ops3d_3_3();
+const Ops3D& ops3d_4_3();
+const Ops3D& ops3d_5_3();
+const Ops3D& ops3d_6_3();
 hipError_t mom_launch_0(const lbm_ctx*, int, const void*, void*, const InitArgs*, double*, double*, double*, double*,
                         double*, double*);
 hipError_t mom_launch_1(const lbm_ctx*, int, const void*, void*, const InitArgs*, double*, double*, double*, double*,
@@ -67,13 +71,14 @@ const Ops2D& ops2d(int lattice, int store)
     return table[lattice][store]();
 }
 
-const Ops3D& ops3d(int lattice)
+const Ops3D& ops3d(int lattice, int store)
 {
+    const bool f32 = store == ST_F32D;
     switch (lattice) {
-    case LBM_D3Q19: return ops3d_3();
-    case LBM_D3Q27: return ops3d_4();
-    case LBM_D3V39: return ops3d_5();
-    default: return ops3d_6();
+    case LBM_D3Q19: return f32 ? ops3d_3_3() : ops3d_3_0();
+    case LBM_D3Q27: return f32 ? ops3d_4_3() : ops3d_4_0();
+    case LBM_D3V39: return f32 ? ops3d_5_3() : ops3d_5_0();
+    default: return f32 ? ops3d_6_3() : ops3d_6_0();
     }
 }
 
@@ -250,7 +255,7 @@ hipError_t launch_step(const lbm_ctx* c, const void* fin, void* fout, bool pull)
 {
     if (c->dim == 3) {
         if (!pull) return hipErrorInvalidValue; // 3D contexts are only ever stepped with a pull
-        return ops3d(c->lattice).step(c, fin, fout);
+        return ops3d(c->lattice, c->store).step(c, fin, fout);
     }
     if (c->store == ST_MOM) return mom_launch_any(c, 3, fin, fout);
     return ops2d(c->lattice, c->store).step(c, fin, fout, pull);
@@ -455,7 +460,7 @@ int lbm_step(lbm_ctx* c, int nsteps)
     for (int s = 0; s < nsteps; ++s) {
         hipError_t he;
         if (c->aa && c->dim == 3) {
-            he = ops3d(c->lattice).step_aa(c, (c->steps & 1) == 0);
+            he = ops3d(c->lattice, c->store).step_aa(c, (c->steps & 1) == 0);
         } else if (c->aa) {
             he = ops2d(c->lattice, c->store).step_aa(c, (c->steps & 1) == 0, uint32_t(c->steps + 1));
         } else {
@@ -532,7 +537,7 @@ int lbm_populations(lbm_ctx* c, double* f_out)
 {
     if (!c || !f_out) return fail(LBM_EINVAL, "ctx or f_out is NULL");
     if (c->dim == 3)
-        HIP_TRY(ops3d(c->lattice).populations(c, c->buf[c->cur], f_out));
+        HIP_TRY(ops3d(c->lattice, c->store).populations(c, c->buf[c->cur], f_out));
     else if (c->store == ST_MOM)
         HIP_TRY(mom_launch_any(c, 1, nullptr, nullptr, nullptr, f_out));
     else
@@ -642,8 +647,8 @@ int64_t lbm_buffer_elems_3d(int lattice, int nx, int ny, int nz, uint32_t flags)
     LatInfo li;
     if (!is_3d(lattice) || !lattice_info(lattice, &li)) return fail(LBM_EINVAL, "not a 3D lattice");
     if (nx < 1 || ny < 1 || nz < 1) return fail(LBM_EINVAL, "empty grid");
-    if (flags & (LBM_STORE_FP32 | LBM_STORE_BF16 | LBM_STORE_MOMENTS))
-        return fail(LBM_EINVAL, "3D lattices store FP64 populations");
+    if (flags & (LBM_STORE_BF16 | LBM_STORE_MOMENTS))
+        return fail(LBM_EINVAL, "3D lattices store FP64 populations, or FP32 with LBM_MATH_FP64");
     if (int64_t(ny) * nz >= (int64_t(1) << 31)) return fail(LBM_EINVAL, "grid too large");
     return layout_elems(li.q, nx, ny * nz);
 }
@@ -660,9 +665,13 @@ int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, 
     if (int64_t(ny) * nz >= (int64_t(1) << 31) || layout_elems(li.q, nx, ny * nz) >= (int64_t(1) << 31))
         return fail(LBM_EINVAL, "grid too large");
     if (!std::isfinite(tau) || !(tau > 0.5)) return fail(LBM_ETAU, "tau must be finite and > 1/2");
-    const uint32_t known = LBM_COLL_PR | LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_SCHEME_AA;
+    const uint32_t known =
+        LBM_COLL_PR | LBM_COLL_BGK | LBM_EQ_INIT_ORDER2 | LBM_SCHEME_AA | LBM_STORE_FP32 | LBM_MATH_FP64;
     if (flags & ~known)
-        return fail(LBM_EINVAL, "3D lattices take LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2 and LBM_SCHEME_AA only");
+        return fail(LBM_EINVAL, "3D lattices take LBM_COLL_PR, LBM_COLL_BGK, LBM_EQ_INIT_ORDER2, LBM_SCHEME_AA and "
+                                "LBM_STORE_FP32 | LBM_MATH_FP64 only");
+    if (bool(flags & LBM_STORE_FP32) != bool(flags & LBM_MATH_FP64))
+        return fail(LBM_EINVAL, "3D FP32 storage computes in double: LBM_STORE_FP32 goes with LBM_MATH_FP64");
     if ((flags & LBM_COLL_PR) && (flags & LBM_COLL_BGK)) return fail(LBM_EINVAL, "two collision flags");
     if (!(flags & LBM_COLL_BGK) && (reg_order < 2 || reg_order > li.n_eq))
         return fail(LBM_EINVAL, "regularization order must be in [2, " + std::to_string(li.n_eq) + "]");
@@ -686,12 +695,12 @@ int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, 
     c->tau4 = tau;
     c->order = (flags & LBM_COLL_BGK) ? 2 : reg_order;
     c->flags = flags;
-    c->store = ST_F64;
+    c->store = (flags & LBM_STORE_FP32) ? ST_F32D : ST_F64;
     c->coll = (flags & LBM_COLL_PR) ? COLL_PR : (flags & LBM_COLL_BGK) ? COLL_BGK : COLL_RR;
     c->aa = (flags & LBM_SCHEME_AA) != 0;
     c->q = li.q;
     c->lay = make_layout(li.q, nx, ny * nz);
-    c->pol = choose_policy(int64_t(sizeof(double)) * layout_elems(li.q, nx, ny * nz), c->aa);
+    c->pol = choose_policy(store_bytes(c), c->aa);
     if (const char* e = std::getenv("RRLBM_XCD_REMAP")) c->xcd_remap = std::atoi(e) != 0;
     c->buf[0] = f_a;
     c->buf[1] = f_b;
@@ -702,11 +711,11 @@ int lbm_init_3d(lbm_ctx** out, int lattice, int nx, int ny, int nz, double tau, 
     hipError_t he;
     if (c->aa) {
         // f^(0) into f_a, collided in place into the placement of an even step count
-        he = ops3d(lattice).init(c, f_a, rho, ux, uy, uz, noise, noise_amp, eq_order);
-        if (he == hipSuccess) he = ops3d(lattice).step_aa(c, false);
+        he = ops3d(lattice, c->store).init(c, f_a, rho, ux, uy, uz, noise, noise_amp, eq_order);
+        if (he == hipSuccess) he = ops3d(lattice, c->store).step_aa(c, false);
     } else {
         // f^(0) goes to f_b shifted by -c_i; one pull launch then collides it into f_a
-        he = ops3d(lattice).init(c, f_b, rho, ux, uy, uz, noise, noise_amp, eq_order);
+        he = ops3d(lattice, c->store).init(c, f_b, rho, ux, uy, uz, noise, noise_amp, eq_order);
         if (he == hipSuccess) he = launch_step(c, f_b, f_a, true); // post-collision state in f_a, cur = 0
     }
     if (he != hipSuccess) {
@@ -731,7 +740,7 @@ int lbm_moments_3d(lbm_ctx* c, double* rho, double* ux, double* uy, double* uz, 
     double* vx = ux ? ux : c->fields + n;
     double* vy = uy ? uy : c->fields + 2 * n;
     double* vz = uz ? uz : c->fields + 3 * n;
-    HIP_TRY(ops3d(c->lattice).moments(c, r, vx, vy, vz, c->partial));
+    HIP_TRY(ops3d(c->lattice, c->store).moments(c, r, vx, vy, vz, c->partial));
     if (sums) {
         HIP_TRY(hipMemcpyAsync(c->partial_host, c->partial, sizeof(double) * MOM3_NS * c->nblk,
                                hipMemcpyDeviceToHost, c->stream));

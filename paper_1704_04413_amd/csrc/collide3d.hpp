@@ -19,6 +19,7 @@
 
 #include "common.hpp"
 #include "lattices3d.hpp"
+#include "storage.hpp"
 
 namespace rr {
 
@@ -280,11 +281,14 @@ __device__ __forceinline__ int block_index3(const Step3Args& a)
     return a.reverse ? a.nblocks - 1 - bid : bid;
 }
 
-template <class L, int MODE, int POL>
+// S: StoreF64, or StoreF32D (float g = f - w in memory, double arithmetic;
+// f = g + w on the load, g = f - w rounded once at the store).
+template <class L, int MODE, int POL, class S = StoreF64>
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU_3D)))
 void k_stream_collide3(Step3Args a)
 {
     static_assert(BX == 64, "one wave per row segment");
+    using E = typename S::elem;
     constexpr int R = L::R;
     const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
     const int bid = block_index3(a);
@@ -307,32 +311,36 @@ void k_stream_collide3(Step3Args a)
             yy -= (yy >= ny) ? ny : 0;
             zz -= (zz >= nz) ? nz : 0;
         }
-        xb[D] = uint32_t(xx) * uint32_t(sizeof(double));
+        xb[D] = uint32_t(xx) * uint32_t(sizeof(E));
         ys[D] = yy;
         zs[D] = zz;
     });
     const char* __restrict__ fin = static_cast<const char*>(a.fin);
     char* __restrict__ fout = static_cast<char*>(a.fout);
-    const int64_t plane = int64_t(a.lay.te) * int64_t(sizeof(double));
-    const int64_t here_row = int64_t(a.lay.row(row)) * int64_t(sizeof(double));
-    const uint32_t xh = uint32_t(x) * uint32_t(sizeof(double));
+    const int64_t plane = int64_t(a.lay.te) * int64_t(sizeof(E));
+    const int64_t here_row = int64_t(a.lay.row(row)) * int64_t(sizeof(E));
+    const uint32_t xh = uint32_t(x) * uint32_t(sizeof(E));
     double v[L::Q];
     static_for<L::Q>([&](auto I) {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
-        const int64_t src_row = int64_t(a.lay.row(zs[cz + R] * ny + ys[cy + R])) * int64_t(sizeof(double));
+        const int64_t src_row = int64_t(a.lay.row(zs[cz + R] * ny + ys[cy + R])) * int64_t(sizeof(E));
         const char* base = fin + src_row + int64_t(I) * plane;
-        const double* p = reinterpret_cast<const double*>(base + xb[cx + R]);
+        const E* p = reinterpret_cast<const E*>(base + xb[cx + R]);
+        double g;
         if constexpr (POL == POL_KEEP)
-            v[I] = __builtin_nontemporal_load(p);
+            g = S::load_nt(p);
         else
-            v[I] = *p;
+            g = S::load(p);
+        if constexpr (S::shifted) g += L::v.w[I];
+        v[I] = g;
     });
     collide3<L, MODE>(v, a.rx, a.order, [&](auto I, double val) {
-        double* p = reinterpret_cast<double*>(fout + here_row + int64_t(I) * plane + xh);
+        E* p = reinterpret_cast<E*>(fout + here_row + int64_t(I) * plane + xh);
+        if constexpr (S::shifted) val -= L::v.w[I];
         if constexpr (POL == POL_STREAM)
-            __builtin_nontemporal_store(val, p);
+            S::store_nt(p, val);
         else
-            *p = val;
+            S::store(p, val);
     });
 }
 
@@ -356,11 +364,12 @@ __device__ __forceinline__ void opaque_v(int& v) { asm volatile("" : "+v"(v)); }
 // writes plane i of the node x + c_i.  Each thread writes exactly the slots
 // it has read, after reading all of them.  Addressing as in the pull kernel
 // (wave-uniform row bases, per-lane byte offsets of x).
-template <class L, int MODE, bool SHIFTED, bool NT>
+template <class L, int MODE, bool SHIFTED, bool NT, class S = StoreF64>
 __global__ __launch_bounds__(BX* BY) __attribute__((amdgpu_waves_per_eu(RRLBM_WAVES_PER_EU_3D)))
 void k_stream_collide3_aa(Step3Args a)
 {
     static_assert(BX == 64, "one wave per row segment");
+    using E = typename S::elem;
     constexpr int R = L::R;
     const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
     const int bid = block_index3(a);
@@ -386,26 +395,29 @@ void k_stream_collide3_aa(Step3Args a)
                 yy -= (yy >= ny) ? ny : 0;
                 zz -= (zz >= nz) ? nz : 0;
             }
-            xb[D] = uint32_t(xx) * uint32_t(sizeof(double));
+            xb[D] = uint32_t(xx) * uint32_t(sizeof(E));
             ys[D] = yy;
             zs[D] = zz;
         });
     };
     char* f = static_cast<char*>(a.fout);
-    const int64_t plane = int64_t(a.lay.te) * int64_t(sizeof(double));
+    const int64_t plane = int64_t(a.lay.te) * int64_t(sizeof(E));
     auto slot = [&](int dz, int dy, uint32_t xoff, int i) {
-        const int64_t r = int64_t(a.lay.row(zs[dz + R] * ny + ys[dy + R])) * int64_t(sizeof(double));
-        return reinterpret_cast<double*>(f + r + int64_t(i) * plane + xoff);
+        const int64_t r = int64_t(a.lay.row(zs[dz + R] * ny + ys[dy + R])) * int64_t(sizeof(E));
+        return reinterpret_cast<E*>(f + r + int64_t(i) * plane + xoff);
     };
     neighbours(x, row);
     double v[L::Q];
     static_for<L::Q>([&](auto I) {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
         constexpr int o = opp_index3<L>(int(I)); // a compile-time constant, not a run-time search
+        double g;
         if constexpr (SHIFTED)
-            v[I] = *slot(-cz, -cy, xb[R - cx], o);
+            g = S::load(slot(-cz, -cy, xb[R - cx], o));
         else
-            v[I] = *slot(0, 0, xb[R], int(I));
+            g = S::load(slot(0, 0, xb[R], int(I)));
+        if constexpr (S::shifted) g += L::v.w[I];
+        v[I] = g;
     });
     // The stores go to the addresses the loads used; hiding the node makes
     // the compiler rebuild them rather than hold all Q across the collision.
@@ -415,11 +427,12 @@ void k_stream_collide3_aa(Step3Args a)
     collide3<L, MODE>(v, a.rx, a.order, [&](auto I, double val) {
         constexpr int cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
         constexpr int o = opp_index3<L>(int(I));
-        double* p = SHIFTED ? slot(cz, cy, xb[R + cx], int(I)) : slot(0, 0, xb[R], o);
+        E* p = SHIFTED ? slot(cz, cy, xb[R + cx], int(I)) : slot(0, 0, xb[R], o);
+        if constexpr (S::shifted) val -= L::v.w[I];
         if constexpr (NT)
-            __builtin_nontemporal_store(val, p);
+            S::store_nt(p, val);
         else
-            *p = val;
+            S::store(p, val);
     });
 }
 
@@ -437,7 +450,7 @@ struct Init3Args {
 // that one step kernel launch gathers f^(0) back at every node and collides
 // it (the kept state is post-collision); !SHIFT: value i in the node's own
 // plane i, for the in-place local kernel.
-template <class L, bool SHIFT = true>
+template <class L, bool SHIFT = true, class S = StoreF64>
 __global__ __launch_bounds__(256) void k_init3(Init3Args a)
 {
     const int nx = a.lay.nx, ny = a.ny, nz = a.nz;
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(256) void k_init3(Init3Args a)
     const int x = int(k % nx), row = int(k / nx), y = row % ny, z = row / ny;
     double f[L::Q];
     const Relax none{ 0.0, 0.0, 0.0, 0.0 };
-    double* out = static_cast<double*>(a.f);
+    typename S::elem* out = static_cast<typename S::elem*>(a.f);
     collide3<L, C3_EQ>(
         f, none, a.eq_order,
         [&](auto I, double val) {
@@ -457,7 +470,8 @@ __global__ __launch_bounds__(256) void k_init3(Init3Args a)
             xd += xd < 0 ? nx : (xd >= nx ? -nx : 0);
             yd += yd < 0 ? ny : (yd >= ny ? -ny : 0);
             zd += zd < 0 ? nz : (zd >= nz ? -nz : 0);
-            out[a.lay.row(zd * ny + yd) + xd + int(I) * a.lay.te] = val;
+            if constexpr (S::shifted) val -= L::v.w[I];
+            S::store(out + a.lay.row(zd * ny + yd) + xd + int(I) * a.lay.te, val);
         },
         a.rho[k], a.ux[k], a.uy[k], a.uz[k]);
 }
@@ -487,18 +501,23 @@ __device__ __forceinline__ int state_index3(const Layout& lay, int ny, int nz, i
 }
 
 // The state as populations [i][z][y][x].
-template <class L, int RD>
-__global__ __launch_bounds__(256) void k_populations3(const double* f, Layout lay, int ny, int nz, double* out)
+template <class L, int RD, class S = StoreF64>
+__global__ __launch_bounds__(256) void k_populations3(const typename S::elem* f, Layout lay, int ny, int nz,
+                                                      double* out)
 {
     const int64_t n = int64_t(lay.nx) * ny * nz;
     const int64_t k = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (k >= n) return;
     const int x = int(k % lay.nx), row = int(k / lay.nx), y = row % ny, z = row / ny;
-    static_for<L::Q>([&](auto I) { out[int64_t(I) * n + k] = f[state_index3<L, RD, int(I)>(lay, ny, nz, x, y, z)]; });
+    static_for<L::Q>([&](auto I) {
+        double v = S::load(f + state_index3<L, RD, int(I)>(lay, ny, nz, x, y, z));
+        if constexpr (S::shifted) v += L::v.w[I];
+        out[int64_t(I) * n + k] = v;
+    });
 }
 
-template <class L, int RD = 0>
-__global__ __launch_bounds__(256) void k_moments3(const double* f, Layout lay, int ny, int nz, double* rho_o,
+template <class L, int RD = 0, class S = StoreF64>
+__global__ __launch_bounds__(256) void k_moments3(const typename S::elem* f, Layout lay, int ny, int nz, double* rho_o,
                                                   double* ux_o, double* uy_o, double* uz_o, double* partial)
 {
     const int64_t n = int64_t(lay.nx) * ny * nz;
@@ -509,7 +528,8 @@ __global__ __launch_bounds__(256) void k_moments3(const double* f, Layout lay, i
         double r = 0, jx = 0, jy = 0, jz = 0, e2 = 0;
         static_for<L::Q>([&](auto I) {
             constexpr double cx = L::v.cx[I], cy = L::v.cy[I], cz = L::v.cz[I];
-            const double v = f[state_index3<L, RD, int(I)>(lay, ny, nz, x, y, z)];
+            double v = S::load(f + state_index3<L, RD, int(I)>(lay, ny, nz, x, y, z));
+            if constexpr (S::shifted) v += L::v.w[I];
             r += v;
             jx += cx * v;
             jy += cy * v;

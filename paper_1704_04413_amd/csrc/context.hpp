@@ -102,7 +102,8 @@ struct Ops2D {
 // lattice LBM_D2Q9..LBM_D2V37, store ST_F64..ST_F32D
 const Ops2D& ops2d(int lattice, int store);
 
-// One 3D lattice: the kernels of step3d.hip compiled for it.
+// One 3D (lattice, storage) pair: the kernels of step3d.hip compiled for it
+// (storage ST_F64 or ST_F32D).
 struct Ops3D {
     hipError_t (*step)(const lbm_ctx* c, const void* fin, void* fout);
     // one in-place step of the single-buffer scheme on buf[0] (shifted: the
@@ -115,7 +116,7 @@ struct Ops3D {
     hipError_t (*populations)(const lbm_ctx* c, const void* src, double* out);
     hipError_t (*moments)(const lbm_ctx* c, double* r, double* ux, double* uy, double* uz, double* partial);
 };
-const Ops3D& ops3d(int lattice);
+const Ops3D& ops3d(int lattice, int store);
 
 // Moment representation (mom.hip).  what: 0 initial state (ia), 1 populations
 // (out), 2 diagnostics (r, ux, uy, th; sums into partial), 3 step (fin -> fout).

@@ -1,9 +1,11 @@
-// The 3D step for one lattice of Table II, chosen at compile time: this file
-// is compiled twice per lattice (RR_LAT3 = LBM_D3Q19, LBM_D3Q27, LBM_D3V39 or
-// LBM_D3Q103), so that the two halves build in parallel.  With RR_AA3 = 0 it
-// provides the pull step for every collision and cache policy, the initial
-// state, the population dump and the diagnostics; with RR_AA3 = 1 the
-// in-place single-buffer step for every collision.
+// The 3D step for one lattice of Table II and one storage, chosen at compile
+// time: this file is compiled four times per lattice (RR_LAT3 = LBM_D3Q19,
+// LBM_D3Q27, LBM_D3V39 or LBM_D3Q103; RR_STORE3 = ST_F64 or ST_F32D, the
+// latter float g = f - w with double arithmetic), so that the parts build in
+// parallel.  With RR_AA3 = 0 it provides the pull step for every collision
+// and cache policy, the initial state, the population dump and the
+// diagnostics; with RR_AA3 = 1 the in-place single-buffer step for every
+// collision.
 #include "context.hpp"
 #include "storage.hpp"
 #include "collide3d.hpp"
@@ -14,16 +16,27 @@
 #if !defined(RR_AA3)
 #define RR_AA3 0
 #endif
+#if !defined(RR_STORE3)
+#define RR_STORE3 0
+#endif
 
-#define RR_STEP3_AA_NAME_(l) step3d_aa_##l
-#define RR_STEP3_AA_NAME(l) RR_STEP3_AA_NAME_(l)
+#define RR_STEP3_AA_NAME_(l, s) step3d_aa_##l##_##s
+#define RR_STEP3_AA_NAME(l, s) RR_STEP3_AA_NAME_(l, s)
 
 namespace rr {
 
 // one in-place step of the single-buffer scheme (the RR_AA3 = 1 unit)
-hipError_t RR_STEP3_AA_NAME(RR_LAT3)(const lbm_ctx* c, bool shifted);
+hipError_t RR_STEP3_AA_NAME(RR_LAT3, RR_STORE3)(const lbm_ctx* c, bool shifted);
 
 namespace {
+
+#if RR_STORE3 == 0
+using Sto3 = StoreF64;
+#elif RR_STORE3 == 3
+using Sto3 = StoreF32D;
+#else
+#error "RR_STORE3 must be ST_F64 or ST_F32D"
+#endif
 
 #if RR_LAT3 == 3
 using Lat = D3Q19;
@@ -51,15 +64,15 @@ hipError_t step_t(const lbm_ctx* c, const void* fin, void* fout)
     const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if constexpr (MODE != C3_PR) {
         if (pol == POL_CACHE) {
-            k_stream_collide3<Lat, MODE, POL_CACHE><<<grid, block, 0, c->stream>>>(a);
+            k_stream_collide3<Lat, MODE, POL_CACHE, Sto3><<<grid, block, 0, c->stream>>>(a);
             return hipGetLastError();
         }
         if (pol == POL_KEEP) {
-            k_stream_collide3<Lat, MODE, POL_KEEP><<<grid, block, 0, c->stream>>>(a);
+            k_stream_collide3<Lat, MODE, POL_KEEP, Sto3><<<grid, block, 0, c->stream>>>(a);
             return hipGetLastError();
         }
     }
-    k_stream_collide3<Lat, MODE, POL_STREAM><<<grid, block, 0, c->stream>>>(a);
+    k_stream_collide3<Lat, MODE, POL_STREAM, Sto3><<<grid, block, 0, c->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -78,9 +91,9 @@ hipError_t init(const lbm_ctx* c, void* dst, const double* rho, const double* ux
     const Init3Args ia{ dst, c->lay, c->ny, c->nz, rho, ux, uy, uz, noise, noise_amp, eq_order };
     // the single-buffer scheme collides the initial populations in place
     if (c->aa)
-        k_init3<Lat, false><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
+        k_init3<Lat, false, Sto3><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
     else
-        k_init3<Lat, true><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
+        k_init3<Lat, true, Sto3><<<dim3(unsigned(c->nblk)), dim3(256), 0, c->stream>>>(ia);
     return hipGetLastError();
 }
 
@@ -88,11 +101,11 @@ hipError_t populations(const lbm_ctx* c, const void* src, double* out)
 {
     const int64_t n = int64_t(c->nx) * c->ny * c->nz;
     const dim3 grid(unsigned((n + 255) / 256)), block(256);
-    const double* f = static_cast<const double*>(src);
+    const auto* f = static_cast<const typename Sto3::elem*>(src);
     switch (state_placement(c)) {
-    case 1: k_populations3<Lat, 1><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out); break;
-    case 2: k_populations3<Lat, 2><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out); break;
-    default: k_populations3<Lat, 0><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out);
+    case 1: k_populations3<Lat, 1, Sto3><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out); break;
+    case 2: k_populations3<Lat, 2, Sto3><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out); break;
+    default: k_populations3<Lat, 0, Sto3><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, out);
     }
     return hipGetLastError();
 }
@@ -100,11 +113,11 @@ hipError_t populations(const lbm_ctx* c, const void* src, double* out)
 hipError_t moments(const lbm_ctx* c, double* r, double* ux, double* uy, double* uz, double* partial)
 {
     const dim3 grid(unsigned(c->nblk)), block(256);
-    const double* f = static_cast<const double*>(c->buf[c->cur]);
+    const auto* f = static_cast<const typename Sto3::elem*>(c->buf[c->cur]);
     switch (state_placement(c)) {
-    case 1: k_moments3<Lat, 1><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial); break;
-    case 2: k_moments3<Lat, 2><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial); break;
-    default: k_moments3<Lat, 0><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial);
+    case 1: k_moments3<Lat, 1, Sto3><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial); break;
+    case 2: k_moments3<Lat, 2, Sto3><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial); break;
+    default: k_moments3<Lat, 0, Sto3><<<grid, block, 0, c->stream>>>(f, c->lay, c->ny, c->nz, r, ux, uy, uz, partial);
     }
     return hipGetLastError();
 }
@@ -123,9 +136,9 @@ hipError_t step_aa_t(const lbm_ctx* c, bool shifted)
                  (c->steps & 1) ? 1 : 0 };
     const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if (shifted)
-        k_stream_collide3_aa<Lat, MODE, true, false><<<grid, block, 0, c->stream>>>(a);
+        k_stream_collide3_aa<Lat, MODE, true, false, Sto3><<<grid, block, 0, c->stream>>>(a);
     else
-        k_stream_collide3_aa<Lat, MODE, false, false><<<grid, block, 0, c->stream>>>(a);
+        k_stream_collide3_aa<Lat, MODE, false, false, Sto3><<<grid, block, 0, c->stream>>>(a);
     return hipGetLastError();
 }
 
@@ -135,17 +148,17 @@ hipError_t step_aa_t(const lbm_ctx* c, bool shifted)
 
 #if RR_AA3 == 0
 
-#define RR_OPS3D_NAME_(l) ops3d_##l
-#define RR_OPS3D_NAME(l) RR_OPS3D_NAME_(l)
-const Ops3D& RR_OPS3D_NAME(RR_LAT3)()
+#define RR_OPS3D_NAME_(l, s) ops3d_##l##_##s
+#define RR_OPS3D_NAME(l, s) RR_OPS3D_NAME_(l, s)
+const Ops3D& RR_OPS3D_NAME(RR_LAT3, RR_STORE3)()
 {
-    static const Ops3D ops{ step, RR_STEP3_AA_NAME(RR_LAT3), init, populations, moments };
+    static const Ops3D ops{ step, RR_STEP3_AA_NAME(RR_LAT3, RR_STORE3), init, populations, moments };
     return ops;
 }
 
 #else
 
-hipError_t RR_STEP3_AA_NAME(RR_LAT3)(const lbm_ctx* c, bool shifted)
+hipError_t RR_STEP3_AA_NAME(RR_LAT3, RR_STORE3)(const lbm_ctx* c, bool shifted)
 {
     switch (c->coll) {
     case COLL_PR: return step_aa_t<C3_PR>(c, shifted);

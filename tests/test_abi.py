@@ -157,8 +157,12 @@ def test_3d_buffer_elems():
             n = b.lbm_buffer_elems_3d(name, nx, ny, nz)
             assert n >= q * nx * ny * nz
             assert n == q * nx * (-(-(ny * nz) // 4) * 4)
-        with pytest.raises(b.LbmError):
-            b.lbm_buffer_elems_3d(name, 4, 4, 4, b.LBM_STORE_FP32)
+        # FP32 storage (with double arithmetic) holds the same number of elements
+        assert b.lbm_buffer_elems_3d(name, 4, 4, 4, b.LBM_STORE_FP32 | b.LBM_MATH_FP64) == \
+            b.lbm_buffer_elems_3d(name, 4, 4, 4)
+        for fl in (b.LBM_STORE_BF16, b.LBM_STORE_MOMENTS):
+            with pytest.raises(b.LbmError):
+                b.lbm_buffer_elems_3d(name, 4, 4, 4, fl)
         with pytest.raises(b.LbmError):
             b.lbm_buffer_elems(name, 4, 4)
     with pytest.raises(b.LbmError):
@@ -176,7 +180,9 @@ def test_3d_buffer_elems():
     (dict(tau=0.5), b.LBM_ETAU),
     (dict(reg_order=4), b.LBM_EINVAL),                # D3V39 stops at rank 3
     (dict(reg_order=1), b.LBM_EINVAL),
-    (dict(flags=b.LBM_STORE_FP32), b.LBM_EINVAL),
+    (dict(flags=b.LBM_STORE_FP32), b.LBM_EINVAL),                    # FP32 storage computes in double
+    (dict(flags=b.LBM_MATH_FP64), b.LBM_EINVAL),
+    (dict(flags=b.LBM_STORE_BF16 | b.LBM_MATH_FP64), b.LBM_EINVAL),
     (dict(flags=b.LBM_THERMAL), b.LBM_EINVAL),
     (dict(flags=b.LBM_COLL_PR | b.LBM_COLL_BGK), b.LBM_EINVAL),
     (dict(same_buffers=True), b.LBM_EINVAL),
