@@ -470,9 +470,9 @@ def summarize_trace3d(args) -> str:
 
 
 def summarize_trace_batch(args) -> str:
-    """Writes profiles/batch64_fp32_kernel_trace.md from the rocpd database of
-    a --kernel-trace --stats run of `bench.py --only-batch` and that run's JSON
-    line.  The timed steps are the last `steps` dispatches of each persistent
+    """Writes profiles/batch64_<storage>_kernel_trace.md from the rocpd
+    database of a --kernel-trace --stats run of `bench.py --only-batch` and
+    that run's JSON line.  The timed steps are the last `steps` dispatches of each persistent
     batch kernel of the chosen tile shape (the autotuner's trials come before
     them)."""
     import sqlite3
@@ -488,7 +488,9 @@ def summarize_trace_batch(args) -> str:
     # the timed launches use the chosen tile's kernels: one-row (WIDE) ones for tiles of 256 and more
     wide = live["tile_x"] >= 256
     names = sorted({d[0] for d in disp if (", true>" in d[0]) == wide})
-    cmd = f"rocprofv3 --kernel-trace --stats -d gpurun_out/profb -o run -- python3 bench.py --only-batch --steps {k}"
+    st = live["storage"]
+    cmd = (f"rocprofv3 --kernel-trace --stats -d gpurun_out/profb{'' if st == 'fp32' else '_' + st} -o run -- "
+           f"python3 bench.py --only-batch{'' if st == 'fp32' else ' --batch-storage ' + st} --steps {k}")
     out = [f"# rocprofv3 kernel trace: batch of {live['workload']}", "",
            "Command (repo root on an MI355X):", "", f"    {cmd}", "",
            "Summary: `python3 bench.py --summarize-trace-batch <run_results.db> <bench output>`", "",
@@ -514,7 +516,7 @@ def summarize_trace_batch(args) -> str:
             f"Live HIP-event timing of the replayed graph in the same run: {live['batched_ms_per_step'] * 1e3:.2f} us "
             f"per step ({live['batched_MLUPS']} MLUPS, {live['batched_frac_hbm'] * 100:.1f}% of peak).",
             f"kernel_source_hash: {kernel_source_hash('batch.hip')}"]
-    path = os.path.join(ROOT, "profiles", "batch64_fp32_kernel_trace.md")
+    path = os.path.join(ROOT, "profiles", f"batch64_{st}_kernel_trace.md")
     with open(path, "w") as f:
         f.write("\n".join(out) + "\n")
     return path
@@ -728,8 +730,8 @@ def batched_suite(torch, b, wl, storage="fp32", steps=40):
     mix = {l: sum(1 for x in inst if x[0] == l) for l in ("D2Q9", "D2V17", "D2V37")}
     return {
         "workload": f"{len(inst)} shear-layer instances, sides 128..1024, lattices {mix}, Re 1e4..1e6, "
-                    f"{storage} shifted storage",
-        "nodes": nodes, "bytes_per_step": nbytes, "steps": steps,
+                    f"{storage} shifted storage" + (" (FP64 arithmetic)" if storage == "fp32d" else ""),
+        "storage": storage, "nodes": nodes, "bytes_per_step": nbytes, "steps": steps,
         "batched_MLUPS": round(nodes * steps / t_bat / 1e6, 1),
         "batched_ms_per_step": round(t_bat / steps * 1e3, 5),
         "batched_GBs": round(nbytes * steps / t_bat / 1e9, 1),
@@ -804,6 +806,8 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=25)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--batch-storage", default="fp32", choices=["fp64", "fp32", "fp32d", "bf16"],
+                    help="member storage of --only-batch")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D lattice lines (128^3)")
     ap.add_argument("--only-3d", metavar="LATTICE:COLL",
                     help="time one 3D case (e.g. D3Q19:RR, or 'all') for --steps and print its line alone")
@@ -821,7 +825,7 @@ def main():
     ap.add_argument("--summarize-closure-pmc", nargs=2, metavar="DIR",
                     help="closure-step counters against the plain step: closure csv dir, plain csv dir")
     ap.add_argument("--only-batch", action="store_true",
-                    help="time the 64-instance batch (FP32, autotuned) alone and print its line")
+                    help="time the 64-instance batch (autotuned; storage from --batch-storage) alone and print its line")
     ap.add_argument("--summarize-trace-batch", nargs=2, metavar=("DB", "BENCH_OUT"),
                     help="write the batch kernel-trace summary from a rocprofv3 database and that run's output")
     ap.add_argument("--only-headline", action="store_true",
@@ -893,7 +897,8 @@ def main():
         return
 
     if args.only_batch:
-        print(json.dumps({"batched": batched_suite(torch, b, wl, steps=args.steps)}), flush=True)
+        print(json.dumps({"batched": batched_suite(torch, b, wl, storage=args.batch_storage, steps=args.steps)}),
+              flush=True)
         return
 
     if args.only_aa:
@@ -1046,6 +1051,7 @@ def main():
         out["lattices_3d"] = suite_3d(torch, b, wl, n=args.n3)
     if not args.no_batch:
         out["batched"] = batched_suite(torch, b, wl)
+        out["batched_fp32d"] = batched_suite(torch, b, wl, storage="fp32d")
     if not args.no_studies:
         from paper_1704_04413_amd import studies
 

@@ -47,7 +47,7 @@
  *   The sequence of states equals that of LBM_STORE_FP64 up to rounding.
  *   LBM_STORE_FP32 | LBM_MATH_FP64 keeps the float storage of g_i and does
  *   the collision in double, so each value is rounded to float once per step
- *   (at the store); batches and the closure do not take it.
+ *   (at the store); batches take it, the closure does not.
  *
  * Scheme (population storage only)
  *   By default a step gathers from one buffer into the other (f_a, f_b

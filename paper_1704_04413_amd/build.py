@@ -38,7 +38,7 @@ UNITS = (
         {"RR_LAT3": lat, "RR_AA3": aa, "RR_STORE3": st})
        for lat in (6, 5, 4, 3) for aa in (0, 1) for st in (0, 3)]
     + [("closure", "closure.hip", {})]
-    + [(f"batch_{st}", "batch.hip", {"RR_STORE": st}) for st in (0, 1, 2)]
+    + [(f"batch_{st}", "batch.hip", {"RR_STORE": st}) for st in (0, 1, 2, 3)]
     + [(f"mom_{lat}", "mom.hip", {"RR_LAT": lat}) for lat in (2, 1, 0)]
     + [("api", "api.hip", {})]
 )

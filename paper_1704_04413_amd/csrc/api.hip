@@ -61,6 +61,7 @@ hipError_t mom_launch_2(const lbm_ctx*, int, const void*, void*, const InitArgs*
 hipError_t batch_launch_0(int, const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
 hipError_t batch_launch_1(int, const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
 hipError_t batch_launch_2(int, const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
+hipError_t batch_launch_3(int, const InstDesc*, const int*, int, int, int, int, int, hipStream_t);
 
 const Ops2D& ops2d(int lattice, int store)
 {
@@ -98,6 +99,7 @@ hipError_t batch_launch(int store, int lattice, const InstDesc* desc, const int*
     switch (store) {
     case ST_F32: return batch_launch_1(lattice, desc, begin, n, total, parity, tile_x, grid, st);
     case ST_BF16: return batch_launch_2(lattice, desc, begin, n, total, parity, tile_x, grid, st);
+    case ST_F32D: return batch_launch_3(lattice, desc, begin, n, total, parity, tile_x, grid, st);
     default: return batch_launch_0(lattice, desc, begin, n, total, parity, tile_x, grid, st);
     }
 }
@@ -951,8 +953,7 @@ int lbm_batch_create(lbm_batch** out, lbm_ctx* const* ctxs, int n, int tile_x, i
         if (c->dim == 3) return fail(LBM_EINVAL, "batch members must be 2D");
         if (c->coll != COLL_RR || c->thermal)
             return fail(LBM_EINVAL, "batch members must use the isothermal recursive regularization");
-        if (c->store == ST_MOM || c->store == ST_F32D)
-            return fail(LBM_EINVAL, "batch members must store FP64, FP32 or BF16 populations with arithmetic of the same width");
+        if (c->store == ST_MOM) return fail(LBM_EINVAL, "batch members must store populations");
         if (c->aa) return fail(LBM_EINVAL, "batch members must use the two-buffer scheme");
         if (c->store != ctxs[0]->store) return fail(LBM_EINVAL, "batch members must share the storage type");
         if (c->stream != ctxs[0]->stream) return fail(LBM_EINVAL, "batch members must share the stream");

@@ -1,5 +1,5 @@
 // The persistent batch kernels for one storage kind, chosen at compile time
-// (RR_STORE = ST_F64, ST_F32 or ST_BF16): one per 2D lattice, each walking
+// (RR_STORE = ST_F64, ST_F32, ST_BF16 or ST_F32D): one per 2D lattice, each walking
 // the work list of that lattice's members, and one that walks a list mixing
 // every lattice.
 #include "context.hpp"
@@ -17,6 +17,8 @@ using BatchSto = StoreF64;
 using BatchSto = StoreF32;
 #elif RR_STORE == 2
 using BatchSto = StoreBF16;
+#elif RR_STORE == 3
+using BatchSto = StoreF32D;
 #else
 #error "RR_STORE must be a population storage"
 #endif
