@@ -672,25 +672,10 @@ def copy_bandwidth(torch, nbytes=1 << 30, reps=20):
     return 2.0 * nbytes * reps / (s.elapsed_time(e) * 1e-3) / 1e9
 
 
-def batch_instances(seed=0, count=64):
-    """64 shear-layer instances: side uniform in {128,...,1024}, lattices
-    D2Q9/D2V17/D2V37 with probabilities 0.5/0.3/0.2, Re log-uniform in
-    [1e4, 1e6] (NumPy PCG64 with `seed`)."""
-    rng = np.random.Generator(np.random.PCG64(seed))
-    sides = np.array([128, 192, 256, 384, 512, 768, 1024])
-    out = []
-    for _ in range(count):
-        n = int(rng.choice(sides))
-        lat = str(rng.choice(["D2Q9", "D2V17", "D2V37"], p=[0.5, 0.3, 0.2]))
-        re = float(10 ** rng.uniform(4, 6))
-        out.append((lat, n, re))
-    return out
-
-
 def batched_suite(torch, b, wl, storage="fp32", steps=40):
     """All instances advanced by one autotuned, graph-replayed persistent
     launch per step, against one launch per instance per step."""
-    inst = batch_instances()
+    inst = wl.batch_instances()
     sims, nodes, nbytes = [], 0, 0
     for lat, n, re in inst:
         q, _, _, cs2 = b.lbm_lattice_info(lat)

@@ -94,3 +94,19 @@ def uniform_noise_3d(seed: int, q: int, nz: int, ny: int, nx: int) -> np.ndarray
     """U(-1, 1) samples of shape (q, nz, ny, nx) from NumPy's PCG64 with `seed`."""
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(-1.0, 1.0, size=(q, nz, ny, nx))
+
+
+def batch_instances(seed: int = 0, count: int = 64):
+    """The mixed batch workload: `count` shear-layer instances (lattice name,
+    side, Re) with side uniform in {128, ..., 1024}, lattices D2Q9/D2V17/D2V37
+    with probabilities 0.5/0.3/0.2 and Re log-uniform in [1e4, 1e6] (NumPy
+    PCG64 with `seed`)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    sides = np.array([128, 192, 256, 384, 512, 768, 1024])
+    out = []
+    for _ in range(count):
+        n = int(rng.choice(sides))
+        lat = str(rng.choice(["D2Q9", "D2V17", "D2V37"], p=[0.5, 0.3, 0.2]))
+        re = float(10 ** rng.uniform(4, 6))
+        out.append((lat, n, re))
+    return out

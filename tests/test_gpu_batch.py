@@ -207,3 +207,51 @@ def test_batch_follows_per_order_relaxation(orc, b, split, monkeypatch):
         same = float(np.mean(gx == gy))
         print(f"[parity] identical values {same:.5f}", flush=True)
         assert same >= 0.99
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp32d"])
+def test_batch_full_workload(b, storage):
+    """The timed batch workload at full size (64 shear layers, sides 128 to
+    1024, 20.2 M nodes) in the launch shape its autotuner picks (256-wide
+    one-row items, 16 blocks per CU), five steps, against the same members
+    stepped one launch at a time (each of those is checked against the oracle
+    at small sizes): every stored value within one float rounding, compared
+    on the GPU."""
+    import torch
+
+    inst = wl.batch_instances()
+    assert len(inst) == 64
+    flags = flags_of(b, storage)
+    print(f"[case] batch full workload {storage} tile 256 bpc 16", flush=True)
+
+    def members():
+        out = []
+        for lat, n, re in inst:
+            q, _, _, cs2 = b.lbm_lattice_info(lat)
+            u0, tau = wl.shear_layer_params(cs2, n, re)
+            rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+            out.append(b.Simulation(lat, n, n, tau, rho, ux, uy, flags=flags))
+        return out
+
+    batched = members()
+    batch = b.lbm_batch_create([s.ctx for s in batched], 256, 16)
+    b.lbm_batch_step(batch, 5)
+    b.lbm_batch_destroy(batch)
+    worst, nodes = 0.0, 0
+    for x, (lat, n, re) in zip(batched, inst):
+        gx = x.populations()
+        x.close()
+        q, _, _, cs2 = b.lbm_lattice_info(lat)
+        u0, tau = wl.shear_layer_params(cs2, n, re)
+        rho, ux, uy = wl.shear_layer_fields(n, n, u0)
+        y = b.Simulation(lat, n, n, tau, rho, ux, uy, flags=flags)
+        y.step(5)
+        gy = y.populations()
+        y.close()
+        assert bool(torch.isfinite(gx).all())
+        worst = max(worst, float((gx - gy).abs().max()))
+        nodes += n * n
+        del gx, gy
+    print(f"[parity] {nodes} nodes, max |batched - single| = {worst:.3e} (bound 1e-7)", flush=True)
+    assert nodes == 20205568
+    assert worst <= 1e-7
