@@ -64,9 +64,9 @@
  *   loads only into an LBM_SCHEME_AA context.  It halves the state memory
  *   and the working set, which the 256 MiB memory-side cache then serves
  *   better: on D2V37 FP64 it is 32% faster at 768^2 and 6% at 1024^2, on
- *   D2V17 FP64 14% at 2048^2, on D3Q19 and D3Q27 13-15% at 128^3; it is
- *   level with the two-buffer step at D2V37 FP64 2048^2 (1.2 GB) and 14%
- *   slower at D3Q103 128^3.
+ *   D2V17 FP64 14% at 2048^2, on D3Q19 and D3Q27 13-15% and on D3V39 9% at
+ *   128^3; it is level with the two-buffer step at D2V37 FP64 2048^2
+ *   (1.2 GB) and 9% slower at D3Q103 128^3.
  *   Not with LBM_STORE_MOMENTS, batches or the closure.
  *
  * Environment (read when a context is created; none changes any result)
@@ -75,11 +75,11 @@
  *     order reversed every other step, 2 non-temporal loads and ordinary
  *     stores.  By default the policy follows the size of one state buffer
  *     (1 up to 128 MiB, 2 from 256 to 320 MiB, 0 otherwise; 3D: RR and BGK).
- *     With LBM_SCHEME_AA on 2D contexts: 1 (the default at every size)
- *     ordinary stores, 0 non-temporal stores in order, 2 non-temporal stores
- *     in the steps that write a node's own slots and ordinary ones in the
- *     others; with 1 and 2 the tile order is reversed every other step.  3D
- *     contexts with LBM_SCHEME_AA always take 1.
+ *     With LBM_SCHEME_AA: 1 ordinary stores, 0 non-temporal stores, 2
+ *     non-temporal stores in the steps that write a node's own slots and
+ *     ordinary ones in the others; the tile order is reversed every other
+ *     step with 1 and 2 in 2D and with every policy in 3D.  The default is 1
+ *     at every size in 2D, and in 3D 1 up to 512 MiB per buffer and 0 above.
  *   RRLBM_XCD_REMAP=0  keeps the hardware's round-robin order of blocks over
  *     the 8 XCDs instead of giving each XCD a contiguous band of tiles.
  *   RRLBM_BATCH_SPLIT=1/2  (read by lbm_batch_create) gives each lattice of a

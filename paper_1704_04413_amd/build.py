@@ -1,7 +1,8 @@
 """Builds librrlbm.so (the HIP C-ABI library) in-tree for gfx950 with hipcc.
 
 The kernels are split over translation units that compile in parallel: the
-2D step once per (lattice, storage) pair, the 3D step once per lattice, the
+2D step once per (lattice, storage) pair, the 3D step six times per lattice
+(pull, in-place, and in-place with non-temporal stores, for two storages), the
 moment representation once per lattice, the batch kernel once per storage,
 the closure, and the host-side C-ABI.  Objects go to _build/ next to this
 file and are linked into one shared library.
@@ -34,9 +35,9 @@ FLAGS = [
 # parallel build ends soonest
 UNITS = (
     [(f"step2d_{lat}_{st}", "step2d.hip", {"RR_LAT": lat, "RR_STORE": st}) for lat in (2, 1, 0) for st in (0, 1, 2, 3)]
-    + [(f"step3d_{lat}{'_aa' if aa else ''}{'_f32' if st else ''}", "step3d.hip",
+    + [(f"step3d_{lat}{('', '_aa', '_aant')[aa]}{'_f32' if st else ''}", "step3d.hip",
         {"RR_LAT3": lat, "RR_AA3": aa, "RR_STORE3": st})
-       for lat in (6, 5, 4, 3) for aa in (0, 1) for st in (0, 3)]
+       for lat in (6, 5, 4, 3) for aa in (0, 1, 2) for st in (0, 3)]
     + [("closure", "closure.hip", {})]
     + [(f"batch_{st}", "batch.hip", {"RR_STORE": st}) for st in (0, 1, 2, 3)]
     + [(f"mom_{lat}", "mom.hip", {"RR_LAT": lat}) for lat in (2, 1, 0)]

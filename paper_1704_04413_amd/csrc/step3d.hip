@@ -5,7 +5,8 @@
 // parallel.  With RR_AA3 = 0 it provides the pull step for every collision
 // and cache policy, the initial state, the population dump and the
 // diagnostics; with RR_AA3 = 1 the in-place single-buffer step for every
-// collision.
+// collision, and with RR_AA3 = 2 the same kernels with non-temporal stores
+// (the single-buffer step calls them for the policies that ask for them).
 #include "context.hpp"
 #include "storage.hpp"
 #include "collide3d.hpp"
@@ -22,11 +23,16 @@
 
 #define RR_STEP3_AA_NAME_(l, s) step3d_aa_##l##_##s
 #define RR_STEP3_AA_NAME(l, s) RR_STEP3_AA_NAME_(l, s)
+#define RR_STEP3_AANT_NAME_(l, s) step3d_aant_##l##_##s
+#define RR_STEP3_AANT_NAME(l, s) RR_STEP3_AANT_NAME_(l, s)
 
 namespace rr {
 
 // one in-place step of the single-buffer scheme (the RR_AA3 = 1 unit)
 hipError_t RR_STEP3_AA_NAME(RR_LAT3, RR_STORE3)(const lbm_ctx* c, bool shifted);
+// its kernels with non-temporal stores (the RR_AA3 = 2 unit); reverse: walk
+// the tiles in reverse order
+hipError_t RR_STEP3_AANT_NAME(RR_LAT3, RR_STORE3)(const lbm_ctx* c, bool shifted, bool reverse);
 
 namespace {
 
@@ -122,24 +128,32 @@ hipError_t moments(const lbm_ctx* c, double* r, double* ux, double* uy, double* 
     return hipGetLastError();
 }
 
-#else // RR_AA3 == 1
+#else // RR_AA3 == 1 or 2
+
+constexpr bool kNT = RR_AA3 == 2;
 
 template <int MODE>
-hipError_t step_aa_t(const lbm_ctx* c, bool shifted)
+hipError_t step_aa_t(const lbm_ctx* c, bool shifted, bool reverse)
 {
     const int rows = c->ny * c->nz;
     const int bxn = (c->nx + BX - 1) / BX, byn = (rows + BY - 1) / BY;
-    // ordinary stores with the tile order reversed every other step (the 2D
-    // scheme's default policy; the others are not built for 3D, each kernel
-    // of the largest lattice costing half a minute of build)
     Step3Args a{ c->buf[0], c->buf[0], c->lay, c->ny, c->nz, bxn, bxn * byn, c->xcd_remap, relax_of(c), c->order,
-                 (c->steps & 1) ? 1 : 0 };
+                 reverse ? 1 : 0 };
     const dim3 grid(unsigned(bxn * byn)), block(BX, BY);
     if (shifted)
-        k_stream_collide3_aa<Lat, MODE, true, false, Sto3><<<grid, block, 0, c->stream>>>(a);
+        k_stream_collide3_aa<Lat, MODE, true, kNT, Sto3><<<grid, block, 0, c->stream>>>(a);
     else
-        k_stream_collide3_aa<Lat, MODE, false, false, Sto3><<<grid, block, 0, c->stream>>>(a);
+        k_stream_collide3_aa<Lat, MODE, false, kNT, Sto3><<<grid, block, 0, c->stream>>>(a);
     return hipGetLastError();
+}
+
+hipError_t step_aa_any(const lbm_ctx* c, bool shifted, bool reverse)
+{
+    switch (c->coll) {
+    case COLL_PR: return step_aa_t<C3_PR>(c, shifted, reverse);
+    case COLL_BGK: return step_aa_t<C3_BGK>(c, shifted, reverse);
+    default: return step_aa_t<C3_RR>(c, shifted, reverse);
+    }
 }
 
 #endif
@@ -156,15 +170,26 @@ const Ops3D& RR_OPS3D_NAME(RR_LAT3, RR_STORE3)()
     return ops;
 }
 
-#else
+#elif RR_AA3 == 1
 
+// The store kinds of the policies as in 2D: POL_CACHE ordinary stores,
+// POL_STREAM non-temporal ones, POL_KEEP non-temporal stores in the step that
+// writes a node's own slots only.  The tile order is reversed every other
+// step under every policy: with non-temporal stores too, the next step's
+// first reads then meet the lines written last (D3V39 FP64 128^3: 70.3% of
+// peak with the reversal, 58.7% without).
 hipError_t RR_STEP3_AA_NAME(RR_LAT3, RR_STORE3)(const lbm_ctx* c, bool shifted)
 {
-    switch (c->coll) {
-    case COLL_PR: return step_aa_t<C3_PR>(c, shifted);
-    case COLL_BGK: return step_aa_t<C3_BGK>(c, shifted);
-    default: return step_aa_t<C3_RR>(c, shifted);
-    }
+    const bool nt = c->pol == POL_STREAM || (c->pol == POL_KEEP && !shifted);
+    const bool reverse = (c->steps & 1) != 0;
+    return nt ? RR_STEP3_AANT_NAME(RR_LAT3, RR_STORE3)(c, shifted, reverse) : step_aa_any(c, shifted, reverse);
+}
+
+#else
+
+hipError_t RR_STEP3_AANT_NAME(RR_LAT3, RR_STORE3)(const lbm_ctx* c, bool shifted, bool reverse)
+{
+    return step_aa_any(c, shifted, reverse);
 }
 
 #endif

@@ -266,14 +266,60 @@ def test_aa_3d_equals_pull_bitwise(b, name, coll):
                        run_3d(b, name, dims, 0.6, fields, flags, s, relax=relax))
 
 
+F32D = 0x2 | 0x400
+
+
+@pytest.mark.parametrize("name", NAMES_3D)
+@pytest.mark.parametrize("storage", ["fp64", "fp32d"])
 @pytest.mark.parametrize("policy", ["0", "1", "2"])
-def test_aa_3d_policies(b, policy, monkeypatch):
+def test_aa_3d_policies(b, name, storage, policy, monkeypatch):
+    """Ordinary stores (1), non-temporal ones (0), non-temporal ones in the
+    steps that write a node's own slots only (2): the same states as the
+    pull step, bit for bit."""
     dims = (66, 6, 5)
-    say(f"AA 3D D3Q27 policy {policy}")
-    fields = fields_3d(b, "D3Q27", dims, seed=4)
-    want = run_3d(b, "D3Q27", dims, 0.6, fields, 0, 7)
+    say(f"AA 3D {name} {storage} policy {policy}")
+    fields = fields_3d(b, name, dims, seed=4)
+    flags = F32D if storage == "fp32d" else 0
+    want = run_3d(b, name, dims, 0.6, fields, flags, 7)
     monkeypatch.setenv("RRLBM_CACHE_POLICY", policy)
-    assert_same_3d(run_3d(b, "D3Q27", dims, 0.6, fields, AA, 7), want)
+    assert_same_3d(run_3d(b, name, dims, 0.6, fields, flags | AA, 7), want)
+
+
+@pytest.mark.parametrize("coll", ["PR", "BGK"])
+def test_aa_3d_nontemporal_other_collisions(b, coll, monkeypatch):
+    dims = (66, 6, 5)
+    say(f"AA 3D D3Q19 {coll} policy 0")
+    fields = fields_3d(b, "D3Q19", dims, seed=8)
+    flags = COLLS_3D[coll][1]
+    want = run_3d(b, "D3Q19", dims, 0.6, fields, flags, 5)
+    monkeypatch.setenv("RRLBM_CACHE_POLICY", "0")
+    assert_same_3d(run_3d(b, "D3Q19", dims, 0.6, fields, flags | AA, 5), want)
+
+
+@pytest.mark.parametrize("name,storage", [("D3V39", "fp64"), ("D3Q103", "fp64"), ("D3Q103", "fp32d"),
+                                          ("D3V39", "fp32d")])
+def test_aa_3d_full_size_bitwise(b, name, storage):
+    """128^3, the size the 3D lines of the benchmark time, with the default
+    policy: non-temporal stores for the buffers above 512 MiB (D3V39 FP64,
+    624 MiB; D3Q103 1648 and 824 MiB), ordinary ones below (D3V39 FP32,
+    312 MiB).  Three in-place steps against three pull steps, every value and
+    the FP64 sums compared on the GPU."""
+    import torch
+
+    n = 128
+    flags = F32D if storage == "fp32d" else 0
+    say(f"AA vs pull 3D full size {name} {storage} {n}^3")
+    q, _, _, cs2 = b.lbm_lattice_info(name)
+    rho, ux, uy, uz = wl.shear_layer_fields_3d(n, n, n, 0.1 * math.sqrt(cs2))
+    out = []
+    for fl in (flags | AA, flags):
+        sim = b.Simulation3D(name, n, n, n, 0.51, rho, ux, uy, uz, flags=fl)
+        sim.step(3)
+        out.append((sim.populations(), np.asarray(sim.moments()["sums"])))
+        sim.close()
+    assert torch.equal(out[0][0], out[1][0])
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    assert out[0][1][7] == 0  # no non-finite node
 
 
 @pytest.mark.parametrize("name,dims", [("D3Q19", (1, 1, 1)), ("D3Q27", (2, 1, 3)), ("D3V39", (3, 3, 3)),
