@@ -33,7 +33,7 @@ struct Step3Args {
     int xcd_remap; // 1: XCD k takes the k-th contiguous eighth of the tiles
     Relax rx;
     int order;
-    int reverse;   // 1: walk the tiles last to first (POL_CACHE, every other step)
+    int reverse;   // 1: walk the tiles last to first (POL_CACHE, and the single-buffer step, every other step)
 };
 
 // Register budget of the 3D step kernel, as the minimum number of waves per
