@@ -288,6 +288,48 @@ def _pmc_sums(csv_dir: str, kernel_hint: str, scheme: str = "pull"):
     return kname, {c: float(np.mean(v)) for (k, c), v in per.items() if k == kname}
 
 
+def summarize_pmc3d(args) -> str:
+    """HBM traffic of the 3D step kernels of one lattice at 128^3 under the
+    default policy and under RRLBM_CACHE_POLICY=1 (ordinary stores for the
+    single-buffer step), from FETCH_SIZE / WRITE_SIZE runs of `bench.py
+    --only-3d <lattice>:RR` scaled by the same counters of a 1 GiB device copy
+    (profiles/<lattice>_128_traffic.txt)."""
+    lat = args.lattice3d
+    fd, wd, fd1, wd1, fc, wc = args.summarize_pmc3d
+    q = {"D3Q19": 19, "D3Q27": 27, "D3V39": 39, "D3Q103": 103}[lat]
+    n = 128
+    _, cf = _busiest(_pmc_per_kernel(fc, "FETCH_SIZE"))
+    _, cw = _busiest(_pmc_per_kernel(wc, "WRITE_SIZE"))
+    copy_kib = float(1 << 20)  # 1 GiB read and written by the calibration copy
+    fs, ws = copy_kib / cf, copy_kib / cw
+    run = f"python3 bench.py --only-3d {lat}:RR --steps 30 --warmup 3 --n3 {n}"
+    out = [f"# HBM traffic of the {lat} 3D step kernels at {n}^3 (rocprofv3 PMC), default policy and policy 1",
+           "#", "# Commands (repo root on an MI355X; one counter per run):"]
+    for tag, pre in (("", ""), ("1", "RRLBM_CACHE_POLICY=1 ")):
+        for c, d in (("FETCH_SIZE", "f"), ("WRITE_SIZE", "w")):
+            out.append(f"#   {pre}rocprofv3 --pmc {c} --output-format csv -d gpurun_out/prof/{d}3_{lat}{tag} -o run -- {run}")
+    out += ["# Calibration with a device copy of 1 GiB (torch copy_):",
+            "#   rocprofv3 --pmc FETCH_SIZE --output-format csv -d gpurun_out/prof/fcopy -o run -- python3 bench.py --copy-only",
+            "#   rocprofv3 --pmc WRITE_SIZE --output-format csv -d gpurun_out/prof/wcopy -o run -- python3 bench.py --copy-only",
+            f"# Summary: python3 bench.py --lattice3d {lat} --summarize-pmc3d <the six csv dirs in that order>",
+            f"# scale factors: fetch {fs:.4f}, write {ws:.4f}",
+            "# algorithmic bytes per launch: 2 Q E n^3 (E = 8 for FP64, 4 for FP32 storage)", "#",
+            "policy  kernel  dispatches  read_MB  written_MB  measured/algorithmic"]
+    for tag, (fdir, wdir) in (("default", (fd, wd)), ("1", (fd1, wd1))):
+        f, w = _pmc_per_kernel(fdir, "FETCH_SIZE"), _pmc_per_kernel(wdir, "WRITE_SIZE")
+        for k in sorted(k for k in f if "k_stream_collide3" in k and k in w):
+            e = 4 if "StoreF32D" in k else 8
+            alg = 2 * q * e * n ** 3
+            rd, wr = float(np.mean(f[k])) * 1024 * fs, float(np.mean(w[k])) * 1024 * ws
+            short = k.split("(")[0].replace("void rr::", "").replace("rr::", "")
+            out.append(f"{tag}  {short}  {len(f[k])}  {rd / 1e6:.1f}  {wr / 1e6:.1f}  {(rd + wr) / alg:.4f}")
+    out.append(f"kernel_source_hash: {kernel_source_hash('step3d.hip')}")
+    path = os.path.join(ROOT, "profiles", f"{lat.lower()}_128_traffic.txt")
+    with open(path, "w") as fh:
+        fh.write("\n".join(out) + "\n")
+    return path
+
+
 def summarize_requests(args) -> str:
     """Cross-check of the FETCH_SIZE / WRITE_SIZE calibration with request
     counters: bytes = 128 R128 + 64 R64 + 32 R32 for reads and 64 W64 +
@@ -797,6 +839,10 @@ def main():
     ap.add_argument("--only-3d", metavar="LATTICE:COLL",
                     help="time one 3D case (e.g. D3Q19:RR, or 'all') for --steps and print its line alone")
     ap.add_argument("--n3", type=int, default=128, help="edge of the 3D box")
+    ap.add_argument("--summarize-pmc3d", nargs=6, metavar="DIR",
+                    help="3D traffic summary: FETCH and WRITE csv dirs (default policy), the same with "
+                         "RRLBM_CACHE_POLICY=1, then the copy's FETCH and WRITE dirs")
+    ap.add_argument("--lattice3d", default="D3V39", help="lattice of --summarize-pmc3d")
     ap.add_argument("--summarize-trace3d", nargs=2, metavar=("DB", "BENCH_OUT"),
                     help="write the 3D kernel-trace summary under profiles/ and exit")
     ap.add_argument("--no-studies", action="store_true", help="skip the precision, Sod and stability studies")
@@ -849,6 +895,9 @@ def main():
         return
     if args.summarize_trace3d:
         print(summarize_trace3d(args))
+        return
+    if args.summarize_pmc3d:
+        print(summarize_pmc3d(args))
         return
     if args.summarize_trace_batch:
         print(summarize_trace_batch(args))
