@@ -66,7 +66,8 @@
  *   better: on D2V37 FP64 it is 32% faster at 768^2 and 6% at 1024^2, on
  *   D2V17 FP64 14% at 2048^2, on D3Q19 and D3Q27 13-15% and on D3V39 9% at
  *   128^3; it is level with the two-buffer step at D2V37 FP64 2048^2
- *   (1.2 GB) and 9% slower at D3Q103 128^3.
+ *   (1.2 GB), 9% slower at D3Q103 128^3 and 7-20% slower on D3Q19, D3Q27
+ *   and D3V39 at 256^3.
  *   Not with LBM_STORE_MOMENTS, batches or the closure.
  *
  * Environment (read when a context is created; none changes any result)
@@ -79,7 +80,8 @@
  *     non-temporal stores in the steps that write a node's own slots and
  *     ordinary ones in the others; the tile order is reversed every other
  *     step with 1 and 2 in 2D and with every policy in 3D.  The default is 1
- *     at every size in 2D, and in 3D 1 up to 512 MiB per buffer and 0 above.
+ *     at every size in 2D, and in 3D 0 for buffers above 512 MiB up to 2 GiB
+ *     and 1 otherwise.
  *   RRLBM_XCD_REMAP=0  keeps the hardware's round-robin order of blocks over
  *     the 8 XCDs instead of giving each XCD a contiguous band of tiles.
  *   RRLBM_BATCH_SPLIT=1/2  (read by lbm_batch_create) gives each lattice of a

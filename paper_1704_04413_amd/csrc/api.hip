@@ -239,20 +239,23 @@ bool lattice_info(int lattice, LatInfo* out)
 // ordinary stores beat non-temporal ones on every lattice and storage
 // measured from 166 MiB to 1.2 GB (D2V37 FP64 2048^2: 68.2% against 57.4%;
 // D2V17 FP64 2048^2: 78.2 against 58.5%) but one (D2V37 FP64 1024^2: 80.7
-// against 81.8%).  The in-place 3D step takes POL_CACHE up to 512 MiB and
-// POL_STREAM above: at 128^3 non-temporal stores won on D3V39 FP64 (624 MiB:
-// 70.3% against 68.0%) and D3Q103 (FP64, 1648 MiB: 61.4 against 58.5%; FP32,
-// 824 MiB: 57.7-59.4 against 57.5%) and lost on D3Q27 FP64 (432 MiB: 75.6
-// against 76.6%) and D3V39 FP32 (312 MiB: 70.1 against 78.5%).
-// RRLBM_CACHE_POLICY=0/1/2 forces one.
+// against 81.8%).  The in-place 3D step takes POL_STREAM for buffers above
+// 512 MiB up to 2 GiB and POL_CACHE otherwise, the band where its
+// non-temporal stores measured faster: at 128^3 they won on D3V39 FP64
+// (624 MiB: 70.3% against 68.0%) and D3Q103 (FP64, 1648 MiB: 61.4 against
+// 58.5%; FP32, 824 MiB: 57.7-59.4 against 57.5%) and lost on D3Q27 FP64
+// (432 MiB: 75.6 against 76.6%) and D3V39 FP32 (312 MiB: 70.1 against
+// 78.5%); at 256^3 they lost on every buffer measured (D3Q19 FP64, 2.4 GiB:
+// 64.3 against 64.8%; D3Q27, 3.4 GiB: 60.7 against 63.1%; D3V39, 4.9 GiB:
+// 58.5 against 59.3%).  RRLBM_CACHE_POLICY=0/1/2 forces one.
 int choose_policy(int64_t buffer_bytes, bool aa = false, bool three_d = false)
 {
     if (const char* e = std::getenv("RRLBM_CACHE_POLICY")) {
         const int p = std::atoi(e);
         if (p >= POL_STREAM && p <= POL_KEEP) return p;
     }
-    if (aa) return three_d && buffer_bytes > (int64_t(512) << 20) ? POL_STREAM : POL_CACHE;
     const int64_t MiB = int64_t(1) << 20;
+    if (aa) return (three_d && buffer_bytes > 512 * MiB && buffer_bytes <= 2048 * MiB) ? POL_STREAM : POL_CACHE;
     if (buffer_bytes <= 128 * MiB) return POL_CACHE;
     if (buffer_bytes > 256 * MiB && buffer_bytes <= 320 * MiB) return POL_KEEP;
     return POL_STREAM;
